@@ -1,0 +1,123 @@
+"""Pins of the oracle's even-odd reduction and Krylov solvers.
+
+The reference solution comes from a direct sparse LU of the brute-force
+matrix (tests/bruteforce.py), which shares no code with the oracle.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from gen import fields
+from oracle import dirac, evenodd, solvers
+from oracle.dense import dense
+from tests import bruteforce
+
+
+def full_matrix(u, dims, kappa, csw):
+    wc = evenodd.WilsonClover(u, kappa, csw)
+    h = bruteforce.hopping_matrix(u, dims)
+    a = bruteforce.clover_block_matrix(wc.a.reshape(-1, 12, 12))
+    return wc, (a - kappa * h).tocsc()
+
+
+def test_schur_equals_dense_complement():
+    dims = (2, 2, 2, 4)
+    u = fields.gauge_field(dims, "haar", 101)
+    wc, m = full_matrix(u, dims, 0.13, 1.0)
+    par = np.repeat(bruteforce.parity_of_sites(dims), 12)
+    e, o = par == 0, par == 1
+    md = m.toarray()
+    schur_ref = md[np.ix_(e, e)] - md[np.ix_(e, o)] @ np.linalg.solve(
+        md[np.ix_(o, o)], md[np.ix_(o, e)])
+    v = int(np.prod(dims))
+    schur = dense(wc.schur, (v // 2, 4, 3))
+    assert np.max(np.abs(schur - schur_ref)) < 1e-14
+    schur_dag = dense(lambda x: wc.schur(x, dagger=True), (v // 2, 4, 3))
+    assert np.max(np.abs(schur_dag - schur_ref.conj().T)) < 1e-14
+
+
+def test_split_join_order():
+    dims = (4, 2, 2, 2)
+    psi = fields.gaussian_spinor(dims, 5)
+    e, o = evenodd.split(psi, dims)
+    flat = psi.reshape(-1, 4, 3)
+    par = bruteforce.parity_of_sites(dims)
+    assert np.array_equal(e, flat[par == 0])
+    assert np.array_equal(o, flat[par == 1])
+    assert np.array_equal(evenodd.join(e, o, dims), psi)
+
+
+@pytest.mark.parametrize("dims,kind,kappa,csw", [
+    ((2, 2, 2, 2), "haar", 0.12, 0.0),
+    ((4, 4, 4, 4), "haar", 0.12, 0.0),
+    ((4, 4, 4, 4), "smooth", 0.135, 1.0),
+])
+@pytest.mark.parametrize("method", ["cgnr", "bicgstab"])
+def test_evenodd_solve_matches_direct(dims, kind, kappa, csw, method):
+    u = fields.gauge_field(dims, kind, 111)
+    b = fields.gaussian_spinor(dims, 112)
+    wc, m = full_matrix(u, dims, kappa, csw)
+    x_ref = spla.spsolve(m, b.reshape(-1))
+    x, info = solvers.solve_evenodd(wc, b, tol=1e-10, method=method)
+    assert info.converged and info.true_residual <= 1e-10
+    # residual from the brute-force matrix, not the oracle's own operator
+    res = np.linalg.norm(b.reshape(-1) - m @ x.reshape(-1)) / np.linalg.norm(b)
+    assert res <= 1e-10
+    cond_est = 50.0
+    assert np.linalg.norm(x.reshape(-1) - x_ref) <= cond_est * 1e-10 * np.linalg.norm(x_ref)
+
+
+def test_full_cgnr_and_fgmres_match_direct():
+    dims = (4, 4, 4, 4)
+    u = fields.gauge_field(dims, "haar", 121)
+    b = fields.gaussian_spinor(dims, 122)
+    wc, m = full_matrix(u, dims, 0.12, 0.0)
+    x_ref = spla.spsolve(m, b.reshape(-1))
+    x1, i1 = solvers.cgnr(wc.M, wc.Mdag, b, tol=1e-10)
+    x2, i2 = solvers.fgmres(wc.M, b, m=32, tol=1e-10)
+    for x, info in ((x1, i1), (x2, i2)):
+        assert info.converged
+        assert np.linalg.norm(x.reshape(-1) - x_ref) <= 50 * 1e-10 * np.linalg.norm(x_ref)
+
+
+def test_fgmres_with_varying_preconditioner_on_schur():
+    """A preconditioner that changes every call (a few CG steps on the normal
+    equations with a varying count) still converges under FGMRES."""
+    dims = (4, 4, 4, 4)
+    u = fields.gauge_field(dims, "smooth", 131)
+    b = fields.gaussian_spinor(dims, 132)
+    wc = evenodd.WilsonClover(u, 0.135, 1.0)
+    bhat = wc.prepare_source(b)
+    calls = [0]
+
+    def prec(v):
+        calls[0] += 1
+        y, _ = solvers.cgnr(wc.schur, lambda z: wc.schur(z, dagger=True), v,
+                            tol=1e-30, maxiter=2 + calls[0] % 3)
+        return y
+
+    x, info = solvers.fgmres(wc.schur, bhat, precond=prec, m=16, tol=1e-10)
+    assert info.converged
+    assert dirac.norm(bhat - wc.schur(x)) <= 1e-10 * dirac.norm(bhat)
+
+
+def test_fcg_on_normal_operator():
+    dims = (4, 4, 2, 4)
+    u = fields.gauge_field(dims, "smooth", 141)
+    wc = evenodd.WilsonClover(u, 0.13, 1.0)
+    b = wc.prepare_source(fields.gaussian_spinor(dims, 142))
+    nop = lambda v: wc.schur(wc.schur(v), dagger=True)  # noqa: E731
+    rhs = wc.schur(b, dagger=True)
+    x, info = solvers.fcg(nop, rhs, tol=1e-10)
+    assert info.converged
+    assert dirac.norm(b - wc.schur(x)) <= 1e-8 * dirac.norm(b)
+
+
+def test_reconstruct_solves_full_system():
+    dims = (4, 4, 4, 4)
+    u = fields.gauge_field(dims, "smooth", 151)
+    b = fields.gaussian_spinor(dims, 152)
+    wc = evenodd.WilsonClover(u, 0.135, 1.0)
+    x, info = solvers.solve_evenodd(wc, b, tol=1e-10)
+    assert info.converged
+    assert dirac.norm(b - wc.M(x)) <= 1e-10 * dirac.norm(b)
