@@ -1,0 +1,173 @@
+/*
+ * lq.h -- C ABI of the MI355X (gfx950) Wilson-clover even-odd operator and
+ * Krylov solvers.
+ *
+ * The problem is the one the paper states (section 3, eq. "linear"): solve
+ * M phi = b, or the normal equations M^dagger M phi = b, for the Wilson or
+ * clover fermion matrix M, a huge sparse complex non-Hermitian matrix, with
+ * an iterative method whose cost is dominated by the matrix-vector product
+ * (sections 3 and 5).  Section 5 adds the even-odd (Schur complement)
+ * reduction, CG on the normal operator, and mixed precision through
+ * iterative refinement.  The operator itself is not printed in the paper;
+ * the conventions used are:
+ *
+ *   M = A - kappa H,
+ *   (H psi)(x) = sum_mu [(1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                        + (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu)],
+ *   A(x) = 1 - csw kappa sum_{mu<nu} sigma_{mu nu} F_{mu nu}(x),
+ *   sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu],
+ *   F_{mu nu} = (Q_{mu nu} - Q_{mu nu}^dagger)/(8i) minus its trace/3,
+ *     Q_{mu nu} the four mu->nu ordered plaquette leaves at x;
+ *   Hermitian chiral-basis gammas: gamma_k = [[0, -i s_k], [i s_k, 0]]
+ *     (k = 1,2,3 <-> mu = 0,1,2), gamma_4 = [[0, 1], [1, 0]] (mu = 3),
+ *     gamma_5 = diag(1, 1, -1, -1);
+ *   links periodic; fermion hops periodic in x, y, z and, when
+ *     t_antiperiodic != 0, antiperiodic in t;
+ *   parity (x0+x1+x2+x3) mod 2, even = 0;
+ *   Schur operator  Mhat = A_ee - kappa^2 H_eo A_oo^{-1} H_oe  on even sites,
+ *   bhat_e = b_e + kappa H_eo A_oo^{-1} b_o,
+ *   x_o = A_oo^{-1} (b_o + kappa H_oe x_e).
+ *
+ * Host layouts (complex128 = two doubles, real then imaginary):
+ *   site index i = ((x3*Lz + x2)*Ly + x1)*Lx + x0 (x fastest, t = x3);
+ *   gauge  U[i][mu][a][b], U_mu(x) the link from x to x+mu;
+ *   spinor psi[i][spin][colour];
+ *   a half-lattice array lists the V/2 sites of one parity in increasing i;
+ *   with nrhs > 1 the right-hand side index is slowest: psi[r][site][s][a].
+ *
+ * Device fields are opaque byte buffers of lq_field_bytes() bytes, owned
+ * by the caller (any device allocation, 256-byte aligned).  Their inner
+ * layout is private to the library (site-blocked, 64 sites per block,
+ * component-major inside a block; FP16 fields carry one FP32 scale per site).
+ *
+ * Every call returns an lq_status; no C++ exception crosses this boundary.
+ * On failure a message is kept in the context (lq_last_error).  All device
+ * work is issued on the stream given to lq_create; calls that return host
+ * data synchronise that stream.  A context must not be used from two
+ * threads at once; separate contexts are independent.
+ */
+#ifndef LQ_H
+#define LQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lq_ctx lq_ctx;
+
+typedef enum {
+  LQ_OK = 0,
+  LQ_EINVAL = -1,   /* bad argument (sizes, parity, precision, null pointer, not SU(3)) */
+  LQ_ENOMEM = -2,   /* device or host allocation failed */
+  LQ_EHIP = -3,     /* a HIP runtime call failed */
+  LQ_ENOCONV = -4,  /* solver did not reach the tolerance; report filled */
+  LQ_ESTATE = -5,   /* call out of order (no gauge field, no clover term) */
+  LQ_ENAN = -6      /* NaN or Inf met in a reduction; report filled */
+} lq_status;
+
+typedef enum { LQ_F64 = 0, LQ_F32 = 1, LQ_F16 = 2 } lq_prec;
+typedef enum { LQ_EVEN = 0, LQ_ODD = 1, LQ_FULL = 2 } lq_parity;
+typedef enum {
+  LQ_CGNR = 0,         /* CG on Mhat^dagger Mhat (plain FP64 when inner_prec = F64) */
+  LQ_BICGSTAB = 1,     /* BiCGStab on Mhat */
+  LQ_FGMRES_NET = 2,   /* FGMRES(m) on Mhat, learned preconditioner on the right */
+  LQ_FCG_NET = 3       /* flexible CG on Mhat^dagger Mhat with N_e N_e^dagger */
+} lq_solver;
+
+/* Solver parameters.  Zero-initialise and set what you need; zeros select
+ * the defaults given per field. */
+typedef struct {
+  int solver;            /* lq_solver, default LQ_CGNR */
+  int inner_prec;        /* lq_prec of the inner iteration: F64 = plain solve,
+                            F32/F16 = mixed precision with FP64 reliable updates */
+  int maxiter;           /* total inner iterations, default 20000 */
+  double delta;          /* reliable-update trigger ||r|| < delta * max ||r||, default 0.1 */
+  int restart;           /* FGMRES restart length m, default 32 */
+  int check_every;       /* iterations per captured graph replay, default 8 */
+  int use_graph;         /* 1 (default when 0 is given: 1) replay captured iterations;
+                            -1 launch each kernel directly */
+  int fault_inject;      /* tests only: 1 = force the inner solve to stagnate */
+} lq_solver_params;
+
+typedef struct {
+  int iterations;          /* inner iterations (all restarts, all RHS max) */
+  int reliable_updates;    /* FP64 true-residual recomputations */
+  int fallback;            /* 1 if the plain FP64 solver had to finish the solve */
+  int dslash_calls;        /* hopping-term sweeps issued (per RHS) */
+  double true_residual;    /* ||b - M x|| / ||b|| of the full system, FP64 */
+  double schur_residual;   /* ||bhat - Mhat x_e|| / ||bhat||, FP64 */
+  double seconds;          /* wall time of the solve inside the library */
+} lq_solve_report;
+
+/* Context: owns device copies of the gauge field (12-real compressed, FP64,
+ * FP32 and FP16), the clover term and solver work space.  dims = {Lx, Ly,
+ * Lz, Lt}, each even and >= 2.  stream: a hipStream_t (NULL = default). */
+lq_status lq_create(const int dims[4], int t_antiperiodic, void* hip_stream, lq_ctx** out);
+void lq_destroy(lq_ctx* ctx);
+/* Last error message of ctx (or of the last failed lq_create when ctx is NULL);
+ * valid until the next call on ctx. */
+const char* lq_last_error(const lq_ctx* ctx);
+/* Bytes of a device field: parity EVEN/ODD = V/2 sites, FULL = both halves. */
+size_t lq_field_bytes(const lq_ctx* ctx, int parity, int prec, int nrhs);
+/* Local volume V and padded half volume (sites per parity rounded up to 64). */
+int64_t lq_volume(const lq_ctx* ctx);
+
+/* Gauge field upload and 12-real compression (rows 0 and 1 kept, row 2 =
+ * conj(row0 x row1) rebuilt in the kernels).  host_U: V*4*9 complex128,
+ * caller-owned, read during the call.  Fails with LQ_EINVAL unless every
+ * link is unitary with det 1 to 1e-12. */
+lq_status lq_upload_gauge(lq_ctx* ctx, const double* host_U);
+
+/* Build the clover term for (kappa, csw) on the GPU in FP64 from the FP64
+ * links: A on both parities, A^{-1} on both parities, and FP32/FP16 copies
+ * of A_ee and A_oo^{-1}.  csw = 0 gives A = 1 (plain Wilson). */
+lq_status lq_set_clover(lq_ctx* ctx, double kappa, double csw);
+
+/* Host canonical spinor(s) -> device field of precision prec (FP16: per-site
+ * scale = max |component| over the 24 reals, components stored as
+ * fp16(value/scale)), and back.  parity EVEN/ODD: host holds V/2 sites;
+ * FULL: host holds V sites.  Synchronous with respect to host memory. */
+lq_status lq_spinor_to_device(lq_ctx* ctx, void* dev, const double* host, int parity,
+                              int prec, int nrhs);
+lq_status lq_spinor_to_host(lq_ctx* ctx, double* host, const void* dev, int parity,
+                            int prec, int nrhs);
+
+/* Even-odd hopping term: out = H_eo in (out_parity EVEN, in odd) or H_oe in
+ * (out_parity ODD, in even); dagger != 0 applies the blocks of H^dagger.
+ * Both fields of precision prec; asynchronous on the context stream. */
+lq_status lq_dslash(lq_ctx* ctx, void* dev_out, const void* dev_in, int out_parity,
+                    int dagger, int prec, int nrhs);
+
+/* out = A_pp in or A_pp^{-1} in on one parity.  F64 supports both parities
+ * and both forms; F32/F16 support A_ee and A_oo^{-1}. */
+lq_status lq_clover_apply(lq_ctx* ctx, void* dev_out, const void* dev_in, int parity,
+                          int inverse, int prec, int nrhs);
+
+/* Schur operator on even fields: out = Mhat in (dagger = 0) or Mhat^dagger in.
+ * Needs lq_set_clover.  dev_tmp: caller buffer of lq_field_bytes(ODD, prec, nrhs). */
+lq_status lq_schur(lq_ctx* ctx, void* dev_out, const void* dev_in, void* dev_tmp, int dagger,
+                   int prec, int nrhs);
+
+/* Global reductions on a device field (FP64 accumulation, fixed tree order):
+ * out[0] = sum |a|^2; dot: out[0] + i out[1] = sum conj(a) b. */
+lq_status lq_norm2(lq_ctx* ctx, double* out, const void* dev_a, int parity, int prec);
+lq_status lq_dot(lq_ctx* ctx, double* out, const void* dev_a, const void* dev_b, int parity,
+                 int prec);
+
+/* Solve M x = b on the full lattice for nrhs right-hand sides with the
+ * clover term of (kappa, csw) (rebuilt if these differ from the current
+ * ones).  Stops when the FP64 true residual ||b - M x|| / ||b|| <= tol for
+ * every RHS.  host_b, host_x: nrhs * V * 12 complex128.  report: nrhs
+ * entries (may be NULL).  Returns LQ_ENOCONV when maxiter is reached. */
+lq_status lq_solve(lq_ctx* ctx, double* host_x, const double* host_b, int nrhs, double kappa,
+                   double csw, double tol, const lq_solver_params* params,
+                   lq_solve_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQ_H */

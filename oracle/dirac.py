@@ -112,3 +112,29 @@ def inner(a: np.ndarray, b: np.ndarray) -> complex:
 
 def norm(a: np.ndarray) -> float:
     return float(np.linalg.norm(a.reshape(-1)))
+
+
+def hop_at(u: np.ndarray, psi: np.ndarray, site, dagger: bool = False,
+           antiperiodic_t: bool = True) -> np.ndarray:
+    """(H psi)(x) at the single site x = (x0, x1, x2, x3), from its eight
+    neighbours; the same definition as hop(), evaluated one site at a time so
+    that outputs of very large lattices can be sampled."""
+    lt, lz, ly, lx = psi.shape[:4]
+    ext = (lx, ly, lz, lt)
+    x = list(site)
+    sgn = -1.0 if dagger else 1.0
+    out = np.zeros((4, 3), dtype=np.complex128)
+    for mu in range(4):
+        f = list(x)
+        f[mu] = (x[mu] + 1) % ext[mu]
+        b = list(x)
+        b[mu] = (x[mu] - 1) % ext[mu]
+        bc_f = -1.0 if (antiperiodic_t and mu == 3 and x[3] == ext[3] - 1) else 1.0
+        bc_b = -1.0 if (antiperiodic_t and mu == 3 and x[3] == 0) else 1.0
+        u_f = u[x[3], x[2], x[1], x[0], mu]
+        u_b = u[b[3], b[2], b[1], b[0], mu]
+        chi_f = bc_f * (psi[f[3], f[2], f[1], f[0]] @ u_f.T)
+        chi_b = bc_b * (psi[b[3], b[2], b[1], b[0]] @ u_b.conj())
+        out += (ONE4 - sgn * GAMMA[mu]) @ chi_f
+        out += (ONE4 + sgn * GAMMA[mu]) @ chi_b
+    return out

@@ -1,0 +1,280 @@
+// C ABI entry points (include/lq.h): argument checks, error capture, context
+// lifetime.  No C++ exception crosses this boundary.
+#include <cstring>
+#include <new>
+
+#include "lq_internal.h"
+#include "reduce.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class F>
+lq_status guarded(lq_ctx* ctx, F&& f) {
+  if (!ctx) return LQ_EINVAL;
+  hipStream_t saved = ctx->cur;
+  try {
+    f();
+    ctx->cur = saved;
+    return LQ_OK;
+  } catch (const lq::Error& e) {
+    ctx->cur = saved;
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->cur = saved;
+    ctx->err = "host allocation failed";
+    return LQ_ENOMEM;
+  } catch (const std::exception& e) {
+    ctx->cur = saved;
+    ctx->err = e.what();
+    return LQ_EINVAL;
+  }
+}
+
+void check_parity(int parity, bool allow_full) {
+  LQ_CHECK(parity == LQ_EVEN || parity == LQ_ODD || (allow_full && parity == LQ_FULL), LQ_EINVAL,
+           "bad parity");
+}
+void check_prec(int prec) {
+  LQ_CHECK(prec == LQ_F64 || prec == LQ_F32 || prec == LQ_F16, LQ_EINVAL, "bad precision");
+}
+
+}  // namespace
+
+namespace lq {
+
+size_t field_bytes(const lq_ctx* ctx, int parity, int prec, int nrhs) {
+  size_t one = parity_field_bytes(ctx->geo.nblk, prec);
+  return one * (parity == LQ_FULL ? 2 : 1) * (size_t)(nrhs > 0 ? nrhs : 1);
+}
+
+void* staging(lq_ctx* ctx, size_t bytes) {
+  if (ctx->staging_bytes < bytes) {
+    if (ctx->staging) {
+      LQ_HIP(hipStreamSynchronize(ctx->cur));
+      (void)hipFree(ctx->staging);
+      ctx->staging = nullptr;
+      ctx->staging_bytes = 0;
+    }
+    LQ_HIP(hipMalloc(&ctx->staging, bytes));
+    ctx->staging_bytes = bytes;
+  }
+  return ctx->staging;
+}
+
+void ensure_red(lq_ctx* ctx) {
+  if (!ctx->red) {
+    LQ_HIP(hipMalloc(&ctx->red, RED_BYTES));
+    LQ_HIP(hipMemsetAsync(ctx->red, 0, RED_BYTES, ctx->cur));
+  }
+}
+
+}  // namespace lq
+
+extern "C" {
+
+lq_status lq_create(const int dims[4], int t_antiperiodic, void* hip_stream, lq_ctx** out) {
+  if (!out || !dims) {
+    g_create_error = "null argument";
+    return LQ_EINVAL;
+  }
+  *out = nullptr;
+  for (int k = 0; k < 4; ++k)
+    if (dims[k] < 2 || (dims[k] & 1)) {
+      g_create_error = "every lattice extent must be even and >= 2";
+      return LQ_EINVAL;
+    }
+  const int64_t V = (int64_t)dims[0] * dims[1] * dims[2] * dims[3];
+  if (V / 2 > (int64_t)lq::RED_MAX_BLOCKS * 256) {
+    g_create_error = "lattice too large for the reduction scratch";
+    return LQ_EINVAL;
+  }
+  lq_ctx* ctx = new (std::nothrow) lq_ctx();
+  if (!ctx) return LQ_ENOMEM;
+  for (int k = 0; k < 4; ++k) {
+    ctx->dims[k] = dims[k];
+    ctx->geo.L[k] = dims[k];
+  }
+  ctx->geo.lxh = dims[0] / 2;
+  ctx->geo.apt = t_antiperiodic ? 1 : 0;
+  ctx->V = V;
+  ctx->geo.vh = V / 2;
+  ctx->geo.nblk = (V / 2 + lq::SB - 1) / lq::SB;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  ctx->cur = ctx->stream;
+  const hipError_t se = hipStreamCreateWithFlags(&ctx->sstream, hipStreamNonBlocking);
+  if (se != hipSuccess) {
+    g_create_error = std::string("hipStreamCreateWithFlags failed: ") + hipGetErrorName(se) +
+                     " (" + hipGetErrorString(se) + ")";
+    delete ctx;
+    return LQ_EHIP;
+  }
+  *out = ctx;
+  return LQ_OK;
+}
+
+void lq_destroy(lq_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  (void)hipStreamSynchronize(ctx->sstream);
+  lq::free_work(ctx);
+  lq::free_clover(ctx);
+  for (int p = 0; p < 3; ++p)
+    if (ctx->gauge[p]) (void)hipFree(ctx->gauge[p]);
+  if (ctx->staging) (void)hipFree(ctx->staging);
+  if (ctx->red) (void)hipFree(ctx->red);
+  (void)hipStreamDestroy(ctx->sstream);
+  delete ctx;
+}
+
+const char* lq_last_error(const lq_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+size_t lq_field_bytes(const lq_ctx* ctx, int parity, int prec, int nrhs) {
+  if (!ctx || (parity != LQ_EVEN && parity != LQ_ODD && parity != LQ_FULL) || prec < 0 ||
+      prec > 2 || nrhs < 1)
+    return 0;
+  return lq::field_bytes(ctx, parity, prec, nrhs);
+}
+
+int64_t lq_volume(const lq_ctx* ctx) { return ctx ? ctx->V : 0; }
+
+lq_status lq_upload_gauge(lq_ctx* ctx, const double* host_U) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(host_U, LQ_EINVAL, "null gauge pointer");
+    lq::upload_gauge(ctx, host_U);
+  });
+}
+
+lq_status lq_set_clover(lq_ctx* ctx, double kappa, double csw) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(kappa > 0.0 && kappa < 0.25, LQ_EINVAL, "kappa must lie in (0, 0.25)");
+    LQ_CHECK(csw >= 0.0, LQ_EINVAL, "csw must be >= 0");
+    lq::build_clover(ctx, kappa, csw);
+  });
+}
+
+lq_status lq_spinor_to_device(lq_ctx* ctx, void* dev, const double* host, int parity, int prec,
+                              int nrhs) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(dev && host && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
+    check_parity(parity, true);
+    check_prec(prec);
+    const int full = parity == LQ_FULL;
+    const int64_t nsites = full ? ctx->V : ctx->geo.vh;
+    const size_t hb = (size_t)nsites * 12 * 16;
+    const size_t fb = lq::field_bytes(ctx, parity, prec, 1);
+    double2* st = reinterpret_cast<double2*>(lq::staging(ctx, hb));
+    for (int r = 0; r < nrhs; ++r) {
+      LQ_HIP(hipMemcpyAsync(st, host + (size_t)r * nsites * 24, hb, hipMemcpyHostToDevice,
+                            ctx->cur));
+      lq::pack_spinor(ctx, reinterpret_cast<char*>(dev) + r * fb, st, prec, nsites, full);
+    }
+    LQ_HIP(hipStreamSynchronize(ctx->cur));
+  });
+}
+
+lq_status lq_spinor_to_host(lq_ctx* ctx, double* host, const void* dev, int parity, int prec,
+                            int nrhs) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(dev && host && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
+    check_parity(parity, true);
+    check_prec(prec);
+    const int full = parity == LQ_FULL;
+    const int64_t nsites = full ? ctx->V : ctx->geo.vh;
+    const size_t hb = (size_t)nsites * 12 * 16;
+    const size_t fb = lq::field_bytes(ctx, parity, prec, 1);
+    double2* st = reinterpret_cast<double2*>(lq::staging(ctx, hb));
+    for (int r = 0; r < nrhs; ++r) {
+      lq::unpack_spinor(ctx, st, reinterpret_cast<const char*>(dev) + r * fb, prec, full);
+      LQ_HIP(hipMemcpyAsync(host + (size_t)r * nsites * 24, st, hb, hipMemcpyDeviceToHost,
+                            ctx->cur));
+      LQ_HIP(hipStreamSynchronize(ctx->cur));
+    }
+  });
+}
+
+lq_status lq_dslash(lq_ctx* ctx, void* dev_out, const void* dev_in, int out_parity, int dagger,
+                    int prec, int nrhs) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(ctx->have_gauge, LQ_ESTATE, "no gauge field uploaded");
+    LQ_CHECK(dev_out && dev_in && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
+    LQ_CHECK(dev_out != dev_in, LQ_EINVAL, "dslash cannot run in place");
+    check_parity(out_parity, false);
+    check_prec(prec);
+    const size_t fb = lq::field_bytes(ctx, LQ_EVEN, prec, 1);
+    for (int r = 0; r < nrhs; ++r)
+      lq::dslash(ctx, reinterpret_cast<char*>(dev_out) + r * fb,
+                 reinterpret_cast<const char*>(dev_in) + r * fb, out_parity, dagger, prec);
+  });
+}
+
+lq_status lq_clover_apply(lq_ctx* ctx, void* dev_out, const void* dev_in, int parity, int inverse,
+                          int prec, int nrhs) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(ctx->clov.valid, LQ_ESTATE, "no clover term (call lq_set_clover)");
+    LQ_CHECK(dev_out && dev_in && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
+    check_parity(parity, false);
+    check_prec(prec);
+    const size_t fb = lq::field_bytes(ctx, LQ_EVEN, prec, 1);
+    for (int r = 0; r < nrhs; ++r)
+      lq::clover_apply(ctx, reinterpret_cast<char*>(dev_out) + r * fb,
+                       reinterpret_cast<const char*>(dev_in) + r * fb, parity, inverse, prec);
+  });
+}
+
+lq_status lq_schur(lq_ctx* ctx, void* dev_out, const void* dev_in, void* dev_tmp, int dagger,
+                   int prec, int nrhs) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(ctx->clov.valid, LQ_ESTATE, "no clover term (call lq_set_clover)");
+    LQ_CHECK(dev_out && dev_in && dev_tmp && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
+    LQ_CHECK(dev_out != dev_in && dev_tmp != dev_in && dev_tmp != dev_out, LQ_EINVAL,
+             "schur needs three distinct buffers");
+    check_prec(prec);
+    const size_t fb = lq::field_bytes(ctx, LQ_EVEN, prec, 1);
+    for (int r = 0; r < nrhs; ++r)
+      lq::schur(ctx, reinterpret_cast<char*>(dev_out) + r * fb,
+                reinterpret_cast<const char*>(dev_in) + r * fb,
+                reinterpret_cast<char*>(dev_tmp) + r * fb, dagger, prec);
+  });
+}
+
+lq_status lq_norm2(lq_ctx* ctx, double* out, const void* dev_a, int parity, int prec) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(out && dev_a, LQ_EINVAL, "null pointer");
+    check_parity(parity, false);
+    check_prec(prec);
+    lq::norm2(ctx, out, dev_a, prec);
+  });
+}
+
+lq_status lq_dot(lq_ctx* ctx, double* out, const void* dev_a, const void* dev_b, int parity,
+                 int prec) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(out && dev_a && dev_b, LQ_EINVAL, "null pointer");
+    check_parity(parity, false);
+    check_prec(prec);
+    lq::dot(ctx, out, dev_a, dev_b, prec);
+  });
+}
+
+lq_status lq_solve(lq_ctx* ctx, double* host_x, const double* host_b, int nrhs, double kappa,
+                   double csw, double tol, const lq_solver_params* params,
+                   lq_solve_report* report) {
+  lq_status st = LQ_OK;
+  lq_status g = guarded(ctx, [&] {
+    LQ_CHECK(host_x && host_b && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
+    LQ_CHECK(ctx->have_gauge, LQ_ESTATE, "no gauge field uploaded");
+    LQ_CHECK(kappa > 0.0 && kappa < 0.25 && csw >= 0.0, LQ_EINVAL, "bad kappa or csw");
+    LQ_CHECK(tol > 0.0 && tol < 1.0, LQ_EINVAL, "tol must lie in (0, 1)");
+    lq::solve(ctx, host_x, host_b, nrhs, kappa, csw, tol, params, report);
+  });
+  (void)st;
+  return g;
+}
+
+}  // extern "C"

@@ -1,0 +1,226 @@
+// Gauge-field upload with 12-real compression, and spinor packing between
+// the host canonical layout and the device site-blocked layouts.
+#include "lq_internal.h"
+
+namespace lq {
+
+namespace {
+
+// One thread per (site, direction): writes rows 0 and 1 of U_mu(x) in FP64,
+// FP32 and FP16 to the compressed arrays of the site's parity and reports
+// max(|U U^dagger - 1|, |det U - 1|) for the block.
+__global__ void compress_gauge_kernel(Geo g, const double2* __restrict__ host, double2* g64,
+                                      float2* g32, __half2* g16, double* blockmax,
+                                      int64_t nlinks) {
+  __shared__ double red[256];
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double err = 0.0;
+  if (t < nlinks) {
+    int64_t i = t >> 2;
+    int mu = (int)(t & 3);
+    // coordinates of full index i
+    int64_t r = i;
+    int x0 = (int)(r % g.L[0]);
+    r /= g.L[0];
+    int x1 = (int)(r % g.L[1]);
+    r /= g.L[1];
+    int x2 = (int)(r % g.L[2]);
+    int x3 = (int)(r / g.L[2]);
+    int p = (x0 + x1 + x2 + x3) & 1;
+    int64_t s = i >> 1;
+    C<double> u[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        double2 v = host[t * 9 + a * 3 + b];
+        u[a][b] = {v.x, v.y};
+      }
+    // unitarity
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        C<double> acc = {0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc = acc + u[a][c] * conj(u[b][c]);
+        if (a == b) acc.re -= 1.0;
+        err = fmax(err, sqrt(norm2(acc)));
+      }
+    C<double> det = u[0][0] * (u[1][1] * u[2][2] - u[1][2] * u[2][1]) -
+                    u[0][1] * (u[1][0] * u[2][2] - u[1][2] * u[2][0]) +
+                    u[0][2] * (u[1][0] * u[2][1] - u[1][1] * u[2][0]);
+    det.re -= 1.0;
+    err = fmax(err, sqrt(norm2(det)));
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      C<double> v = u[c / 3][c % 3];
+      int64_t k = link_idx(g.nblk, p, mu, s, c);
+      g64[k] = make_double2(v.re, v.im);
+      g32[k] = make_float2((float)v.re, (float)v.im);
+      _Float16 hr = (_Float16)v.re, hi = (_Float16)v.im;
+      __half2 h;
+      h.x = __half(hr);
+      h.y = __half(hi);
+      g16[k] = h;
+    }
+  }
+  red[threadIdx.x] = err;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blockmax[blockIdx.x] = red[0];
+}
+
+// Host canonical half or full field (double2 per complex) -> device field.
+// full = 1: thread per full-lattice site; else thread per checkerboard site.
+template <class P>
+__global__ void pack_kernel(Geo g, Field<P> f_even, Field<P> f_odd, const double2* __restrict__ src,
+                            int64_t n, int full) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  Field<P> f = f_even;
+  int64_t s = t;
+  if (full) {
+    int64_t r = t;
+    int x0 = (int)(r % g.L[0]);
+    r /= g.L[0];
+    int x1 = (int)(r % g.L[1]);
+    r /= g.L[1];
+    int x2 = (int)(r % g.L[2]);
+    int x3 = (int)(r / g.L[2]);
+    if ((x0 + x1 + x2 + x3) & 1) f = f_odd;
+    s = t >> 1;
+  }
+  double2 v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = src[t * 12 + c];
+  if constexpr (P::has_norm) {
+    double m = 0.0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmax(m, fmax(fabs(v[c].x), fabs(v[c].y)));
+    f.norm[s] = (float)m;
+    double inv = m > 0.0 ? 1.0 / m : 0.0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      __half2 h;
+      h.x = __half((_Float16)(v[c].x * inv));
+      h.y = __half((_Float16)(v[c].y * inv));
+      f.d[spin_idx(s, c)] = h;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+      st<P>(f.d, spin_idx(s, c), C<typename P::R>{(typename P::R)v[c].x, (typename P::R)v[c].y});
+  }
+}
+
+template <class P>
+__global__ void unpack_kernel(Geo g, Field<P> f_even, Field<P> f_odd, double2* __restrict__ dst,
+                              int64_t n, int full) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  Field<P> f = f_even;
+  int64_t s = t;
+  if (full) {
+    int64_t r = t;
+    int x0 = (int)(r % g.L[0]);
+    r /= g.L[0];
+    int x1 = (int)(r % g.L[1]);
+    r /= g.L[1];
+    int x2 = (int)(r % g.L[2]);
+    int x3 = (int)(r / g.L[2]);
+    if ((x0 + x1 + x2 + x3) & 1) f = f_odd;
+    s = t >> 1;
+  }
+  C<typename P::R> v[12];
+  load_spinor<P>(f, s, v);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) dst[t * 12 + c] = make_double2((double)v[c].re, (double)v[c].im);
+}
+
+template <class P>
+void pack_t(lq_ctx* ctx, void* dev, const double2* src, int full) {
+  const Geo& g = ctx->geo;
+  char* base = reinterpret_cast<char*>(dev);
+  Field<P> fe = field_at<P>(base, g.nblk);
+  Field<P> fo = field_at<P>(base + parity_field_bytes(g.nblk, P::id), g.nblk);
+  int64_t n = full ? ctx->V : g.vh;
+  hipLaunchKernelGGL(pack_kernel<P>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur, g, fe, fo,
+                     src, n, full);
+  LQ_HIP(hipGetLastError());
+}
+
+template <class P>
+void unpack_t(lq_ctx* ctx, double2* dst, const void* dev, int full) {
+  const Geo& g = ctx->geo;
+  char* base = reinterpret_cast<char*>(const_cast<void*>(dev));
+  Field<P> fe = field_at<P>(base, g.nblk);
+  Field<P> fo = field_at<P>(base + parity_field_bytes(g.nblk, P::id), g.nblk);
+  int64_t n = full ? ctx->V : g.vh;
+  hipLaunchKernelGGL(unpack_kernel<P>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur, g, fe,
+                     fo, dst, n, full);
+  LQ_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void upload_gauge(lq_ctx* ctx, const double* host_U) {
+  const Geo& g = ctx->geo;
+  const int64_t nlinks = ctx->V * 4;
+  const size_t host_bytes = (size_t)nlinks * 9 * 16;
+  double2* st = reinterpret_cast<double2*>(staging(ctx, host_bytes));
+  LQ_HIP(hipMemcpyAsync(st, host_U, host_bytes, hipMemcpyHostToDevice, ctx->cur));
+  const int64_t ncomp = 2 * 4 * g.nblk * 6 * SB;
+  for (int p = 0; p < 3; ++p) {
+    if (!ctx->gauge[p]) {
+      size_t b = (size_t)ncomp * (p == 0 ? 16 : p == 1 ? 8 : 4);
+      LQ_HIP(hipMalloc(&ctx->gauge[p], b));
+      LQ_HIP(hipMemsetAsync(ctx->gauge[p], 0, b, ctx->cur));
+    }
+  }
+  const int nb = grid_for(nlinks, 256);
+  double* bm = nullptr;
+  LQ_HIP(hipMalloc(&bm, sizeof(double) * nb));
+  hipLaunchKernelGGL(compress_gauge_kernel, dim3(nb), dim3(256), 0, ctx->cur, g, st,
+                     (double2*)ctx->gauge[0], (float2*)ctx->gauge[1], (__half2*)ctx->gauge[2], bm,
+                     nlinks);
+  hipError_t le = hipGetLastError();
+  std::vector<double> hbm(nb);
+  hipError_t ce = hipMemcpyAsync(hbm.data(), bm, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                                 ctx->cur);
+  hipError_t se = hipStreamSynchronize(ctx->cur);
+  (void)hipFree(bm);
+  LQ_HIP(le);
+  LQ_HIP(ce);
+  LQ_HIP(se);
+  double worst = 0.0;
+  for (double v : hbm) worst = v > worst ? v : worst;
+  if (!(worst <= 1e-12)) {
+    ctx->have_gauge = false;
+    throw Error(LQ_EINVAL, "gauge field is not SU(3): max(|UU^+ - 1|, |det U - 1|) = " +
+                               std::to_string(worst));
+  }
+  ctx->have_gauge = true;
+  ctx->clov.valid = false;
+}
+
+void pack_spinor(lq_ctx* ctx, void* dev, const double2* src, int prec, int64_t, int full) {
+  switch (prec) {
+    case LQ_F64: pack_t<P64>(ctx, dev, src, full); break;
+    case LQ_F32: pack_t<P32>(ctx, dev, src, full); break;
+    default: pack_t<P16>(ctx, dev, src, full); break;
+  }
+}
+
+void unpack_spinor(lq_ctx* ctx, double2* dst, const void* dev, int prec, int full) {
+  switch (prec) {
+    case LQ_F64: unpack_t<P64>(ctx, dst, dev, full); break;
+    case LQ_F32: unpack_t<P32>(ctx, dst, dev, full); break;
+    default: unpack_t<P16>(ctx, dst, dev, full); break;
+  }
+}
+
+}  // namespace lq

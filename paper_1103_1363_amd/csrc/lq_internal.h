@@ -1,0 +1,300 @@
+// Internal declarations of the lq library: context, device layouts, the
+// complex arithmetic and precision traits shared by the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/lq.h"
+
+namespace lq {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  lq_status code;
+  Error(lq_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define LQ_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw ::lq::Error(LQ_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LQ_CHECK(cond, code, msg)                     \
+  do {                                                \
+    if (!(cond)) throw ::lq::Error((code), (msg));    \
+  } while (0)
+
+// ---------------------------------------------------------------- layout
+// Sites of one parity are numbered by their checkerboard index s = i / 2
+// (i the full-lattice index).  Device fields group sites into blocks of 64;
+// inside a block each complex component occupies 64 consecutive slots, so
+// the 64 lanes of a wavefront read one component of 64 consecutive sites
+// with a single coalesced load.
+constexpr int SB = 64;  // sites per block
+
+__host__ __device__ inline int64_t spin_idx(int64_t s, int c) {  // c in [0, 12)
+  return ((s >> 6) * 12 + c) * SB + (s & 63);
+}
+__host__ __device__ inline int64_t clov_idx(int64_t s, int c) {  // c in [0, 36)
+  return ((s >> 6) * 36 + c) * SB + (s & 63);
+}
+// compressed links: parity p, direction mu, site s, complex entry c in [0, 6)
+// (row 0 then row 1)
+__host__ __device__ inline int64_t link_idx(int64_t nblk, int p, int mu, int64_t s, int c) {
+  return ((((int64_t)p * 4 + mu) * nblk + (s >> 6)) * 6 + c) * SB + (s & 63);
+}
+
+// Lattice geometry as passed to kernels.
+struct Geo {
+  int L[4];      // Lx, Ly, Lz, Lt
+  int lxh;       // Lx / 2
+  int apt;       // antiperiodic in t
+  int64_t vh;    // sites per parity
+  int64_t nblk;  // blocks of 64 per parity (vh rounded up)
+};
+
+// Coordinates of checkerboard site s of parity p.
+__device__ inline void site_coords(const Geo& g, int p, int64_t s, int x[4]) {
+  int64_t r = s / g.lxh;
+  int xh = (int)(s - r * g.lxh);
+  x[1] = (int)(r % g.L[1]);
+  r /= g.L[1];
+  x[2] = (int)(r % g.L[2]);
+  x[3] = (int)(r / g.L[2]);
+  x[0] = 2 * xh + ((p + x[1] + x[2] + x[3]) & 1);
+}
+__device__ inline int64_t cb_index(const Geo& g, const int x[4]) {
+  return ((((int64_t)x[3] * g.L[2] + x[2]) * g.L[1] + x[1]) * g.L[0] + x[0]) >> 1;
+}
+
+// ---------------------------------------------------------------- complex
+template <class R>
+struct C {
+  R re, im;
+};
+template <class R>
+__device__ __forceinline__ C<R> cmk(R a, R b) { return C<R>{a, b}; }
+template <class R>
+__device__ __forceinline__ C<R> operator+(C<R> a, C<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R>
+__device__ __forceinline__ C<R> operator-(C<R> a, C<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R>
+__device__ __forceinline__ C<R> operator-(C<R> a) { return {-a.re, -a.im}; }
+template <class R>
+__device__ __forceinline__ C<R> operator*(C<R> a, C<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R>
+__device__ __forceinline__ C<R> operator*(R s, C<R> a) { return {s * a.re, s * a.im}; }
+template <class R>
+__device__ __forceinline__ C<R> conj(C<R> a) { return {a.re, -a.im}; }
+template <class R>
+__device__ __forceinline__ C<R> times_i(C<R> a) { return {-a.im, a.re}; }
+// conj(a) * b
+template <class R>
+__device__ __forceinline__ C<R> cmul_conj(C<R> a, C<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <class R>
+__device__ __forceinline__ R norm2(C<R> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------- precision traits
+// Storage type S, arithmetic type R.  FP16 fields hold fp16(value / scale)
+// with one FP32 scale per site stored after the component array.
+struct P64 {
+  using R = double;
+  using S = double2;
+  static constexpr bool has_norm = false;
+  static constexpr int id = LQ_F64;
+};
+struct P32 {
+  using R = float;
+  using S = float2;
+  static constexpr bool has_norm = false;
+  static constexpr int id = LQ_F32;
+};
+struct P16 {
+  using R = float;
+  using S = __half2;
+  static constexpr bool has_norm = true;
+  static constexpr int id = LQ_F16;
+};
+
+template <class P>
+__device__ __forceinline__ C<typename P::R> ld(const typename P::S* p, int64_t i);
+template <>
+__device__ __forceinline__ C<double> ld<P64>(const double2* p, int64_t i) {
+  double2 v = p[i];
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ C<float> ld<P32>(const float2* p, int64_t i) {
+  float2 v = p[i];
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ C<float> ld<P16>(const __half2* p, int64_t i) {
+  float2 v = __half22float2(p[i]);
+  return {v.x, v.y};
+}
+template <class P>
+__device__ __forceinline__ void st(typename P::S* p, int64_t i, C<typename P::R> v);
+template <>
+__device__ __forceinline__ void st<P64>(double2* p, int64_t i, C<double> v) {
+  p[i] = make_double2(v.re, v.im);
+}
+template <>
+__device__ __forceinline__ void st<P32>(float2* p, int64_t i, C<float> v) {
+  p[i] = make_float2(v.re, v.im);
+}
+template <>
+__device__ __forceinline__ void st<P16>(__half2* p, int64_t i, C<float> v) {
+  p[i] = __floats2half2_rn(v.re, v.im);
+}
+
+// A device spinor field of one parity (and one right-hand side).
+template <class P>
+struct Field {
+  typename P::S* d;
+  float* norm;  // FP16 only: per-site scale
+};
+
+// bytes of one parity field of vh sites for precision prec
+inline size_t parity_field_bytes(int64_t nblk, int prec) {
+  int64_t n = nblk * SB;
+  switch (prec) {
+    case LQ_F64: return (size_t)n * 12 * 16;
+    case LQ_F32: return (size_t)n * 12 * 8;
+    default: return (size_t)n * 12 * 4 + (size_t)n * 4;
+  }
+}
+
+template <class P>
+inline Field<P> field_at(void* base, int64_t nblk) {
+  Field<P> f;
+  f.d = reinterpret_cast<typename P::S*>(base);
+  f.norm = P::has_norm ? reinterpret_cast<float*>(reinterpret_cast<char*>(base) +
+                                                  (size_t)nblk * SB * 12 * 4)
+                       : nullptr;
+  return f;
+}
+
+// Load the 12 components of site s (spin-major, colour-minor).
+template <class P>
+__device__ __forceinline__ void load_spinor(const Field<P>& f, int64_t s,
+                                            C<typename P::R> v[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = ld<P>(f.d, spin_idx(s, c));
+  if constexpr (P::has_norm) {
+    float n = f.norm[s];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = n * v[c];
+  }
+}
+template <class P>
+__device__ __forceinline__ void store_spinor(const Field<P>& f, int64_t s,
+                                             C<typename P::R> v[12]) {
+  if constexpr (P::has_norm) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    f.norm[s] = m;
+    float inv = m > 0.f ? 1.f / m : 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st<P>(f.d, spin_idx(s, c), inv * v[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st<P>(f.d, spin_idx(s, c), v[c]);
+  }
+}
+
+// Load the 12 raw components of site s (FP16: without the scale) and the
+// site scale (1 for FP64/FP32).
+template <class P>
+__device__ __forceinline__ typename P::R load_raw(const Field<P>& f, int64_t s,
+                                                   C<typename P::R> v[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = ld<P>(f.d, spin_idx(s, c));
+  if constexpr (P::has_norm)
+    return f.norm[s];
+  else
+    return (typename P::R)1;
+}
+
+// ---------------------------------------------------------------- context
+struct Clover {
+  // FP64: A and A^{-1} for both parities; lower precisions: A_ee and A_oo^{-1}
+  void* a64[2] = {nullptr, nullptr};
+  void* ainv64[2] = {nullptr, nullptr};
+  void* a_ee[3] = {nullptr, nullptr, nullptr};
+  void* ainv_oo[3] = {nullptr, nullptr, nullptr};
+  double kappa = 0, csw = 0;
+  bool valid = false;
+};
+
+struct Work;  // solver work space (solver.hip)
+
+}  // namespace lq
+
+struct lq_ctx {
+  lq::Geo geo;
+  int dims[4];
+  int64_t V;
+  hipStream_t stream = nullptr;   // caller's stream (public per-operation calls)
+  hipStream_t sstream = nullptr;  // library-owned stream used by the solvers
+  hipStream_t cur = nullptr;      // stream the kernel wrappers launch on
+  void* gauge[3] = {nullptr, nullptr, nullptr};  // compressed links per precision
+  bool have_gauge = false;
+  lq::Clover clov;
+  void* staging = nullptr;  // FP64 host-layout staging buffer
+  size_t staging_bytes = 0;
+  void* red = nullptr;      // reduction scratch (partials + counter + result)
+  lq::Work* work = nullptr;
+  std::string err;
+};
+
+namespace lq {
+
+// Reduction scratch layout (ctx->red): partial sums then a counter then results.
+constexpr int RED_MAX_BLOCKS = 65536;
+constexpr int RED_NVAL = 4;  // values reduced at once at most
+
+size_t field_bytes(const lq_ctx* ctx, int parity, int prec, int nrhs);
+void* staging(lq_ctx* ctx, size_t bytes);
+void ensure_red(lq_ctx* ctx);
+
+// layout.hip
+void upload_gauge(lq_ctx* ctx, const double* host_U);
+void pack_spinor(lq_ctx* ctx, void* dev, const double2* src_dev, int prec, int64_t nsites_half,
+                 int full);
+void unpack_spinor(lq_ctx* ctx, double2* dst_dev, const void* dev, int prec, int full);
+
+// dslash.hip
+void dslash(lq_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec);
+void clover_apply(lq_ctx* ctx, void* out, const void* in, int parity, int inverse, int prec);
+void schur(lq_ctx* ctx, void* out, const void* in, void* tmp, int dagger, int prec);
+
+// clover.hip
+void build_clover(lq_ctx* ctx, double kappa, double csw);
+void free_clover(lq_ctx* ctx);
+
+// blas.hip
+void norm2(lq_ctx* ctx, double* out_host, const void* a, int prec);
+void dot(lq_ctx* ctx, double* out_host, const void* a, const void* b, int prec);
+
+// solver.hip
+void solve(lq_ctx* ctx, double* host_x, const double* host_b, int nrhs, double kappa, double csw,
+           double tol, const lq_solver_params* params, lq_solve_report* report);
+void free_work(lq_ctx* ctx);
+
+inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+}  // namespace lq

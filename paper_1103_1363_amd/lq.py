@@ -1,0 +1,229 @@
+"""Python binding of liblq.so (include/lq.h): argument marshalling only.
+
+Device fields are torch uint8 CUDA tensors of lq_field_bytes() bytes; every
+step of the operator and the solvers runs in the HIP library.  Importing
+this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblq.so")
+
+F64, F32, F16 = 0, 1, 2
+EVEN, ODD, FULL = 0, 1, 2
+CGNR, BICGSTAB, FGMRES_NET, FCG_NET = 0, 1, 2, 3
+PREC = {"f64": F64, "f32": F32, "f16": F16}
+
+STATUS = {0: "LQ_OK", -1: "LQ_EINVAL", -2: "LQ_ENOMEM", -3: "LQ_EHIP", -4: "LQ_ENOCONV",
+          -5: "LQ_ESTATE", -6: "LQ_ENAN"}
+
+
+class LQError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SolverParams(ct.Structure):
+    _fields_ = [("solver", ct.c_int), ("inner_prec", ct.c_int), ("maxiter", ct.c_int),
+                ("delta", ct.c_double), ("restart", ct.c_int), ("check_every", ct.c_int),
+                ("use_graph", ct.c_int), ("fault_inject", ct.c_int)]
+
+
+class SolveReport(ct.Structure):
+    _fields_ = [("iterations", ct.c_int), ("reliable_updates", ct.c_int),
+                ("fallback", ct.c_int), ("dslash_calls", ct.c_int),
+                ("true_residual", ct.c_double), ("schur_residual", ct.c_double),
+                ("seconds", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1103_1363_amd.build` (no CPU fallback exists)")
+        # torch ships its own HIP runtime; load it first so that liblq.so binds
+        # to the same runtime instance (two HIP runtimes in one process do not
+        # share devices, streams or allocations)
+        import torch  # noqa: F401
+        L = ct.CDLL(LIB_PATH)
+        vp, dp, ip = ct.c_void_p, ct.POINTER(ct.c_double), ct.c_int
+        L.lq_create.argtypes = [ct.POINTER(ct.c_int), ip, vp, ct.POINTER(vp)]
+        L.lq_create.restype = ip
+        L.lq_destroy.argtypes = [vp]
+        L.lq_destroy.restype = None
+        L.lq_last_error.argtypes = [vp]
+        L.lq_last_error.restype = ct.c_char_p
+        L.lq_field_bytes.argtypes = [vp, ip, ip, ip]
+        L.lq_field_bytes.restype = ct.c_size_t
+        L.lq_volume.argtypes = [vp]
+        L.lq_volume.restype = ct.c_int64
+        L.lq_upload_gauge.argtypes = [vp, dp]
+        L.lq_set_clover.argtypes = [vp, ct.c_double, ct.c_double]
+        L.lq_spinor_to_device.argtypes = [vp, vp, dp, ip, ip, ip]
+        L.lq_spinor_to_host.argtypes = [vp, dp, vp, ip, ip, ip]
+        L.lq_dslash.argtypes = [vp, vp, vp, ip, ip, ip, ip]
+        L.lq_clover_apply.argtypes = [vp, vp, vp, ip, ip, ip, ip]
+        L.lq_schur.argtypes = [vp, vp, vp, vp, ip, ip, ip]
+        L.lq_norm2.argtypes = [vp, dp, vp, ip, ip]
+        L.lq_dot.argtypes = [vp, dp, vp, vp, ip, ip]
+        L.lq_solve.argtypes = [vp, dp, dp, ip, ct.c_double, ct.c_double, ct.c_double,
+                               ct.POINTER(SolverParams), ct.POINTER(SolveReport)]
+        for name in ("lq_upload_gauge", "lq_set_clover", "lq_spinor_to_device",
+                     "lq_spinor_to_host", "lq_dslash", "lq_clover_apply", "lq_schur",
+                     "lq_norm2", "lq_dot", "lq_solve"):
+            getattr(L, name).restype = ip
+        _lib = L
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream_handle():
+    torch = _torch()
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Report:
+    iterations: int
+    reliable_updates: int
+    fallback: int
+    dslash_calls: int
+    true_residual: float
+    schur_residual: float
+    seconds: float
+
+
+class Lattice:
+    """One lq context: lattice geometry, gauge field, clover term, solvers."""
+
+    def __init__(self, dims, antiperiodic_t=True, stream=None):
+        self._L = lib()
+        self.dims = tuple(int(d) for d in dims)
+        arr = (ct.c_int * 4)(*self.dims)
+        h = ct.c_void_p()
+        st = stream if stream is not None else current_stream_handle()
+        rc = self._L.lq_create(arr, int(bool(antiperiodic_t)), st, ct.byref(h))
+        if rc != 0:
+            raise LQError(rc, self._L.lq_last_error(None).decode())
+        self._h = h
+        self.volume = int(self._L.lq_volume(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.lq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise LQError(rc, self._L.lq_last_error(self._h).decode())
+
+    # -- fields ---------------------------------------------------------
+    def field_bytes(self, parity, prec, nrhs=1):
+        return int(self._L.lq_field_bytes(self._h, parity, prec, nrhs))
+
+    def new_field(self, parity, prec, nrhs=1):
+        torch = _torch()
+        return torch.zeros(self.field_bytes(parity, prec, nrhs), dtype=torch.uint8,
+                           device="cuda")
+
+    def to_device(self, host, parity, prec, out=None):
+        host = np.ascontiguousarray(host, dtype=np.complex128)
+        nsite = self.volume if parity == FULL else self.volume // 2
+        nrhs = host.size // (nsite * 12)
+        assert nrhs * nsite * 12 == host.size, "host array size does not match the parity"
+        if out is None:
+            out = self.new_field(parity, prec, nrhs)
+        self._check(self._L.lq_spinor_to_device(self._h, ct.c_void_p(out.data_ptr()),
+                                                _dptr(host.view(np.float64)), parity, prec,
+                                                nrhs))
+        return out
+
+    def to_host(self, dev, parity, prec, nrhs=1):
+        nsite = self.volume if parity == FULL else self.volume // 2
+        out = np.empty((nrhs, nsite, 4, 3), dtype=np.complex128)
+        self._check(self._L.lq_spinor_to_host(self._h, _dptr(out.view(np.float64)),
+                                              ct.c_void_p(dev.data_ptr()), parity, prec, nrhs))
+        return out[0] if nrhs == 1 else out
+
+    # -- operator -------------------------------------------------------
+    def upload_gauge(self, u):
+        u = np.ascontiguousarray(u, dtype=np.complex128)
+        assert u.size == self.volume * 36
+        self._check(self._L.lq_upload_gauge(self._h, _dptr(u.view(np.float64))))
+
+    def set_clover(self, kappa, csw):
+        self._check(self._L.lq_set_clover(self._h, float(kappa), float(csw)))
+
+    def dslash(self, out, inp, out_parity, dagger=False, prec=F64, nrhs=1):
+        self._check(self._L.lq_dslash(self._h, ct.c_void_p(out.data_ptr()),
+                                      ct.c_void_p(inp.data_ptr()), out_parity, int(dagger),
+                                      prec, nrhs))
+
+    def clover(self, out, inp, parity, inverse=False, prec=F64, nrhs=1):
+        self._check(self._L.lq_clover_apply(self._h, ct.c_void_p(out.data_ptr()),
+                                            ct.c_void_p(inp.data_ptr()), parity,
+                                            int(inverse), prec, nrhs))
+
+    def schur(self, out, inp, tmp, dagger=False, prec=F64, nrhs=1):
+        self._check(self._L.lq_schur(self._h, ct.c_void_p(out.data_ptr()),
+                                     ct.c_void_p(inp.data_ptr()), ct.c_void_p(tmp.data_ptr()),
+                                     int(dagger), prec, nrhs))
+
+    def norm2(self, a, parity=EVEN, prec=F64):
+        v = np.zeros(1)
+        self._check(self._L.lq_norm2(self._h, _dptr(v), ct.c_void_p(a.data_ptr()), parity,
+                                     prec))
+        return float(v[0])
+
+    def dot(self, a, b, parity=EVEN, prec=F64):
+        v = np.zeros(2)
+        self._check(self._L.lq_dot(self._h, _dptr(v), ct.c_void_p(a.data_ptr()),
+                                   ct.c_void_p(b.data_ptr()), parity, prec))
+        return complex(v[0], v[1])
+
+    # -- solver ---------------------------------------------------------
+    def solve(self, b, kappa, csw, tol=1e-10, solver=CGNR, inner_prec=F64, maxiter=0,
+              delta=0.0, restart=0, check_every=0, use_graph=0, fault_inject=0,
+              raise_on_noconv=True):
+        """Solve M x = b on the full lattice; b has shape (nrhs?, V-sites..., 4, 3)."""
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        nrhs = b.size // (self.volume * 12)
+        assert nrhs * self.volume * 12 == b.size
+        x = np.zeros_like(b)
+        p = SolverParams(solver, inner_prec, maxiter, delta, restart, check_every, use_graph,
+                         fault_inject)
+        reps = (SolveReport * nrhs)()
+        rc = self._L.lq_solve(self._h, _dptr(x.view(np.float64)), _dptr(b.view(np.float64)),
+                              nrhs, float(kappa), float(csw), float(tol), ct.byref(p), reps)
+        reports = [Report(**r.as_dict()) for r in reps]
+        if rc != 0 and (rc != -4 or raise_on_noconv):
+            self._check(rc)
+        return x, reports

@@ -176,3 +176,14 @@ def test_hop_is_antiperiodic_in_t_only():
     # at x3 = 0 the backward t hop flips: (1+g4)(-chi) + (1-g4) chi = -2 g4 chi
     expect = 6 * chi - 2 * dirac.GAMMA[3] @ chi
     assert np.allclose(edge, expect)
+
+
+def test_hop_at_matches_hop():
+    dims = (4, 2, 6, 4)
+    u = fields.gauge_field(dims, "haar", 45)
+    psi = fields.gaussian_spinor(dims, 46)
+    for dag in (False, True):
+        h = dirac.hop(u, psi, dagger=dag)
+        for site in [(0, 0, 0, 0), (3, 1, 5, 3), (2, 0, 3, 0), (1, 1, 1, 3)]:
+            x0, x1, x2, x3 = site
+            assert np.max(np.abs(dirac.hop_at(u, psi, site, dag) - h[x3, x2, x1, x0])) < 1e-14
