@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the even-odd Wilson-clover solve on one MI355X.
+
+One step = one complete solve of M x = b to a 1e-10 FP64 true residual on
+the 32^3x64 lattice (kappa = 0.135, csw = 1.0, smooth SU(3) links with
+eps = 0.3, Gaussian source), with b and x resident in HBM: mixed-precision
+CG on the normal equations of the Schur operator (FP32 inner iteration by
+default, FP64 reliable updates, FP64 final residual).
+
+Printed (one JSON line):
+  value         whole-solve throughput: algorithmic bytes of every kernel the
+                solve launched / wall time of the timed steps, in GB/s;
+  ms_per_step   wall time per solve;
+  roofline      the solve's dominant kernel (largest share of kernel time),
+                timed with HIP events inside the library during one
+                profiled solve, priced against the 8 TB/s HBM peak;
+  plain_fp64    the same solve with plain FP64 CG, for comparison;
+  dslash_gbs    stand-alone hopping-term sweeps per precision (HIP events);
+  cpu_baseline  the FP64 oracle timed on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+KAPPA, CSW, TOL = 0.135, 1.0, 1e-10
+KNAMES = ["hop_oe+clover_inv", "hop_eo+clover+norm", "hop_oe_dag+clover_inv",
+          "hop_eo_dag+clover+cg_update", "p_update"]
+# rocprofv3 names of the iteration kernels (template arguments elided)
+KSYMBOLS = ["cg_k1<false>", "cg_k2", "cg_k1<true>", "cg_k4", "cg_k5"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def dslash_rates(lq, lat, torch, b_full, nrep=50):
+    """Stand-alone even-odd hopping sweeps H_eo on the 32^3x64 field per
+    precision, timed with torch events on the stream the library launches on."""
+    out = {}
+    vh = lat.volume // 2
+    for name, prec in (("f64", lq.F64), ("f32", lq.F32), ("f16", lq.F16)):
+        full = lat.to_device(b_full, lq.FULL, prec)
+        din = full[lat.field_bytes(lq.EVEN, prec):]  # odd half of the full field
+        dout = lat.new_field(lq.EVEN, prec)
+        for _ in range(5):
+            lat.dslash(dout, din, lq.EVEN, False, prec)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(nrep):
+            lat.dslash(dout, din, lq.EVEN, False, prec)
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / nrep
+        per_site = {"f64": 1152, "f32": 576, "f16": 296}[name]
+        gbs = per_site * vh / (us * 1e-6) / 1e9
+        out[name] = {"us": round(us, 2), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / 8000, 3),
+                     "GFLOP/s": round(1320 * vh / (us * 1e-6) / 1e9, 1)}
+        del full, din, dout
+    return out
+
+
+def cpu_baseline(u, b, dims):
+    """The FP64 oracle on the host: one even-odd hopping sweep H_eo of the same
+    32^3x64 workload (a bounded sample of the solve, whose iterations each make
+    four such sweeps), priced with the same algorithmic byte count."""
+    from oracle import evenodd
+    from oracle import dirac
+    e, o = evenodd.split(b, dims)
+    t0 = time.perf_counter()
+    full = evenodd.join(None, o, dims)
+    y = dirac.hop(u, full)
+    evenodd.split(y, dims)
+    dt = time.perf_counter() - t0
+    vh = e.shape[0]
+    return {"value": round(1152 * vh / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "seconds": round(dt, 2),
+            "sample": "one FP64 even-odd hopping-term sweep (H_eo, 1152 algorithmic bytes per "
+                      "output site) of the 32^3x64 field by the NumPy oracle, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--dims", default="32,32,32,64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): this build has no "
+              "multi-GPU path; how the solve would shard is described in DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if world != 1:
+        print("bench.py is single-process; run it without torch.distributed", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from gen import fields
+    from paper_1103_1363_amd import lq
+
+    dims = tuple(int(x) for x in a.dims.split(","))
+    inner = {"f32": lq.F32, "f16": lq.F16}[a.inner]
+    log(f"generating the {dims} smooth gauge field and source")
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 2)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 2)
+
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    lat.set_clover(KAPPA, CSW)
+    db = lat.to_device(b, lq.FULL, lq.F64)
+    dx = lat.new_field(lq.FULL, lq.F64)
+    torch.cuda.synchronize()
+
+    log(f"warmup: {a.warmup} solve(s), inner {a.inner}")
+    for _ in range(a.warmup):
+        lat.solve_device(dx, db, KAPPA, CSW, TOL, inner_prec=inner)
+    torch.cuda.synchronize()
+    log(f"timed: {a.steps} solve(s)")
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(a.steps):
+        reps += lat.solve_device(dx, db, KAPPA, CSW, TOL, inner_prec=inner)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    total_bytes = sum(r.bytes for r in reps)
+    value = total_bytes / wall / 1e9
+    r0 = reps[-1]
+    log(f"solve: {wall / a.steps * 1e3:.1f} ms, {r0.iterations} iterations, "
+        f"{r0.reliable_updates} reliable updates, residual {r0.true_residual:.2e}")
+
+    result = {
+        "metric": "Dslash GB/s & %HBM peak; solve time to 1e-10 residual, plain vs mixed/learned",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.inner,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{'x'.join(map(str, dims))} even-odd Wilson-clover solve to 1e-10 "
+                        f"(kappa={KAPPA}, csw={CSW}, smooth SU(3) links eps=0.3, Gaussian "
+                        f"source), CG on the Schur normal equations, {a.inner} inner "
+                        "iteration with FP64 reliable updates",
+            "lattice": list(dims), "kappa": KAPPA, "csw": CSW, "tol": TOL,
+            "rhs": 1, "parallelism": "single GPU",
+        },
+        "solve": {"iterations": r0.iterations, "reliable_updates": r0.reliable_updates,
+                  "fallback": r0.fallback, "true_residual": r0.true_residual,
+                  "seconds_inside_library": round(r0.seconds, 4),
+                  "algorithmic_GB": round(r0.bytes / 1e9, 2)},
+    }
+
+    x_mixed = lat.to_host(dx, lq.FULL, lq.F64)
+    if not a.no_plain:
+        log("plain FP64 solve for comparison")
+        dx2 = lat.new_field(lq.FULL, lq.F64)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        rp = lat.solve_device(dx2, db, KAPPA, CSW, TOL, inner_prec=lq.F64)[0]
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp
+        x_plain = lat.to_host(dx2, lq.FULL, lq.F64)
+        err = float(np.linalg.norm(x_mixed - x_plain) / np.linalg.norm(x_plain))
+        result["plain_fp64"] = {"ms": round(tp * 1e3, 2), "iterations": rp.iterations,
+                                "true_residual": rp.true_residual,
+                                "GB/s": round(rp.bytes / tp / 1e9, 1)}
+        result["speedup_vs_plain_fp64"] = round(tp / (wall / a.steps), 3)
+        result["mixed_vs_plain_rel_error"] = err
+        del dx2
+
+    log("profiled solve (per-kernel HIP events)")
+    rprof = lat.solve_device(dx, db, KAPPA, CSW, TOL, inner_prec=inner, profile=1)[0]
+    k = int(np.argmax(rprof.kernel_ms))
+    avg_s = rprof.kernel_ms[k] / rprof.kernel_calls[k] * 1e-3
+    achieved = rprof.kernel_bytes[k] / avg_s / 1e9
+    result["roofline"] = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+        "frac": round(achieved / 8000.0, 4), "traffic": None,
+        "kernel": f"{KSYMBOLS[k]} ({KNAMES[k]}, {a.inner})",
+        "bytes_per_launch": rprof.kernel_bytes[k], "avg_us": round(avg_s * 1e6, 2),
+        "launches_timed": rprof.kernel_calls[k],
+    }
+    result["kernels"] = {
+        KNAMES[i]: {"avg_us": round(rprof.kernel_ms[i] / max(1, rprof.kernel_calls[i]) * 1e3, 2),
+                    "GB/s": round(rprof.kernel_bytes[i] /
+                                  (rprof.kernel_ms[i] / max(1, rprof.kernel_calls[i]) * 1e-3)
+                                  / 1e9, 1) if rprof.kernel_ms[i] > 0 else None}
+        for i in range(5)}
+
+    log("stand-alone hopping-term sweeps")
+    result["dslash_gbs"] = dslash_rates(lq, lat, torch, b)
+
+    if not a.no_cpu_baseline:
+        log("CPU baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(u, b, dims)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

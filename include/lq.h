@@ -90,7 +90,18 @@ typedef struct {
   int use_graph;         /* 1 (default when 0 is given: 1) replay captured iterations;
                             -1 launch each kernel directly */
   int fault_inject;      /* tests only: 1 = force the inner solve to stagnate */
+  int profile;           /* 1: time every inner-iteration kernel with HIP events (no graph) */
 } lq_solver_params;
+
+/* Kernels of one inner CG iteration, in launch order (report index). */
+enum {
+  LQ_K_HOP_OE = 0,   /* t = A_oo^-1 H_oe p */
+  LQ_K_HOP_EO = 1,   /* q = A_ee p - kappa^2 H_eo t, |q|^2 */
+  LQ_K_HOPD_OE = 2,  /* t = A_oo^-1 H^+_oe q */
+  LQ_K_UPDATE = 3,   /* A_ee q - kappa^2 H^+_eo t fused with x, r, rt updates, |r|^2 */
+  LQ_K_PUPDATE = 4,  /* p = r + beta p */
+  LQ_NK = 5
+};
 
 typedef struct {
   int iterations;          /* inner iterations (all restarts, all RHS max) */
@@ -100,6 +111,10 @@ typedef struct {
   double true_residual;    /* ||b - M x|| / ||b|| of the full system, FP64 */
   double schur_residual;   /* ||bhat - Mhat x_e|| / ||bhat||, FP64 */
   double seconds;          /* wall time of the solve inside the library */
+  double bytes;            /* algorithmic (compulsory) bytes of every kernel launched */
+  double kernel_ms[LQ_NK];      /* profile = 1: summed durations per iteration kernel */
+  double kernel_bytes[LQ_NK];   /* algorithmic bytes of one launch of each kernel */
+  int kernel_calls[LQ_NK];      /* profile = 1: launches timed per kernel */
 } lq_solve_report;
 
 /* Context: owns device copies of the gauge field (12-real compressed, FP64,
@@ -165,6 +180,15 @@ lq_status lq_dot(lq_ctx* ctx, double* out, const void* dev_a, const void* dev_b,
 lq_status lq_solve(lq_ctx* ctx, double* host_x, const double* host_b, int nrhs, double kappa,
                    double csw, double tol, const lq_solver_params* params,
                    lq_solve_report* report);
+
+/* The same solve on device-resident fields: dev_b and dev_x are full-lattice
+ * FP64 fields (lq_field_bytes(ctx, LQ_FULL, LQ_F64, nrhs) bytes each, as
+ * written by lq_spinor_to_device with parity LQ_FULL), caller-owned and
+ * distinct.  dev_x is overwritten with the solution; no host transfer of
+ * b or x takes place.  The call returns after the solve has finished. */
+lq_status lq_solve_device(lq_ctx* ctx, void* dev_x, const void* dev_b, int nrhs, double kappa,
+                          double csw, double tol, const lq_solver_params* params,
+                          lq_solve_report* report);
 
 #ifdef __cplusplus
 }

@@ -265,16 +265,26 @@ lq_status lq_dot(lq_ctx* ctx, double* out, const void* dev_a, const void* dev_b,
 lq_status lq_solve(lq_ctx* ctx, double* host_x, const double* host_b, int nrhs, double kappa,
                    double csw, double tol, const lq_solver_params* params,
                    lq_solve_report* report) {
-  lq_status st = LQ_OK;
-  lq_status g = guarded(ctx, [&] {
+  return guarded(ctx, [&] {
     LQ_CHECK(host_x && host_b && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
     LQ_CHECK(ctx->have_gauge, LQ_ESTATE, "no gauge field uploaded");
     LQ_CHECK(kappa > 0.0 && kappa < 0.25 && csw >= 0.0, LQ_EINVAL, "bad kappa or csw");
     LQ_CHECK(tol > 0.0 && tol < 1.0, LQ_EINVAL, "tol must lie in (0, 1)");
-    lq::solve(ctx, host_x, host_b, nrhs, kappa, csw, tol, params, report);
+    lq::solve(ctx, host_x, host_b, nullptr, nullptr, nrhs, kappa, csw, tol, params, report);
   });
-  (void)st;
-  return g;
+}
+
+lq_status lq_solve_device(lq_ctx* ctx, void* dev_x, const void* dev_b, int nrhs, double kappa,
+                          double csw, double tol, const lq_solver_params* params,
+                          lq_solve_report* report) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(dev_x && dev_b && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
+    LQ_CHECK(dev_x != dev_b, LQ_EINVAL, "x and b must be distinct buffers");
+    LQ_CHECK(ctx->have_gauge, LQ_ESTATE, "no gauge field uploaded");
+    LQ_CHECK(kappa > 0.0 && kappa < 0.25 && csw >= 0.0, LQ_EINVAL, "bad kappa or csw");
+    LQ_CHECK(tol > 0.0 && tol < 1.0, LQ_EINVAL, "tol must lie in (0, 1)");
+    lq::solve(ctx, nullptr, nullptr, dev_x, dev_b, nrhs, kappa, csw, tol, params, report);
+  });
 }
 
 }  // extern "C"

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(RBLK) void norm2_kernel(Geo g, Field<P> a, RedBuf r
     }
     v[0] += acc * n * n;
   }
-  reduce_finalize<1>(v, rb, NoFin{});
+  block_partial<1>(v, rb.part);
 }
 
 template <class P>
@@ -50,15 +50,19 @@ __global__ __launch_bounds__(RBLK) void dot_kernel(Geo g, Field<P> a, Field<P> b
     v[0] += re * na * nb;
     v[1] += im * na * nb;
   }
-  reduce_finalize<2>(v, rb, NoFin{});
+  block_partial<2>(v, rb.part);
 }
 
 template <class P>
 void norm2_t(lq_ctx* ctx, double* out, const void* a) {
   const Geo& g = ctx->geo;
+  ctx->bytes += (double)g.vh * spinor_site_bytes(P::id);
   RedBuf rb = red_buf(ctx);
-  hipLaunchKernelGGL(norm2_kernel<P>, dim3(red_grid(g.vh)), dim3(RBLK), 0, ctx->cur, g,
+  const int nb = red_grid(g.vh);
+  hipLaunchKernelGGL(norm2_kernel<P>, dim3(nb), dim3(RBLK), 0, ctx->cur, g,
                      field_at<P>(const_cast<void*>(a), g.nblk), rb);
+  hipLaunchKernelGGL((finalize_kernel<1, NoFin>), dim3(1), dim3(256), 0, ctx->cur, rb, nb,
+                     NoFin{});
   LQ_HIP(hipGetLastError());
   LQ_HIP(hipMemcpyAsync(out, rb.result, sizeof(double), hipMemcpyDeviceToHost, ctx->cur));
   LQ_HIP(hipStreamSynchronize(ctx->cur));
@@ -67,10 +71,14 @@ void norm2_t(lq_ctx* ctx, double* out, const void* a) {
 template <class P>
 void dot_t(lq_ctx* ctx, double* out, const void* a, const void* b) {
   const Geo& g = ctx->geo;
+  ctx->bytes += (double)g.vh * 2 * spinor_site_bytes(P::id);
   RedBuf rb = red_buf(ctx);
-  hipLaunchKernelGGL(dot_kernel<P>, dim3(red_grid(g.vh)), dim3(RBLK), 0, ctx->cur, g,
+  const int nb = red_grid(g.vh);
+  hipLaunchKernelGGL(dot_kernel<P>, dim3(nb), dim3(RBLK), 0, ctx->cur, g,
                      field_at<P>(const_cast<void*>(a), g.nblk),
                      field_at<P>(const_cast<void*>(b), g.nblk), rb);
+  hipLaunchKernelGGL((finalize_kernel<2, NoFin>), dim3(1), dim3(256), 0, ctx->cur, rb, nb,
+                     NoFin{});
   LQ_HIP(hipGetLastError());
   LQ_HIP(hipMemcpyAsync(out, rb.result, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->cur));
   LQ_HIP(hipStreamSynchronize(ctx->cur));

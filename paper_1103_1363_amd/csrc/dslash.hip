@@ -70,6 +70,7 @@ __global__ __launch_bounds__(BLK) void schur_k2_kernel(Geo g, Field<P> out, Fiel
 template <class P>
 void dslash_t(lq_ctx* ctx, void* out, const void* in, int p, int dag) {
   const Geo& g = ctx->geo;
+  ctx->bytes += (double)g.vh * dslash_site_bytes(P::id);
   Field<P> fo = field_at<P>(out, g.nblk);
   Field<P> fi = field_at<P>(const_cast<void*>(in), g.nblk);
   auto* gp = reinterpret_cast<const typename P::S*>(ctx->gauge[P::id]);
@@ -86,6 +87,7 @@ void dslash_t(lq_ctx* ctx, void* out, const void* in, int p, int dag) {
 template <class P>
 void clover_t(lq_ctx* ctx, void* out, const void* in, const void* cl) {
   const Geo& g = ctx->geo;
+  ctx->bytes += (double)g.vh * (clover_site_bytes(P::id) + 2 * spinor_site_bytes(P::id));
   Field<P> fo = field_at<P>(out, g.nblk);
   Field<P> fi = field_at<P>(const_cast<void*>(in), g.nblk);
   hipLaunchKernelGGL(clover_kernel<P>, dim3(grid_for(g.vh, BLK)), dim3(BLK), 0, ctx->cur, g,
@@ -96,6 +98,9 @@ void clover_t(lq_ctx* ctx, void* out, const void* in, const void* cl) {
 template <class P, bool DAG>
 void schur_t(lq_ctx* ctx, void* out, const void* in, void* tmp) {
   const Geo& g = ctx->geo;
+  // K1: links, input, clover, output; K2: links, t, x, clover, output
+  ctx->bytes += (double)g.vh * (16 * link_site_bytes(P::id) + 5 * spinor_site_bytes(P::id) +
+                                2 * clover_site_bytes(P::id));
   Field<P> fo = field_at<P>(out, g.nblk);
   Field<P> fi = field_at<P>(const_cast<void*>(in), g.nblk);
   Field<P> ft = field_at<P>(tmp, g.nblk);

@@ -135,10 +135,13 @@ __global__ void unpack_kernel(Geo g, Field<P> f_even, Field<P> f_odd, double2* _
     if ((x0 + x1 + x2 + x3) & 1) f = f_odd;
     s = t >> 1;
   }
+  // the stored value is component * scale; form the product in FP64 so the
+  // host sees exactly what the field represents
   C<typename P::R> v[12];
-  load_spinor<P>(f, s, v);
+  const double sc = (double)load_raw<P>(f, s, v);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) dst[t * 12 + c] = make_double2((double)v[c].re, (double)v[c].im);
+  for (int c = 0; c < 12; ++c)
+    dst[t * 12 + c] = make_double2(sc * (double)v[c].re, sc * (double)v[c].im);
 }
 
 template <class P>
@@ -148,6 +151,7 @@ void pack_t(lq_ctx* ctx, void* dev, const double2* src, int full) {
   Field<P> fe = field_at<P>(base, g.nblk);
   Field<P> fo = field_at<P>(base + parity_field_bytes(g.nblk, P::id), g.nblk);
   int64_t n = full ? ctx->V : g.vh;
+  ctx->bytes += (double)n * (192.0 + spinor_site_bytes(P::id));
   hipLaunchKernelGGL(pack_kernel<P>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur, g, fe, fo,
                      src, n, full);
   LQ_HIP(hipGetLastError());
@@ -160,6 +164,7 @@ void unpack_t(lq_ctx* ctx, double2* dst, const void* dev, int full) {
   Field<P> fe = field_at<P>(base, g.nblk);
   Field<P> fo = field_at<P>(base + parity_field_bytes(g.nblk, P::id), g.nblk);
   int64_t n = full ? ctx->V : g.vh;
+  ctx->bytes += (double)n * (192.0 + spinor_site_bytes(P::id));
   hipLaunchKernelGGL(unpack_kernel<P>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur, g, fe,
                      fo, dst, n, full);
   LQ_HIP(hipGetLastError());

@@ -259,6 +259,7 @@ struct lq_ctx {
   void* red = nullptr;      // reduction scratch (partials + counter + result)
   lq::Work* work = nullptr;
   std::string err;
+  double bytes = 0.0;       // algorithmic bytes of every kernel launched so far
 };
 
 namespace lq {
@@ -291,10 +292,28 @@ void norm2(lq_ctx* ctx, double* out_host, const void* a, int prec);
 void dot(lq_ctx* ctx, double* out_host, const void* a, const void* b, int prec);
 
 // solver.hip
-void solve(lq_ctx* ctx, double* host_x, const double* host_b, int nrhs, double kappa, double csw,
-           double tol, const lq_solver_params* params, lq_solve_report* report);
+// host_x/host_b (host canonical arrays) or dev_x/dev_b (full-lattice FP64
+// device fields); the unused pair is null.
+void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const void* dev_b,
+           int nrhs, double kappa, double csw, double tol, const lq_solver_params* params,
+           lq_solve_report* report);
 void free_work(lq_ctx* ctx);
 
 inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+// Compulsory bytes per site of one field or table in each precision: a spinor
+// (12 complex; FP16 adds its 4-byte scale), a 12-real compressed link, and
+// the two Hermitian 6x6 clover blocks (72 reals).
+inline double spinor_site_bytes(int prec) {
+  return prec == LQ_F64 ? 192.0 : prec == LQ_F32 ? 96.0 : 52.0;
+}
+inline double link_site_bytes(int prec) { return prec == LQ_F64 ? 96.0 : prec == LQ_F32 ? 48.0 : 24.0; }
+inline double clover_site_bytes(int prec) {
+  return prec == LQ_F64 ? 576.0 : prec == LQ_F32 ? 288.0 : 144.0;
+}
+// One even-odd hopping sweep: 8 links, one input and one output spinor per site.
+inline double dslash_site_bytes(int prec) {
+  return 8 * link_site_bytes(prec) + 2 * spinor_site_bytes(prec);
+}
 
 }  // namespace lq

@@ -1,13 +1,17 @@
-// Single-pass global reductions in FP64.
+// Global reductions in FP64, in two launches.
 //
-// Each workgroup reduces its values with wavefront shuffles (64 lanes) and
-// an LDS step across its waves, writes one partial per value, and takes a
-// ticket from a device counter.  The workgroup that takes the last ticket
-// sums all partials in block order (so the result does not depend on the
-// order in which workgroups finish), runs a caller-supplied finaliser on
-// the totals (for example to form CG's alpha and beta on the device) and
-// resets the counter for the next launch.  The agent-scope fences make the
-// partials written through other XCDs' L2 caches visible to that workgroup.
+// The producing kernel reduces its per-site values inside each workgroup
+// (wavefront shuffles over 64 lanes, then an LDS step across the waves) and
+// writes one partial per value and workgroup.  A one-workgroup finalising
+// kernel then sums the partials in a fixed order (the result does not
+// depend on workgroup scheduling) and runs a caller-supplied finaliser on
+// the totals, for example to form CG's alpha and beta on the device.
+//
+// A single-pass "last workgroup finishes" scheme was measured to halve the
+// bandwidth of the producing kernels on MI355X: making each partial visible
+// across the XCDs' separate L2 caches needs an agent-scope release per
+// workgroup, which writes back the whole L2.  The kernel boundary provides
+// that visibility once per launch instead.
 #pragma once
 
 #include "lq_internal.h"
@@ -15,9 +19,8 @@
 namespace lq {
 
 struct RedBuf {
-  double* part;       // RED_MAX_BLOCKS * RED_NVAL partial sums
-  unsigned* counter;  // ticket counter, zero between launches
-  double* result;     // RED_NVAL totals of the last launch
+  double* part;    // RED_MAX_BLOCKS * RED_NVAL partial sums
+  double* result;  // RED_NVAL totals of the last reduction
 };
 
 inline RedBuf red_buf(lq_ctx* ctx) {
@@ -25,11 +28,10 @@ inline RedBuf red_buf(lq_ctx* ctx) {
   char* b = reinterpret_cast<char*>(ctx->red);
   RedBuf r;
   r.part = reinterpret_cast<double*>(b);
-  r.counter = reinterpret_cast<unsigned*>(b + sizeof(double) * RED_MAX_BLOCKS * RED_NVAL);
-  r.result = reinterpret_cast<double*>(b + sizeof(double) * RED_MAX_BLOCKS * RED_NVAL + 256);
+  r.result = reinterpret_cast<double*>(b + sizeof(double) * RED_MAX_BLOCKS * RED_NVAL);
   return r;
 }
-constexpr size_t RED_BYTES = sizeof(double) * RED_MAX_BLOCKS * RED_NVAL + 256 + 256;
+constexpr size_t RED_BYTES = sizeof(double) * RED_MAX_BLOCKS * RED_NVAL + 256;
 
 template <int N>
 __device__ __forceinline__ void wave_sum(double v[N]) {
@@ -39,7 +41,7 @@ __device__ __forceinline__ void wave_sum(double v[N]) {
     for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
 }
 
-// Sum v over the workgroup; the total is valid in thread 0.
+// Sum v over the workgroup (at most 16 waves); the total is valid in thread 0.
 template <int N>
 __device__ __forceinline__ void block_sum(double v[N], double (*sh)[16]) {
   wave_sum<N>(v);
@@ -58,37 +60,31 @@ __device__ __forceinline__ void block_sum(double v[N], double (*sh)[16]) {
     }
 }
 
-// Every thread of every workgroup must call this (no early return before it).
-// fin(const double* tot) runs once, in thread 0 of the last workgroup.
-template <int N, class Fin>
-__device__ __forceinline__ void reduce_finalize(double v[N], const RedBuf& rb, Fin fin) {
+// Every thread of every workgroup calls this (no early return before it).
+template <int N>
+__device__ __forceinline__ void block_partial(double v[N], double* part) {
   __shared__ double sh[N][16];
-  __shared__ int is_last;
   block_sum<N>(v, sh);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < N; ++k) rb.part[(int64_t)blockIdx.x * N + k] = v[k];
-    __threadfence();
-    const unsigned prev = atomicAdd(rb.counter, 1u);
-    is_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+    for (int k = 0; k < N; ++k) part[(int64_t)blockIdx.x * N + k] = v[k];
+}
+
+// One workgroup: totals of nparts partials, then fin(totals) in thread 0.
+template <int N, class Fin>
+__global__ __launch_bounds__(256) void finalize_kernel(RedBuf rb, int nparts, Fin fin) {
+  __shared__ double sh[N][16];
   double t[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) t[k] = 0.0;
-  // fixed assignment of partials to threads and a fixed tree: deterministic
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x)
 #pragma unroll
-    for (int k = 0; k < N; ++k) t[k] += __builtin_nontemporal_load(&rb.part[(int64_t)b * N + k]);
+    for (int k = 0; k < N; ++k) t[k] += rb.part[(int64_t)b * N + k];
   block_sum<N>(t, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < N; ++k) rb.result[k] = t[k];
     fin(t);
-    __threadfence();
-    *rb.counter = 0u;
   }
 }
 

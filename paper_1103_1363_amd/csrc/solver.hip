@@ -1,7 +1,575 @@
-#include "lq_internal.h"
+// Solvers of M x = b through the even-odd Schur system (include/lq.h).
+//
+// The plain method is CG on the normal equations of Mhat in FP64.  Mixed
+// precision follows the paper's iterative-refinement idea (section 5): the
+// iteration runs with FP32 or FP16 fields while FP64 holds the solution;
+// whenever the inner residual has dropped by a factor delta since the last
+// update (a "reliable update"), the inner correction is added to the FP64
+// solution, the Schur residual is recomputed in FP64 from the operator, and
+// the inner residuals are replaced by it.  The solve ends on the FP64 true
+// residual of the full system, after reconstructing the odd sites.
+//
+// Fallback: a NaN/breakdown in the inner iteration, or five consecutive
+// reliable updates without halving the FP64 residual, hands the solve to
+// the plain FP64 iteration, started from the current FP64 solution.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "solver_kernels.h"
+
 namespace lq {
-void solve(lq_ctx*, double*, const double*, int, double, double, double, const lq_solver_params*, lq_solve_report*) {
-  throw Error(LQ_EINVAL, "not built yet");
+
+struct Work {
+  int64_t nblk = 0;
+  // FP64 fields
+  void* b_own = nullptr;   // full-lattice buffers for host-array solves
+  void* x_own = nullptr;
+  void* b = nullptr;       // current right-hand side: even half then odd half (FP64)
+  void* x = nullptr;       // current solution (FP64, full lattice)
+  void* bhat = nullptr;    // even
+  void* r64 = nullptr;     // even: bhat - Mhat x
+  void* rn64 = nullptr;    // even: Mhat^+ r64
+  void* te = nullptr;      // even scratch
+  void* to = nullptr;      // odd scratch
+  void* to2 = nullptr;     // odd scratch
+  // inner-iteration fields per inner precision (index = operator precision)
+  void* p[3] = {nullptr, nullptr, nullptr};
+  void* q[3] = {nullptr, nullptr, nullptr};
+  void* t[3] = {nullptr, nullptr, nullptr};
+  void* xl[3] = {nullptr, nullptr, nullptr};  // vector precision: F64 for F64, F32 otherwise
+  void* r[3] = {nullptr, nullptr, nullptr};
+  void* rt[3] = {nullptr, nullptr, nullptr};
+  CGState* st = nullptr;       // device
+  CGState* st_host = nullptr;  // pinned
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
+  int graph_iters[3] = {0, 0, 0};
+  double graph_k2[3] = {0, 0, 0};
+};
+
+namespace {
+
+void* dalloc(size_t bytes) {
+  void* p = nullptr;
+  LQ_HIP(hipMalloc(&p, bytes));
+  return p;
 }
-void free_work(lq_ctx*) {}
+
+int vec_prec(int op_prec) { return op_prec == LQ_F64 ? LQ_F64 : LQ_F32; }
+
+Work* work(lq_ctx* ctx, int inner) {
+  if (!ctx->work) {
+    Work* w = new Work();
+    ctx->work = w;
+    w->nblk = ctx->geo.nblk;
+    const size_t f64 = parity_field_bytes(w->nblk, LQ_F64);
+    w->b_own = dalloc(2 * f64);
+    w->x_own = dalloc(2 * f64);
+    w->bhat = dalloc(f64);
+    w->r64 = dalloc(f64);
+    w->rn64 = dalloc(f64);
+    w->te = dalloc(f64);
+    w->to = dalloc(f64);
+    w->to2 = dalloc(f64);
+    w->st = reinterpret_cast<CGState*>(dalloc(sizeof(CGState)));
+    LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->st_host), sizeof(CGState), hipHostMallocDefault));
+  }
+  Work* w = ctx->work;
+  if (!w->p[inner]) {
+    const size_t fo = parity_field_bytes(w->nblk, inner);
+    const size_t fv = parity_field_bytes(w->nblk, vec_prec(inner));
+    w->p[inner] = dalloc(fo);
+    w->q[inner] = dalloc(fo);
+    w->t[inner] = dalloc(fo);
+    w->xl[inner] = dalloc(fv);
+    w->r[inner] = dalloc(fv);
+    w->rt[inner] = dalloc(fv);
+  }
+  return w;
 }
+
+template <class P>
+Field<P> F(void* p, int64_t nblk) {
+  return field_at<P>(p, nblk);
+}
+
+char* odd_half(void* full, int64_t nblk) {
+  return reinterpret_cast<char*>(full) + parity_field_bytes(nblk, LQ_F64);
+}
+
+template <class PX, class PY, class PO>
+void axpby(lq_ctx* ctx, void* out, double a, const void* x, double b, const void* y) {
+  const Geo& g = ctx->geo;
+  ctx->bytes += (double)g.vh * (spinor_site_bytes(PX::id) + spinor_site_bytes(PY::id) +
+                                spinor_site_bytes(PO::id));
+  hipLaunchKernelGGL((axpby_kernel<PX, PY, PO>), dim3(grid_for(g.vh, SBLK)), dim3(SBLK), 0,
+                     ctx->cur, g, F<PO>(out, g.nblk), a, F<PX>(const_cast<void*>(x), g.nblk), b,
+                     F<PY>(const_cast<void*>(y), g.nblk));
+  LQ_HIP(hipGetLastError());
+}
+void axpby64(lq_ctx* ctx, void* out, double a, const void* x, double b, const void* y) {
+  axpby<P64, P64, P64>(ctx, out, a, x, b, y);
+}
+
+template <class PO>
+void zero(lq_ctx* ctx, void* out) {
+  const Geo& g = ctx->geo;
+  ctx->bytes += (double)g.vh * spinor_site_bytes(PO::id);
+  hipLaunchKernelGGL(zero_kernel<PO>, dim3(grid_for(g.vh, SBLK)), dim3(SBLK), 0, ctx->cur, g,
+                     F<PO>(out, g.nblk));
+  LQ_HIP(hipGetLastError());
+}
+
+double nrm2(lq_ctx* ctx, const void* a) {
+  double v = 0;
+  norm2(ctx, &v, a, LQ_F64);
+  return v;
+}
+
+// ------------------------------------------------------------ CG iteration
+// Algorithmic bytes per site of each kernel of one iteration (operator
+// precision po, vector precision pv).
+void iteration_site_bytes(int po, int pv, double out[LQ_NK]) {
+  const double L = link_site_bytes(po), S = spinor_site_bytes(po), C = clover_site_bytes(po);
+  const double Sv = spinor_site_bytes(pv);
+  out[LQ_K_HOP_OE] = 8 * L + 2 * S + C;
+  out[LQ_K_HOP_EO] = 8 * L + 3 * S + C;
+  out[LQ_K_HOPD_OE] = 8 * L + 2 * S + C;
+  out[LQ_K_UPDATE] = 8 * L + 3 * S + C + 6 * Sv;
+  out[LQ_K_PUPDATE] = Sv + 2 * S;
+}
+
+// Per-kernel HIP-event timing of the iteration kernels (profile mode).
+struct Prof {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double ms[LQ_NK] = {0, 0, 0, 0, 0};
+  int calls[LQ_NK] = {0, 0, 0, 0, 0};
+  hipStream_t s = nullptr;
+  void begin() { LQ_HIP(hipEventRecord(e0, s)); }
+  void end(int k) {
+    LQ_HIP(hipEventRecord(e1, s));
+    LQ_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    LQ_HIP(hipEventElapsedTime(&t, e0, e1));
+    ms[k] += t;
+    calls[k] += 1;
+  }
+};
+
+template <class PO, class PV>
+void launch_iteration(lq_ctx* ctx, Work* w, int ip, double k2d, Prof* pf = nullptr) {
+  const Geo& g = ctx->geo;
+  const int64_t nb = g.nblk;
+  const dim3 grid(grid_for(g.vh, SBLK)), blk(SBLK);
+  using S = typename PO::S;
+  const S* gp = reinterpret_cast<const S*>(ctx->gauge[PO::id]);
+  const S* ai = reinterpret_cast<const S*>(ctx->clov.ainv_oo[PO::id]);
+  const S* ae = reinterpret_cast<const S*>(ctx->clov.a_ee[PO::id]);
+  const typename PO::R k2 = (typename PO::R)k2d;
+  RedBuf rb = red_buf(ctx);
+  Field<PO> p = F<PO>(w->p[ip], nb), q = F<PO>(w->q[ip], nb), t = F<PO>(w->t[ip], nb);
+  Field<PV> x = F<PV>(w->xl[ip], nb), r = F<PV>(w->r[ip], nb), rt = F<PV>(w->rt[ip], nb);
+  if (pf) pf->begin();
+  hipLaunchKernelGGL((cg_k1<PO, false>), grid, blk, 0, ctx->cur, g, w->st, t, p, gp, ai);
+  if (pf) pf->end(LQ_K_HOP_OE), pf->begin();
+  hipLaunchKernelGGL((cg_k2<PO>), grid, blk, 0, ctx->cur, g, w->st, q, t, p, gp, ae, k2, rb);
+  if (pf) pf->end(LQ_K_HOP_EO);
+  hipLaunchKernelGGL((finalize_kernel<1, FinAlpha>), dim3(1), dim3(256), 0, ctx->cur, rb,
+                     (int)grid.x, FinAlpha{w->st});
+  if (pf) pf->begin();
+  hipLaunchKernelGGL((cg_k1<PO, true>), grid, blk, 0, ctx->cur, g, w->st, t, q, gp, ai);
+  if (pf) pf->end(LQ_K_HOPD_OE), pf->begin();
+  hipLaunchKernelGGL((cg_k4<PO, PV>), grid, blk, 0, ctx->cur, g, w->st, t, q, p, x, r, rt, gp,
+                     ae, k2, rb);
+  if (pf) pf->end(LQ_K_UPDATE);
+  hipLaunchKernelGGL((finalize_kernel<2, FinBeta>), dim3(1), dim3(256), 0, ctx->cur, rb,
+                     (int)grid.x, FinBeta{w->st});
+  if (pf) pf->begin();
+  hipLaunchKernelGGL((cg_k5<PO, PV>), grid, blk, 0, ctx->cur, g, w->st, p, r);
+  if (pf) pf->end(LQ_K_PUPDATE);
+  LQ_HIP(hipGetLastError());
+}
+
+template <class PO, class PV>
+void run_iterations(lq_ctx* ctx, Work* w, int ip, double k2, int n, bool use_graph,
+                    Prof* pf) {
+  if (pf) {
+    // one iteration at a time, so that no timed launch is a no-op
+    launch_iteration<PO, PV>(ctx, w, ip, k2, pf);
+    return;
+  }
+  if (!use_graph) {
+    for (int i = 0; i < n; ++i) launch_iteration<PO, PV>(ctx, w, ip, k2);
+    return;
+  }
+  if (!w->graph[ip] || w->graph_iters[ip] != n || w->graph_k2[ip] != k2) {
+    if (w->graph[ip]) {
+      (void)hipGraphExecDestroy(w->graph[ip]);
+      w->graph[ip] = nullptr;
+    }
+    hipGraph_t gr = nullptr;
+    LQ_HIP(hipStreamBeginCapture(ctx->cur, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int i = 0; i < n; ++i) launch_iteration<PO, PV>(ctx, w, ip, k2);
+    } catch (...) {
+      (void)hipStreamEndCapture(ctx->cur, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      throw;
+    }
+    LQ_HIP(hipStreamEndCapture(ctx->cur, &gr));
+    hipError_t e = hipGraphInstantiate(&w->graph[ip], gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    LQ_HIP(e);
+    w->graph_iters[ip] = n;
+    w->graph_k2[ip] = k2;
+  }
+  LQ_HIP(hipGraphLaunch(w->graph[ip], ctx->cur));
+}
+
+struct SolveStats {
+  int iterations = 0;
+  int reliable = 0;
+  int fallback = 0;
+  int dslash = 0;
+};
+
+// Schur residual r64 = bhat - Mhat x_e (FP64); returns |r64|^2.
+double schur_residual(lq_ctx* ctx, Work* w, SolveStats& ss) {
+  schur(ctx, w->te, w->x, w->to, 0, LQ_F64);
+  axpby64(ctx, w->r64, 1.0, w->bhat, -1.0, w->te);
+  ss.dslash += 2;
+  return nrm2(ctx, w->r64);
+}
+
+template <class PO, class PV>
+void load_inner_state(lq_ctx* ctx, Work* w, int ip, double rn2_64, bool restart_p, double beta) {
+  // r = rn64, rt = r64 (cast to inner precision); p = r (+ beta p)
+  axpby<P64, P64, PV>(ctx, w->r[ip], 1.0, w->rn64, 0.0, w->rn64);
+  axpby<P64, P64, PV>(ctx, w->rt[ip], 1.0, w->r64, 0.0, w->r64);
+  if (restart_p)
+    axpby<PV, PV, PO>(ctx, w->p[ip], 1.0, w->r[ip], 0.0, w->r[ip]);
+  else
+    axpby<PV, PO, PO>(ctx, w->p[ip], 1.0, w->r[ip], beta, w->p[ip]);
+  (void)rn2_64;
+}
+
+// Returns true when the Schur residual reached target; x (even half) updated.
+template <class PO, class PV>
+bool cg_normal(lq_ctx* ctx, Work* w, double target, double delta, int maxiter, int check_every,
+               bool use_graph, int fault_inject, SolveStats& ss, bool& want_fallback,
+               Prof* pf) {
+  const int ip = PO::id;
+  double kb[LQ_NK];
+  iteration_site_bytes(PO::id, PV::id, kb);
+  const double iter_bytes = (double)ctx->geo.vh * (kb[0] + kb[1] + kb[2] + kb[3] + kb[4]);
+  const double last_bytes = (double)ctx->geo.vh * kb[LQ_K_PUPDATE];
+  const double k2 = ctx->clov.kappa * ctx->clov.kappa;
+  const double target2 = target * target;
+  want_fallback = false;
+  double rt2 = schur_residual(ctx, w, ss);
+  if (rt2 <= target2) return true;
+  schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
+  ss.dslash += 2;
+  double rr = nrm2(ctx, w->rn64);
+  zero<PV>(ctx, w->xl[ip]);
+  load_inner_state<PO, PV>(ctx, w, ip, rr, true, 0.0);
+  CGState& h = *w->st_host;
+  std::memset(&h, 0, sizeof(CGState));
+  h.rr = rr;
+  h.rt2 = rt2;
+  h.rt2_max = rt2;
+  h.target2 = target2;
+  h.delta2 = delta * delta;
+  h.active = 1;
+  h.reason = R_RUN;
+  h.iter = 0;
+  h.maxiter = maxiter;
+  LQ_HIP(hipMemcpyAsync(w->st, &h, sizeof(CGState), hipMemcpyHostToDevice, ctx->cur));
+  double best_hist[6];
+  int nhist = 0;
+  // iteration-level stagnation: the inner residual must halve every
+  // STALL_ITERS iterations, otherwise a mixed-precision solve falls back
+  constexpr int STALL_ITERS = 200;
+  int ref_iter = 0;
+  double ref_rt2 = rt2;
+  int counted = 0;
+  for (;;) {
+    run_iterations<PO, PV>(ctx, w, ip, k2, check_every, use_graph, pf);
+    LQ_HIP(hipMemcpyAsync(&h, w->st, sizeof(CGState), hipMemcpyDeviceToHost, ctx->cur));
+    LQ_HIP(hipStreamSynchronize(ctx->cur));
+    // count the iterations that ran (the stopping one skips the p update)
+    ctx->bytes += (h.iter - counted) * iter_bytes - (h.active ? 0.0 : last_bytes);
+    counted = h.iter;
+    if (h.active) {
+      if (h.rt2 <= 0.25 * ref_rt2) {
+        ref_iter = h.iter;
+        ref_rt2 = h.rt2;
+      } else if (PO::id != LQ_F64 && h.iter - ref_iter >= STALL_ITERS) {
+        ss.iterations = h.iter;
+        if (!fault_inject) axpby<P64, PV, P64>(ctx, w->x, 1.0, w->x, 1.0, w->xl[ip]);
+        want_fallback = true;
+        return false;
+      }
+      continue;
+    }
+    ss.iterations = h.iter;
+    if (h.reason == R_NAN) {
+      if (PO::id != LQ_F64) {
+        want_fallback = true;
+        return false;
+      }
+      throw Error(LQ_ENAN, "NaN or breakdown in the FP64 CG iteration");
+    }
+    // fold the inner correction into the FP64 solution
+    if (!fault_inject) axpby<P64, PV, P64>(ctx, w->x, 1.0, w->x, 1.0, w->xl[ip]);
+    zero<PV>(ctx, w->xl[ip]);
+    rt2 = schur_residual(ctx, w, ss);
+    ss.reliable += 1;
+    if (!std::isfinite(rt2)) {
+      if (PO::id != LQ_F64) {
+        want_fallback = true;
+        return false;
+      }
+      throw Error(LQ_ENAN, "NaN in the FP64 residual");
+    }
+    if (rt2 <= target2) return true;
+    if (h.reason == R_MAXITER || h.iter >= maxiter) return false;
+    // stagnation: five updates without halving the FP64 residual norm
+    if (nhist < 6) {
+      best_hist[nhist++] = rt2;
+    } else {
+      for (int i = 0; i < 5; ++i) best_hist[i] = best_hist[i + 1];
+      best_hist[5] = rt2;
+    }
+    if (PO::id != LQ_F64 && nhist == 6) {
+      double recent = best_hist[1];
+      for (int i = 2; i < 6; ++i) recent = std::fmin(recent, best_hist[i]);
+      if (recent > 0.25 * best_hist[0]) {
+        want_fallback = true;
+        return false;
+      }
+    }
+    schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
+    ss.dslash += 2;
+    const double rr_new = nrm2(ctx, w->rn64);
+    // The iteration that triggered the update computed x, r and
+    // beta = |r_k+1|^2 / |r_k|^2 but not p_k+1.  p continues as
+    // r_new + (|r_new|^2 / |r_k|^2) p_k, with |r_k|^2 = h.rr / h.beta.
+    const double beta = (h.rr > 0.0 && h.beta > 0.0) ? h.beta * rr_new / h.rr : 0.0;
+    load_inner_state<PO, PV>(ctx, w, ip, rr_new, false, beta);
+    h.rr = rr_new;
+    h.rt2 = rt2;
+    h.rt2_max = rt2;
+    h.active = 1;
+    h.reason = R_RUN;
+    if (rt2 <= 0.25 * ref_rt2) {
+      ref_iter = h.iter;
+      ref_rt2 = rt2;
+    }
+    LQ_HIP(hipMemcpyAsync(w->st, &h, sizeof(CGState), hipMemcpyHostToDevice, ctx->cur));
+  }
+}
+
+bool run_cg(lq_ctx* ctx, Work* w, int inner, double target, double delta, int maxiter,
+            int check_every, bool use_graph, int fault_inject, SolveStats& ss, bool& fb,
+            Prof* pf) {
+  switch (inner) {
+    case LQ_F64:
+      return cg_normal<P64, P64>(ctx, w, target, delta, maxiter, check_every, use_graph, 0, ss, fb,
+                                 pf);
+    case LQ_F32:
+      return cg_normal<P32, P32>(ctx, w, target, delta, maxiter, check_every, use_graph,
+                                 fault_inject, ss, fb, pf);
+    default:
+      return cg_normal<P16, P32>(ctx, w, target, delta, maxiter, check_every, use_graph,
+                                 fault_inject, ss, fb, pf);
+  }
+}
+
+// x_o = A_oo^-1 (b_o + kappa H_oe x_e); returns |b - M x|^2 over both parities.
+double reconstruct_and_residual(lq_ctx* ctx, Work* w, SolveStats& ss) {
+  const int64_t nb = ctx->geo.nblk;
+  const double kappa = ctx->clov.kappa;
+  void* be = w->b;
+  void* bo = odd_half(w->b, nb);
+  void* xe = w->x;
+  void* xo = odd_half(w->x, nb);
+  dslash(ctx, w->to, xe, LQ_ODD, 0, LQ_F64);
+  axpby64(ctx, w->to, 1.0, bo, kappa, w->to);
+  clover_apply(ctx, xo, w->to, LQ_ODD, 1, LQ_F64);
+  // r_e = b_e - A_ee x_e + kappa H_eo x_o
+  clover_apply(ctx, w->te, xe, LQ_EVEN, 0, LQ_F64);
+  axpby64(ctx, w->te, 1.0, be, -1.0, w->te);
+  dslash(ctx, w->r64, xo, LQ_EVEN, 0, LQ_F64);
+  axpby64(ctx, w->te, 1.0, w->te, kappa, w->r64);
+  const double re = nrm2(ctx, w->te);
+  // r_o = b_o - A_oo x_o + kappa H_oe x_e
+  clover_apply(ctx, w->to, xo, LQ_ODD, 0, LQ_F64);
+  axpby64(ctx, w->to, 1.0, bo, -1.0, w->to);
+  dslash(ctx, w->to2, xe, LQ_ODD, 0, LQ_F64);
+  axpby64(ctx, w->to, 1.0, w->to, kappa, w->to2);
+  const double ro = nrm2(ctx, w->to);
+  ss.dslash += 3;
+  return re + ro;
+}
+
+}  // namespace
+
+void free_work(lq_ctx* ctx) {
+  Work* w = ctx->work;
+  if (!w) return;
+  for (void* p : {w->b_own, w->x_own, w->bhat, w->r64, w->rn64, w->te, w->to, w->to2})
+    if (p) (void)hipFree(p);
+  for (int i = 0; i < 3; ++i) {
+    for (void* p : {w->p[i], w->q[i], w->t[i], w->xl[i], w->r[i], w->rt[i]})
+      if (p) (void)hipFree(p);
+    if (w->graph[i]) (void)hipGraphExecDestroy(w->graph[i]);
+  }
+  if (w->st) (void)hipFree(w->st);
+  if (w->st_host) (void)hipHostFree(w->st_host);
+  delete w;
+  ctx->work = nullptr;
+}
+
+void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const void* dev_b,
+           int nrhs, double kappa, double csw, double tol, const lq_solver_params* prm,
+           lq_solve_report* report) {
+  lq_solver_params p{};
+  if (prm) p = *prm;
+  const int inner = p.inner_prec;
+  LQ_CHECK(inner == LQ_F64 || inner == LQ_F32 || inner == LQ_F16, LQ_EINVAL,
+           "bad inner precision");
+  LQ_CHECK(p.solver == LQ_CGNR, LQ_EINVAL, "this solver kind is not available in this build");
+  const int maxiter = p.maxiter > 0 ? p.maxiter : 20000;
+  const double delta = inner == LQ_F64 ? 0.0 : (p.delta > 0.0 ? p.delta : 0.1);
+  const int check_every = p.check_every > 0 ? p.check_every : 8;
+  const bool use_graph = p.use_graph >= 0;
+  // everything below runs on the library stream, after the caller's work
+  if (ctx->stream) LQ_HIP(hipStreamSynchronize(ctx->stream));
+  else LQ_HIP(hipDeviceSynchronize());
+  ctx->cur = ctx->sstream;
+  if (!ctx->clov.valid || ctx->clov.kappa != kappa || ctx->clov.csw != csw)
+    build_clover(ctx, kappa, csw);
+  Work* w = work(ctx, inner);
+  work(ctx, LQ_F64);
+  const int64_t nsite = ctx->V;
+  const size_t hb = (size_t)nsite * 12 * 16;
+  lq_status worst = LQ_OK;
+  Prof prof_obj;
+  Prof* prof = nullptr;
+  if (p.profile) {
+    prof_obj.s = ctx->cur;
+    LQ_HIP(hipEventCreate(&prof_obj.e0));
+    LQ_HIP(hipEventCreate(&prof_obj.e1));
+    prof = &prof_obj;
+  }
+  struct EvGuard {
+    Prof* p;
+    ~EvGuard() {
+      if (p) {
+        (void)hipEventDestroy(p->e0);
+        (void)hipEventDestroy(p->e1);
+      }
+    }
+  } ev_guard{prof};
+  double kb[LQ_NK];
+  iteration_site_bytes(inner, vec_prec(inner), kb);
+  std::string msg;
+  for (int rhs = 0; rhs < nrhs; ++rhs) {
+    auto t0 = std::chrono::steady_clock::now();
+    SolveStats ss;
+    const double bytes0 = ctx->bytes;
+    if (prof)
+      for (int k = 0; k < LQ_NK; ++k) prof->ms[k] = 0.0, prof->calls[k] = 0;
+    const int64_t nb = ctx->geo.nblk;
+    const size_t fb = 2 * parity_field_bytes(nb, LQ_F64);
+    if (host_b) {
+      w->b = w->b_own;
+      w->x = w->x_own;
+      double2* stg = reinterpret_cast<double2*>(staging(ctx, hb));
+      LQ_HIP(hipMemcpyAsync(stg, host_b + (size_t)rhs * nsite * 24, hb, hipMemcpyHostToDevice,
+                            ctx->cur));
+      pack_spinor(ctx, w->b, stg, LQ_F64, nsite, 1);
+    } else {
+      w->b = const_cast<char*>(reinterpret_cast<const char*>(dev_b)) + rhs * fb;
+      w->x = reinterpret_cast<char*>(dev_x) + rhs * fb;
+    }
+    const double b2 = nrm2(ctx, w->b) + nrm2(ctx, odd_half(w->b, nb));
+    // bhat = b_e + kappa H_eo A_oo^-1 b_o
+    clover_apply(ctx, w->to, odd_half(w->b, nb), LQ_ODD, 1, LQ_F64);
+    dslash(ctx, w->te, w->to, LQ_EVEN, 0, LQ_F64);
+    axpby64(ctx, w->bhat, 1.0, w->b, kappa, w->te);
+    ss.dslash += 1;
+    const double bhat_norm = std::sqrt(nrm2(ctx, w->bhat));
+    zero<P64>(ctx, w->x);
+    zero<P64>(ctx, odd_half(w->x, nb));
+    double res2 = 0.0;
+    bool ok = false;
+    double frac = 0.5;
+    lq_status st = LQ_OK;
+    if (b2 == 0.0) {
+      ok = true;
+    } else {
+      for (int round = 0; round < 4 && !ok; ++round) {
+        bool fb = false;
+        int left = maxiter - ss.iterations;
+        SolveStats inner_ss;
+        bool conv = run_cg(ctx, w, ss.fallback ? LQ_F64 : inner, frac * tol * bhat_norm,
+                           ss.fallback ? 0.0 : delta, left, check_every, use_graph,
+                           p.fault_inject, inner_ss, fb, prof);
+        ss.iterations += inner_ss.iterations;
+        ss.reliable += inner_ss.reliable;
+        ss.dslash += inner_ss.dslash + 4 * inner_ss.iterations;
+        if (fb) {
+          ss.fallback = 1;
+          work(ctx, LQ_F64);
+          SolveStats f_ss;
+          left = maxiter - ss.iterations;
+          conv = run_cg(ctx, w, LQ_F64, frac * tol * bhat_norm, 0.0, left, check_every,
+                        use_graph, 0, f_ss, fb, prof);
+          ss.iterations += f_ss.iterations;
+          ss.reliable += f_ss.reliable;
+          ss.dslash += f_ss.dslash + 4 * f_ss.iterations;
+        }
+        res2 = reconstruct_and_residual(ctx, w, ss);
+        ok = res2 <= tol * tol * b2;
+        if (!conv && !ok) break;
+        frac *= 0.5;
+      }
+      if (!ok) st = LQ_ENOCONV;
+    }
+    // result to host
+    if (host_x) {
+      double2* stg = reinterpret_cast<double2*>(staging(ctx, hb));
+      unpack_spinor(ctx, stg, w->x, LQ_F64, 1);
+      LQ_HIP(hipMemcpyAsync(host_x + (size_t)rhs * nsite * 24, stg, hb, hipMemcpyDeviceToHost,
+                            ctx->cur));
+    }
+    const double schur2 = b2 == 0.0 ? 0.0 : schur_residual(ctx, w, ss);
+    LQ_HIP(hipStreamSynchronize(ctx->cur));
+    auto t1 = std::chrono::steady_clock::now();
+    if (report) {
+      lq_solve_report& r = report[rhs];
+      r.iterations = ss.iterations;
+      r.reliable_updates = ss.reliable;
+      r.fallback = ss.fallback;
+      r.dslash_calls = ss.dslash;
+      r.true_residual = b2 > 0.0 ? std::sqrt(res2 / b2) : 0.0;
+      r.schur_residual = bhat_norm > 0.0 ? std::sqrt(schur2) / bhat_norm : 0.0;
+      r.seconds = std::chrono::duration<double>(t1 - t0).count();
+      r.bytes = ctx->bytes - bytes0;
+      for (int k = 0; k < LQ_NK; ++k) {
+        r.kernel_bytes[k] = kb[k] * (double)ctx->geo.vh;
+        r.kernel_ms[k] = prof ? prof->ms[k] : 0.0;
+        r.kernel_calls[k] = prof ? prof->calls[k] : 0;
+      }
+    }
+    if (st != LQ_OK && worst == LQ_OK) {
+      worst = st;
+      msg = "right-hand side " + std::to_string(rhs) + " did not reach the tolerance";
+    }
+  }
+  if (worst != LQ_OK) throw Error(worst, msg);
+}
+
+}  // namespace lq

@@ -33,17 +33,23 @@ class LQError(RuntimeError):
 class SolverParams(ct.Structure):
     _fields_ = [("solver", ct.c_int), ("inner_prec", ct.c_int), ("maxiter", ct.c_int),
                 ("delta", ct.c_double), ("restart", ct.c_int), ("check_every", ct.c_int),
-                ("use_graph", ct.c_int), ("fault_inject", ct.c_int)]
+                ("use_graph", ct.c_int), ("fault_inject", ct.c_int), ("profile", ct.c_int)]
 
 
 class SolveReport(ct.Structure):
     _fields_ = [("iterations", ct.c_int), ("reliable_updates", ct.c_int),
                 ("fallback", ct.c_int), ("dslash_calls", ct.c_int),
                 ("true_residual", ct.c_double), ("schur_residual", ct.c_double),
-                ("seconds", ct.c_double)]
+                ("seconds", ct.c_double), ("bytes", ct.c_double),
+                ("kernel_ms", ct.c_double * 5), ("kernel_bytes", ct.c_double * 5),
+                ("kernel_calls", ct.c_int * 5)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if hasattr(v, "__len__") else v
+        return d
 
 
 _lib = None
@@ -82,9 +88,11 @@ def lib():
         L.lq_dot.argtypes = [vp, dp, vp, vp, ip, ip]
         L.lq_solve.argtypes = [vp, dp, dp, ip, ct.c_double, ct.c_double, ct.c_double,
                                ct.POINTER(SolverParams), ct.POINTER(SolveReport)]
+        L.lq_solve_device.argtypes = [vp, vp, vp, ip, ct.c_double, ct.c_double, ct.c_double,
+                                      ct.POINTER(SolverParams), ct.POINTER(SolveReport)]
         for name in ("lq_upload_gauge", "lq_set_clover", "lq_spinor_to_device",
                      "lq_spinor_to_host", "lq_dslash", "lq_clover_apply", "lq_schur",
-                     "lq_norm2", "lq_dot", "lq_solve"):
+                     "lq_norm2", "lq_dot", "lq_solve", "lq_solve_device"):
             getattr(L, name).restype = ip
         _lib = L
     return _lib
@@ -113,6 +121,10 @@ class Report:
     true_residual: float
     schur_residual: float
     seconds: float
+    bytes: float
+    kernel_ms: list
+    kernel_bytes: list
+    kernel_calls: list
 
 
 class Lattice:
@@ -212,14 +224,14 @@ class Lattice:
     # -- solver ---------------------------------------------------------
     def solve(self, b, kappa, csw, tol=1e-10, solver=CGNR, inner_prec=F64, maxiter=0,
               delta=0.0, restart=0, check_every=0, use_graph=0, fault_inject=0,
-              raise_on_noconv=True):
+              profile=0, raise_on_noconv=True):
         """Solve M x = b on the full lattice; b has shape (nrhs?, V-sites..., 4, 3)."""
         b = np.ascontiguousarray(b, dtype=np.complex128)
         nrhs = b.size // (self.volume * 12)
         assert nrhs * self.volume * 12 == b.size
         x = np.zeros_like(b)
         p = SolverParams(solver, inner_prec, maxiter, delta, restart, check_every, use_graph,
-                         fault_inject)
+                         fault_inject, profile)
         reps = (SolveReport * nrhs)()
         rc = self._L.lq_solve(self._h, _dptr(x.view(np.float64)), _dptr(b.view(np.float64)),
                               nrhs, float(kappa), float(csw), float(tol), ct.byref(p), reps)
@@ -227,3 +239,18 @@ class Lattice:
         if rc != 0 and (rc != -4 or raise_on_noconv):
             self._check(rc)
         return x, reports
+
+    def solve_device(self, dev_x, dev_b, kappa, csw, tol=1e-10, nrhs=1, solver=CGNR,
+                     inner_prec=F64, maxiter=0, delta=0.0, restart=0, check_every=0,
+                     use_graph=0, fault_inject=0, profile=0, raise_on_noconv=True):
+        """Solve with device-resident full-lattice FP64 fields (see lq_solve_device)."""
+        p = SolverParams(solver, inner_prec, maxiter, delta, restart, check_every, use_graph,
+                         fault_inject, profile)
+        reps = (SolveReport * nrhs)()
+        rc = self._L.lq_solve_device(self._h, ct.c_void_p(dev_x.data_ptr()),
+                                     ct.c_void_p(dev_b.data_ptr()), nrhs, float(kappa),
+                                     float(csw), float(tol), ct.byref(p), reps)
+        reports = [Report(**r.as_dict()) for r in reps]
+        if rc != 0 and (rc != -4 or raise_on_noconv):
+            self._check(rc)
+        return reports

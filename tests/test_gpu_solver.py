@@ -1,0 +1,123 @@
+"""GPU solves of M x = b (through lq_solve) checked by the FP64 oracle: the
+true residual is recomputed with the oracle's own operator, and on small
+lattices the solution is compared with a direct sparse LU solve of the
+brute-force matrix."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from gen import fields
+from oracle import dirac, evenodd
+from tests import bruteforce
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lq():
+    from paper_1103_1363_amd import lq as _lq
+    return _lq
+
+
+def oracle_residual(u, kappa, csw, x, b):
+    wc = evenodd.WilsonClover(u, kappa, csw)
+    return dirac.norm(b - wc.M(x.reshape(b.shape))) / dirac.norm(b)
+
+
+def direct(u, dims, kappa, csw, b):
+    wc = evenodd.WilsonClover(u, kappa, csw)
+    h = bruteforce.hopping_matrix(u, dims)
+    a = bruteforce.clover_block_matrix(wc.a.reshape(-1, 12, 12))
+    return spla.spsolve((a - kappa * h).tocsc(), b.reshape(-1))
+
+
+@pytest.mark.parametrize("inner", [0, 1, 2])
+def test_config0_wilson_haar_4x4(lq, inner):
+    """4^4, Wilson (csw = 0), kappa = 0.12, Haar links, Gaussian source."""
+    dims, kappa, csw = (4, 4, 4, 4), 0.12, 0.0
+    say(f"solve 4^4 wilson inner={inner}")
+    u = fields.gauge_field(dims, "haar", fields.SEED_GAUGE)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x, rep = lat.solve(b, kappa, csw, 1e-10, inner_prec=inner)
+    res = oracle_residual(u, kappa, csw, x, b)
+    assert res <= 1e-10, (res, rep)
+    assert abs(rep[0].true_residual - res) <= 0.1 * res + 1e-14
+    xr = direct(u, dims, kappa, csw, b)
+    err = np.linalg.norm(x.reshape(-1) - xr) / np.linalg.norm(xr)
+    assert err <= 4 * 1e-10 * 4, err  # cond(M) ~ 4 at this kappa
+
+
+@pytest.mark.parametrize("dims", [(10, 6, 4, 6), (8, 8, 8, 8)])
+@pytest.mark.parametrize("inner", [0, 1, 2])
+def test_clover_smooth_solves(lq, dims, inner):
+    kappa, csw = 0.135, 1.0
+    say(f"solve clover dims={dims} inner={inner}")
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 1)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 1)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x, rep = lat.solve(b, kappa, csw, 1e-10, inner_prec=inner)
+    res = oracle_residual(u, kappa, csw, x, b)
+    assert res <= 1e-10, (res, rep)
+    if inner > 0:
+        assert rep[0].reliable_updates >= 1
+
+
+def test_graph_and_direct_launch_agree(lq):
+    dims, kappa, csw = (8, 4, 4, 8), 0.13, 1.0
+    say("solve graph vs direct launches")
+    u = fields.gauge_field(dims, "smooth", 7)
+    b = fields.gaussian_spinor(dims, 8)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x1, r1 = lat.solve(b, kappa, csw, 1e-10, use_graph=0)
+    x2, r2 = lat.solve(b, kappa, csw, 1e-10, use_graph=-1)
+    assert r1[0].iterations == r2[0].iterations
+    assert np.array_equal(x1, x2)
+
+
+def test_fault_injection_falls_back_to_fp64(lq):
+    dims, kappa, csw = (8, 8, 8, 8), 0.135, 1.0
+    say("solve with forced stagnation of the mixed-precision inner solve")
+    u = fields.gauge_field(dims, "smooth", 9)
+    b = fields.gaussian_spinor(dims, 10)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x, rep = lat.solve(b, kappa, csw, 1e-10, inner_prec=1, fault_inject=1,
+                       raise_on_noconv=False)
+    say(f"report {rep[0]}")
+    assert rep[0].fallback == 1
+    assert oracle_residual(u, kappa, csw, x, b) <= 1e-10
+
+
+def test_multiple_rhs_and_zero_source(lq):
+    dims, kappa, csw = (4, 4, 4, 8), 0.13, 1.0
+    say("solve two right-hand sides, one of them zero")
+    u = fields.gauge_field(dims, "smooth", 11)
+    b = np.stack([fields.gaussian_spinor(dims, 12), np.zeros(u.shape[:4] + (4, 3))])
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x, rep = lat.solve(b, kappa, csw, 1e-10, inner_prec=1)
+    assert oracle_residual(u, kappa, csw, x[0], b[0]) <= 1e-10
+    assert np.all(x[1] == 0)
+
+
+def test_config1_mixed_fp32_16x32(lq):
+    """16^3x32 even-odd Wilson-clover, kappa = 0.135, csw = 1, smooth links,
+    FP32 inner CG with FP64 reliable updates, against plain FP64 CG."""
+    dims, kappa, csw = (16, 16, 16, 32), 0.135, 1.0
+    say("solve 16^3x32 mixed fp32 vs plain fp64")
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 1)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 1)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x64, r64 = lat.solve(b, kappa, csw, 1e-10, inner_prec=0)
+    x32, r32 = lat.solve(b, kappa, csw, 1e-10, inner_prec=1)
+    for x in (x64, x32):
+        assert oracle_residual(u, kappa, csw, x, b) <= 1e-10
+    err = np.linalg.norm((x32 - x64).reshape(-1)) / np.linalg.norm(x64.reshape(-1))
+    say(f"fp64 {r64[0]}\nfp32 {r32[0]}\nmixed vs plain relative difference {err:.2e}")
+    assert err <= 1e-8
