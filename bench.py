@@ -4,8 +4,9 @@
 One step = one complete solve of M x = b to a 1e-10 FP64 true residual on
 the 32^3x64 lattice (kappa = 0.135, csw = 1.0, smooth SU(3) links with
 eps = 0.3, Gaussian source), with b and x resident in HBM: mixed-precision
-CG on the normal equations of the Schur operator (FP32 inner iteration by
-default, FP64 reliable updates, FP64 final residual).
+CG on the normal equations of the Schur operator (FP16 inner iteration with
+per-site FP32 scales by default, FP32 inner vectors, FP64 reliable updates,
+FP64 final residual).
 
 Printed (one JSON line):
   value         whole-solve throughput: algorithmic bytes of every kernel the
@@ -67,6 +68,27 @@ def dslash_rates(lq, lat, torch, b_full, nrep=50):
     return out
 
 
+def copy_rate(torch, nbytes=1 << 30, nrep=20):
+    """A plain device-to-device copy of known size (1 GiB read + 1 GiB written):
+    the achievable HBM bandwidth on this machine, and the reference kernel that
+    scales the FETCH_SIZE / WRITE_SIZE counters."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(nrep):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    s = a.elapsed_time(b) * 1e-3 / nrep
+    del src, dst
+    return {"bytes_per_copy": 2 * nbytes, "us": round(s * 1e6, 1),
+            "GB/s": round(2 * nbytes / s / 1e9, 1)}
+
+
 def cpu_baseline(u, b, dims):
     """The FP64 oracle on the host: one even-odd hopping sweep H_eo of the same
     32^3x64 workload (a bounded sample of the solve, whose iterations each make
@@ -91,7 +113,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--inner", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--inner", choices=["f32", "f16"], default="f16")
     ap.add_argument("--dims", default="32,32,32,64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -209,6 +231,7 @@ def main():
 
     log("stand-alone hopping-term sweeps")
     result["dslash_gbs"] = dslash_rates(lq, lat, torch, b)
+    result["hbm_copy"] = copy_rate(torch)
 
     if not a.no_cpu_baseline:
         log("CPU baseline (oracle)")

@@ -32,9 +32,9 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def compile_one(src: str) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def compile_one(src: str, build_dir: str = BUILD, defines=()) -> str:
+    obj = os.path.join(build_dir, src.replace(".hip", ".o"))
+    cmd = [HIPCC, *FLAGS, *("-D" + d for d in defines), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -47,25 +47,30 @@ def compile_one(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int = 8, out: str = OUT, defines=()) -> str:
+    """Compile every source and link `out`; `defines` (NAME=VALUE) select
+    compile-time tuning parameters such as LQ_WAVES_F32."""
+    build_dir = BUILD if out == OUT else out + ".objs"
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs)))) as ex:
-        objs = list(ex.map(compile_one, srcs))
-    tmp = OUT + ".tmp"
+        objs = list(ex.map(lambda s: compile_one(s, build_dir, defines), srcs))
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=int(os.environ.get("MAX_JOBS", "8")))
+    ap.add_argument("--out", default=OUT)
+    ap.add_argument("-D", "--define", action="append", default=[])
     a = ap.parse_args()
-    print(build(a.jobs))
+    print(build(a.jobs, os.path.abspath(a.out), a.define))
 
 
 if __name__ == "__main__":

@@ -1,5 +1,6 @@
 // C ABI entry points (include/lq.h): argument checks, error capture, context
 // lifetime.  No C++ exception crosses this boundary.
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -44,6 +45,18 @@ void check_prec(int prec) {
 }  // namespace
 
 namespace lq {
+
+// Largest number of sites of one parity per tile; LQ_TILE_SITES overrides
+// the default (tuning experiments).
+int64_t tile_target() {
+  const char* e = std::getenv("LQ_TILE_SITES");
+  if (e) {
+    const long long v = std::atoll(e);
+    if (v >= 64) return v;
+  }
+  // measured on MI355X at 32^3x64: 65536 beats 4096, 16384 and untiled
+  return 65536;
+}
 
 size_t field_bytes(const lq_ctx* ctx, int parity, int prec, int nrhs) {
   size_t one = parity_field_bytes(ctx->geo.nblk, prec);
@@ -97,11 +110,10 @@ lq_status lq_create(const int dims[4], int t_antiperiodic, void* hip_stream, lq_
     ctx->dims[k] = dims[k];
     ctx->geo.L[k] = dims[k];
   }
-  ctx->geo.lxh = dims[0] / 2;
+  lq::choose_tiles(ctx->geo.L, lq::tile_target(), ctx->geo.T);
+  lq::geo_finish(ctx->geo);
   ctx->geo.apt = t_antiperiodic ? 1 : 0;
   ctx->V = V;
-  ctx->geo.vh = V / 2;
-  ctx->geo.nblk = (V / 2 + lq::SB - 1) / lq::SB;
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   ctx->cur = ctx->stream;
   const hipError_t se = hipStreamCreateWithFlags(&ctx->sstream, hipStreamNonBlocking);
@@ -172,7 +184,7 @@ lq_status lq_spinor_to_device(lq_ctx* ctx, void* dev, const double* host, int pa
     for (int r = 0; r < nrhs; ++r) {
       LQ_HIP(hipMemcpyAsync(st, host + (size_t)r * nsites * 24, hb, hipMemcpyHostToDevice,
                             ctx->cur));
-      lq::pack_spinor(ctx, reinterpret_cast<char*>(dev) + r * fb, st, prec, nsites, full);
+      lq::pack_spinor(ctx, reinterpret_cast<char*>(dev) + r * fb, st, prec, parity);
     }
     LQ_HIP(hipStreamSynchronize(ctx->cur));
   });
@@ -190,7 +202,7 @@ lq_status lq_spinor_to_host(lq_ctx* ctx, double* host, const void* dev, int pari
     const size_t fb = lq::field_bytes(ctx, parity, prec, 1);
     double2* st = reinterpret_cast<double2*>(lq::staging(ctx, hb));
     for (int r = 0; r < nrhs; ++r) {
-      lq::unpack_spinor(ctx, st, reinterpret_cast<const char*>(dev) + r * fb, prec, full);
+      lq::unpack_spinor(ctx, st, reinterpret_cast<const char*>(dev) + r * fb, prec, parity);
       LQ_HIP(hipMemcpyAsync(host + (size_t)r * nsites * 24, st, hb, hipMemcpyDeviceToHost,
                             ctx->cur));
       LQ_HIP(hipStreamSynchronize(ctx->cur));

@@ -192,17 +192,9 @@ __global__ __launch_bounds__(128) void build_clover_kernel(Geo g, const double2*
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= V) return;
   int x[4];
-  {
-    int64_t r = i;
-    x[0] = (int)(r % g.L[0]);
-    r /= g.L[0];
-    x[1] = (int)(r % g.L[1]);
-    r /= g.L[1];
-    x[2] = (int)(r % g.L[2]);
-    x[3] = (int)(r / g.L[2]);
-  }
+  canonical_coords(g, i, x);
   const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
-  const int64_t s = i >> 1;
+  const int64_t s = cb_index(g, x);
   M3 f01, f02, f03, f12, f13, f23;
   if (ck != 0.0) {
     f01 = field_strength(g, g64, x, 0, 1);

@@ -11,7 +11,7 @@ namespace {
 constexpr int BLK = 256;
 
 template <class P, bool DAG>
-__global__ __launch_bounds__(BLK) void dslash_kernel(Geo g, int p, Field<P> out, Field<P> in,
+LQ_HOP_KERNEL(P) void dslash_kernel(Geo g, int p, Field<P> out, Field<P> in,
                                                      const typename P::S* __restrict__ gauge) {
   const int64_t s = xcd_block(blockIdx.x, gridDim.x) * BLK + threadIdx.x;
   if (s >= g.vh) return;
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(BLK) void clover_kernel(Geo g, Field<P> out, Field<
 
 // t_o = A_oo^{-1} H_oe in_e   (DAG: H^+ blocks)
 template <class P, bool DAG>
-__global__ __launch_bounds__(BLK) void schur_k1_kernel(Geo g, Field<P> out, Field<P> in,
+LQ_HOP_KERNEL(P) void schur_k1_kernel(Geo g, Field<P> out, Field<P> in,
                                                        const typename P::S* __restrict__ gauge,
                                                        const typename P::S* __restrict__ ainv) {
   const int64_t s = xcd_block(blockIdx.x, gridDim.x) * BLK + threadIdx.x;
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(BLK) void schur_k1_kernel(Geo g, Field<P> out, Fiel
 
 // out_e = A_ee x_e - kappa^2 H_eo t_o
 template <class P, bool DAG>
-__global__ __launch_bounds__(BLK) void schur_k2_kernel(Geo g, Field<P> out, Field<P> t,
+LQ_HOP_KERNEL(P) void schur_k2_kernel(Geo g, Field<P> out, Field<P> t,
                                                        Field<P> x,
                                                        const typename P::S* __restrict__ gauge,
                                                        const typename P::S* __restrict__ aee,

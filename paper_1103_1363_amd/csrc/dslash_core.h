@@ -80,7 +80,7 @@ __device__ __forceinline__ void load_link(const typename P::S* __restrict__ gaug
                                           int p, int mu, int64_t s, C<typename P::R> u[9]) {
   using R = typename P::R;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) u[c] = ld<P>(gauge, link_idx(nblk, p, mu, s, c));
+  for (int c = 0; c < 6; ++c) u[c] = ldnt<P>(gauge, link_idx(nblk, p, mu, s, c));
   // row2 = conj(row0 x row1)
   u[6] = conj(u[1] * u[5] - u[2] * u[4]);
   u[7] = conj(u[2] * u[3] - u[0] * u[5]);
@@ -112,17 +112,21 @@ __device__ __forceinline__ void link_mul(const C<R> u[9], const C<R> h[6], C<R> 
 template <int MU, int S, bool BACK, class P>
 __device__ __forceinline__ void hop_dir(const Geo& g, const Field<P>& in,
                                         const typename P::S* __restrict__ gauge, int p,
-                                        int64_t s, const int x[4], C<typename P::R> acc[12]) {
+                                        int64_t s, const int l[4], const int tc[4], int x3,
+                                        C<typename P::R> acc[12]) {
   using R = typename P::R;
-  int y[4] = {x[0], x[1], x[2], x[3]};
   R sign = (R)1;
-  if constexpr (!BACK) {
-    y[MU] = (x[MU] + 1 == g.L[MU]) ? 0 : x[MU] + 1;
-    if (MU == 3 && g.apt && x[3] == g.L[3] - 1) sign = (R)-1;
-  } else {
-    y[MU] = (x[MU] == 0) ? g.L[MU] - 1 : x[MU] - 1;
-    if (MU == 3 && g.apt && x[3] == 0) sign = (R)-1;
+  if constexpr (MU == 3) {
+    if (g.apt && x3 == (BACK ? 0 : g.L[3] - 1)) sign = (R)-1;
   }
+  // Neighbour number from its coordinates.  (A division-free step,
+  // `neighbour()` in site_index.h, gives the same numbers but lets the
+  // compiler hoist all eight hops' loads: 256 VGPRs and spills.)
+  int y[4] = {tc[0] * g.T[0] + l[0], tc[1] * g.T[1] + l[1], tc[2] * g.T[2] + l[2], x3};
+  if constexpr (!BACK)
+    y[MU] = (y[MU] + 1 == g.L[MU]) ? 0 : y[MU] + 1;
+  else
+    y[MU] = (y[MU] == 0) ? g.L[MU] - 1 : y[MU] - 1;
   const int64_t sy = cb_index(g, y);
   C<R> v[12];
   const R scale = load_raw<P>(in, sy, v) * sign;
@@ -148,17 +152,24 @@ __device__ __forceinline__ void hop_site(const Geo& g, const Field<P>& in,
   using R = typename P::R;
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = C<R>{(R)0, (R)0};
-  int x[4];
-  site_coords(g, p, s, x);
+  int l[4], tc[4];
+  site_local(g, p, s, l, tc);
+  const int x3 = tc[3] * g.T[3] + l[3];
   constexpr int SF = DAG ? -1 : 1;  // forward-hop projector sign
-  hop_dir<0, SF, false>(g, in, gauge, p, s, x, acc);
-  hop_dir<0, -SF, true>(g, in, gauge, p, s, x, acc);
-  hop_dir<1, SF, false>(g, in, gauge, p, s, x, acc);
-  hop_dir<1, -SF, true>(g, in, gauge, p, s, x, acc);
-  hop_dir<2, SF, false>(g, in, gauge, p, s, x, acc);
-  hop_dir<2, -SF, true>(g, in, gauge, p, s, x, acc);
-  hop_dir<3, SF, false>(g, in, gauge, p, s, x, acc);
-  hop_dir<3, -SF, true>(g, in, gauge, p, s, x, acc);
+  // The scheduling barriers keep the loads of at most two hops in flight per
+  // thread: hoisting all eight (144 loads) would cost registers and with them
+  // the occupancy that hides memory latency on this bandwidth-bound kernel.
+  hop_dir<0, SF, false>(g, in, gauge, p, s, l, tc, x3, acc);
+  hop_dir<0, -SF, true>(g, in, gauge, p, s, l, tc, x3, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_dir<1, SF, false>(g, in, gauge, p, s, l, tc, x3, acc);
+  hop_dir<1, -SF, true>(g, in, gauge, p, s, l, tc, x3, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_dir<2, SF, false>(g, in, gauge, p, s, l, tc, x3, acc);
+  hop_dir<2, -SF, true>(g, in, gauge, p, s, l, tc, x3, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  hop_dir<3, SF, false>(g, in, gauge, p, s, l, tc, x3, acc);
+  hop_dir<3, -SF, true>(g, in, gauge, p, s, l, tc, x3, acc);
 }
 
 // ---------------------------------------------------------------- clover
@@ -178,7 +189,7 @@ __device__ __forceinline__ void clover_mul(const typename P::S* __restrict__ cl,
   for (int b = 0; b < 2; ++b) {
     C<R> m[18];
 #pragma unroll
-    for (int k = 0; k < 18; ++k) m[k] = ld<P>(cl, clov_idx(s, 18 * b + k));
+    for (int k = 0; k < 18; ++k) m[k] = ldnt<P>(cl, clov_idx(s, 18 * b + k));
     const C<R>* xb = x + 6 * b;
 #pragma unroll
     for (int r = 0; r < 6; ++r) {

@@ -18,16 +18,10 @@ __global__ void compress_gauge_kernel(Geo g, const double2* __restrict__ host, d
   if (t < nlinks) {
     int64_t i = t >> 2;
     int mu = (int)(t & 3);
-    // coordinates of full index i
-    int64_t r = i;
-    int x0 = (int)(r % g.L[0]);
-    r /= g.L[0];
-    int x1 = (int)(r % g.L[1]);
-    r /= g.L[1];
-    int x2 = (int)(r % g.L[2]);
-    int x3 = (int)(r / g.L[2]);
-    int p = (x0 + x1 + x2 + x3) & 1;
-    int64_t s = i >> 1;
+    int x[4];
+    canonical_coords(g, i, x);
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const int64_t s = cb_index(g, x);
     C<double> u[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -74,26 +68,31 @@ __global__ void compress_gauge_kernel(Geo g, const double2* __restrict__ host, d
   if (threadIdx.x == 0) blockmax[blockIdx.x] = red[0];
 }
 
+// Device site of host index t and its parity.  parity EVEN/ODD: t ranks
+// the site among the sites of that parity in canonical order (t = i / 2);
+// FULL: t is the canonical index i.
+__device__ inline int64_t host_to_device_site(const Geo& g, int parity, int64_t t, int& p) {
+  int x[4];
+  if (parity == LQ_FULL) {
+    canonical_coords(g, t, x);
+    p = (x[0] + x[1] + x[2] + x[3]) & 1;
+  } else {
+    canonical_coords(g, 2 * t, x);  // x0 even; the parity picks x0 or x0 + 1
+    p = parity;
+    x[0] += (p + x[0] + x[1] + x[2] + x[3]) & 1;
+  }
+  return cb_index(g, x);
+}
+
 // Host canonical half or full field (double2 per complex) -> device field.
-// full = 1: thread per full-lattice site; else thread per checkerboard site.
 template <class P>
 __global__ void pack_kernel(Geo g, Field<P> f_even, Field<P> f_odd, const double2* __restrict__ src,
-                            int64_t n, int full) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                            int64_t n, int parity) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  Field<P> f = f_even;
-  int64_t s = t;
-  if (full) {
-    int64_t r = t;
-    int x0 = (int)(r % g.L[0]);
-    r /= g.L[0];
-    int x1 = (int)(r % g.L[1]);
-    r /= g.L[1];
-    int x2 = (int)(r % g.L[2]);
-    int x3 = (int)(r / g.L[2]);
-    if ((x0 + x1 + x2 + x3) & 1) f = f_odd;
-    s = t >> 1;
-  }
+  int p = 0;
+  const int64_t s = host_to_device_site(g, parity, t, p);
+  const Field<P> f = p ? f_odd : f_even;
   double2 v[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) v[c] = src[t * 12 + c];
@@ -119,22 +118,12 @@ __global__ void pack_kernel(Geo g, Field<P> f_even, Field<P> f_odd, const double
 
 template <class P>
 __global__ void unpack_kernel(Geo g, Field<P> f_even, Field<P> f_odd, double2* __restrict__ dst,
-                              int64_t n, int full) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                              int64_t n, int parity) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  Field<P> f = f_even;
-  int64_t s = t;
-  if (full) {
-    int64_t r = t;
-    int x0 = (int)(r % g.L[0]);
-    r /= g.L[0];
-    int x1 = (int)(r % g.L[1]);
-    r /= g.L[1];
-    int x2 = (int)(r % g.L[2]);
-    int x3 = (int)(r / g.L[2]);
-    if ((x0 + x1 + x2 + x3) & 1) f = f_odd;
-    s = t >> 1;
-  }
+  int p = 0;
+  const int64_t s = host_to_device_site(g, parity, t, p);
+  const Field<P> f = p ? f_odd : f_even;
   // the stored value is component * scale; form the product in FP64 so the
   // host sees exactly what the field represents
   C<typename P::R> v[12];
@@ -144,29 +133,33 @@ __global__ void unpack_kernel(Geo g, Field<P> f_even, Field<P> f_odd, double2* _
     dst[t * 12 + c] = make_double2(sc * (double)v[c].re, sc * (double)v[c].im);
 }
 
+// For a half field, dev is that parity's field (both f_even and f_odd
+// point at it); for FULL, dev holds the even half then the odd half.
 template <class P>
-void pack_t(lq_ctx* ctx, void* dev, const double2* src, int full) {
+void pack_t(lq_ctx* ctx, void* dev, const double2* src, int parity) {
   const Geo& g = ctx->geo;
   char* base = reinterpret_cast<char*>(dev);
   Field<P> fe = field_at<P>(base, g.nblk);
-  Field<P> fo = field_at<P>(base + parity_field_bytes(g.nblk, P::id), g.nblk);
-  int64_t n = full ? ctx->V : g.vh;
+  Field<P> fo = parity == LQ_FULL ? field_at<P>(base + parity_field_bytes(g.nblk, P::id), g.nblk)
+                                  : fe;
+  const int64_t n = parity == LQ_FULL ? ctx->V : g.vh;
   ctx->bytes += (double)n * (192.0 + spinor_site_bytes(P::id));
   hipLaunchKernelGGL(pack_kernel<P>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur, g, fe, fo,
-                     src, n, full);
+                     src, n, parity);
   LQ_HIP(hipGetLastError());
 }
 
 template <class P>
-void unpack_t(lq_ctx* ctx, double2* dst, const void* dev, int full) {
+void unpack_t(lq_ctx* ctx, double2* dst, const void* dev, int parity) {
   const Geo& g = ctx->geo;
   char* base = reinterpret_cast<char*>(const_cast<void*>(dev));
   Field<P> fe = field_at<P>(base, g.nblk);
-  Field<P> fo = field_at<P>(base + parity_field_bytes(g.nblk, P::id), g.nblk);
-  int64_t n = full ? ctx->V : g.vh;
+  Field<P> fo = parity == LQ_FULL ? field_at<P>(base + parity_field_bytes(g.nblk, P::id), g.nblk)
+                                  : fe;
+  const int64_t n = parity == LQ_FULL ? ctx->V : g.vh;
   ctx->bytes += (double)n * (192.0 + spinor_site_bytes(P::id));
   hipLaunchKernelGGL(unpack_kernel<P>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur, g, fe,
-                     fo, dst, n, full);
+                     fo, dst, n, parity);
   LQ_HIP(hipGetLastError());
 }
 
@@ -212,19 +205,19 @@ void upload_gauge(lq_ctx* ctx, const double* host_U) {
   ctx->clov.valid = false;
 }
 
-void pack_spinor(lq_ctx* ctx, void* dev, const double2* src, int prec, int64_t, int full) {
+void pack_spinor(lq_ctx* ctx, void* dev, const double2* src, int prec, int parity) {
   switch (prec) {
-    case LQ_F64: pack_t<P64>(ctx, dev, src, full); break;
-    case LQ_F32: pack_t<P32>(ctx, dev, src, full); break;
-    default: pack_t<P16>(ctx, dev, src, full); break;
+    case LQ_F64: pack_t<P64>(ctx, dev, src, parity); break;
+    case LQ_F32: pack_t<P32>(ctx, dev, src, parity); break;
+    default: pack_t<P16>(ctx, dev, src, parity); break;
   }
 }
 
-void unpack_spinor(lq_ctx* ctx, double2* dst, const void* dev, int prec, int full) {
+void unpack_spinor(lq_ctx* ctx, double2* dst, const void* dev, int prec, int parity) {
   switch (prec) {
-    case LQ_F64: unpack_t<P64>(ctx, dst, dev, full); break;
-    case LQ_F32: unpack_t<P32>(ctx, dst, dev, full); break;
-    default: unpack_t<P16>(ctx, dst, dev, full); break;
+    case LQ_F64: unpack_t<P64>(ctx, dst, dev, parity); break;
+    case LQ_F32: unpack_t<P32>(ctx, dst, dev, parity); break;
+    default: unpack_t<P16>(ctx, dst, dev, parity); break;
   }
 }
 

@@ -12,6 +12,9 @@
 
 #include "../../include/lq.h"
 
+#define LQ_HD __host__ __device__
+#include "site_index.h"
+
 namespace lq {
 
 // ---------------------------------------------------------------- errors
@@ -52,28 +55,6 @@ __host__ __device__ inline int64_t link_idx(int64_t nblk, int p, int mu, int64_t
   return ((((int64_t)p * 4 + mu) * nblk + (s >> 6)) * 6 + c) * SB + (s & 63);
 }
 
-// Lattice geometry as passed to kernels.
-struct Geo {
-  int L[4];      // Lx, Ly, Lz, Lt
-  int lxh;       // Lx / 2
-  int apt;       // antiperiodic in t
-  int64_t vh;    // sites per parity
-  int64_t nblk;  // blocks of 64 per parity (vh rounded up)
-};
-
-// Coordinates of checkerboard site s of parity p.
-__device__ inline void site_coords(const Geo& g, int p, int64_t s, int x[4]) {
-  int64_t r = s / g.lxh;
-  int xh = (int)(s - r * g.lxh);
-  x[1] = (int)(r % g.L[1]);
-  r /= g.L[1];
-  x[2] = (int)(r % g.L[2]);
-  x[3] = (int)(r / g.L[2]);
-  x[0] = 2 * xh + ((p + x[1] + x[2] + x[3]) & 1);
-}
-__device__ inline int64_t cb_index(const Geo& g, const int x[4]) {
-  return ((((int64_t)x[3] * g.L[2] + x[2]) * g.L[1] + x[1]) * g.L[0] + x[0]) >> 1;
-}
 
 // ---------------------------------------------------------------- complex
 template <class R>
@@ -107,6 +88,21 @@ template <class R>
 __device__ __forceinline__ R norm2(C<R> a) { return a.re * a.re + a.im * a.im; }
 
 // ---------------------------------------------------------------- precision traits
+// Register budget of the hopping kernels: at least this many waves per SIMD
+// (512 / waves VGPRs per lane).  The compiler otherwise hoists all eight
+// neighbour loads and trades occupancy for instruction-level parallelism,
+// which loses on these bandwidth-bound kernels.
+#ifndef LQ_WAVES_F64
+#define LQ_WAVES_F64 2
+#endif
+#ifndef LQ_WAVES_F32
+#define LQ_WAVES_F32 4
+#endif
+#ifndef LQ_WAVES_F16
+#define LQ_WAVES_F16 3
+#endif
+#define LQ_HOP_KERNEL(P) \
+  __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P::waves)))
 // Storage type S, arithmetic type R.  FP16 fields hold fp16(value / scale)
 // with one FP32 scale per site stored after the component array.
 struct P64 {
@@ -114,18 +110,21 @@ struct P64 {
   using S = double2;
   static constexpr bool has_norm = false;
   static constexpr int id = LQ_F64;
+  static constexpr int waves = LQ_WAVES_F64;  // minimum waves per SIMD of hopping kernels
 };
 struct P32 {
   using R = float;
   using S = float2;
   static constexpr bool has_norm = false;
   static constexpr int id = LQ_F32;
+  static constexpr int waves = LQ_WAVES_F32;
 };
 struct P16 {
   using R = float;
   using S = __half2;
   static constexpr bool has_norm = true;
   static constexpr int id = LQ_F16;
+  static constexpr int waves = LQ_WAVES_F16;
 };
 
 template <class P>
@@ -145,6 +144,33 @@ __device__ __forceinline__ C<float> ld<P16>(const __half2* p, int64_t i) {
   float2 v = __half22float2(p[i]);
   return {v.x, v.y};
 }
+// Streaming loads for data read exactly once per sweep (links, clover
+// tables): the non-temporal hint lets L2 keep the spinors, which are read
+// by eight neighbours, instead of the streamed tables.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u1;
+template <class P>
+__device__ __forceinline__ C<typename P::R> ldnt(const typename P::S* p, int64_t i);
+template <>
+__device__ __forceinline__ C<double> ldnt<P64>(const double2* p, int64_t i) {
+  const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p) + i);
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ C<float> ldnt<P32>(const float2* p, int64_t i) {
+  const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p) + i);
+  return {v.x, v.y};
+}
+template <>
+__device__ __forceinline__ C<float> ldnt<P16>(const __half2* p, int64_t i) {
+  const nt_u1 v = __builtin_nontemporal_load(reinterpret_cast<const nt_u1*>(p) + i);
+  __half2 h;
+  __builtin_memcpy(&h, &v, 4);
+  const float2 f = __half22float2(h);
+  return {f.x, f.y};
+}
+
 template <class P>
 __device__ __forceinline__ void st(typename P::S* p, int64_t i, C<typename P::R> v);
 template <>
@@ -274,9 +300,10 @@ void ensure_red(lq_ctx* ctx);
 
 // layout.hip
 void upload_gauge(lq_ctx* ctx, const double* host_U);
-void pack_spinor(lq_ctx* ctx, void* dev, const double2* src_dev, int prec, int64_t nsites_half,
-                 int full);
-void unpack_spinor(lq_ctx* ctx, double2* dst_dev, const void* dev, int prec, int full);
+// parity: LQ_EVEN / LQ_ODD (host half field, dev one parity field) or
+// LQ_FULL (host full field, dev = even half then odd half)
+void pack_spinor(lq_ctx* ctx, void* dev, const double2* src_dev, int prec, int parity);
+void unpack_spinor(lq_ctx* ctx, double2* dst_dev, const void* dev, int prec, int parity);
 
 // dslash.hip
 void dslash(lq_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int prec);

@@ -489,7 +489,7 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
       double2* stg = reinterpret_cast<double2*>(staging(ctx, hb));
       LQ_HIP(hipMemcpyAsync(stg, host_b + (size_t)rhs * nsite * 24, hb, hipMemcpyHostToDevice,
                             ctx->cur));
-      pack_spinor(ctx, w->b, stg, LQ_F64, nsite, 1);
+      pack_spinor(ctx, w->b, stg, LQ_F64, LQ_FULL);
     } else {
       w->b = const_cast<char*>(reinterpret_cast<const char*>(dev_b)) + rhs * fb;
       w->x = reinterpret_cast<char*>(dev_x) + rhs * fb;
@@ -541,7 +541,7 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
     // result to host
     if (host_x) {
       double2* stg = reinterpret_cast<double2*>(staging(ctx, hb));
-      unpack_spinor(ctx, stg, w->x, LQ_F64, 1);
+      unpack_spinor(ctx, stg, w->x, LQ_F64, LQ_FULL);
       LQ_HIP(hipMemcpyAsync(host_x + (size_t)rhs * nsite * 24, stg, hb, hipMemcpyDeviceToHost,
                             ctx->cur));
     }

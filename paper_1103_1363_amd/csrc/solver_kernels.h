@@ -61,7 +61,7 @@ __device__ __forceinline__ double site_norm2(const C<R> v[12]) {
 }
 
 template <class PO, bool DAG>
-__global__ __launch_bounds__(SBLK) void cg_k1(Geo g, const CGState* __restrict__ st, Field<PO> t,
+LQ_HOP_KERNEL(PO) void cg_k1(Geo g, const CGState* __restrict__ st, Field<PO> t,
                                               Field<PO> in, const typename PO::S* __restrict__ gauge,
                                               const typename PO::S* __restrict__ ainv) {
   if (!st->active) return;
@@ -89,7 +89,7 @@ struct FinAlpha {
 };
 
 template <class PO>
-__global__ __launch_bounds__(SBLK) void cg_k2(Geo g, CGState* st, Field<PO> q, Field<PO> t,
+LQ_HOP_KERNEL(PO) void cg_k2(Geo g, CGState* st, Field<PO> q, Field<PO> t,
                                               Field<PO> p, const typename PO::S* __restrict__ gauge,
                                               const typename PO::S* __restrict__ aee,
                                               typename PO::R k2, RedBuf rb) {
@@ -139,7 +139,7 @@ struct FinBeta {
 };
 
 template <class PO, class PV>
-__global__ __launch_bounds__(SBLK) void cg_k4(Geo g, CGState* st, Field<PO> t, Field<PO> q,
+LQ_HOP_KERNEL(PO) void cg_k4(Geo g, CGState* st, Field<PO> t, Field<PO> q,
                                               Field<PO> p, Field<PV> x, Field<PV> r, Field<PV> rt,
                                               const typename PO::S* __restrict__ gauge,
                                               const typename PO::S* __restrict__ aee,

@@ -13,7 +13,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblq.so")
+# LQ_LIBRARY selects another build of the same library (tuning experiments)
+LIB_PATH = os.environ.get("LQ_LIBRARY") or os.path.join(_HERE, "liblq.so")
 
 F64, F32, F16 = 0, 1, 2
 EVEN, ODD, FULL = 0, 1, 2
