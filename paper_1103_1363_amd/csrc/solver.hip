@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "bicgstab_kernels.h"
 #include "solver_kernels.h"
 
 namespace lq {
@@ -42,6 +43,14 @@ struct Work {
   void* rt[3] = {nullptr, nullptr, nullptr};
   CGState* st = nullptr;       // device
   CGState* st_host = nullptr;  // pinned
+  // BiCGStab extras (operator precision): s and M s
+  void* bs[3] = {nullptr, nullptr, nullptr};
+  void* bt[3] = {nullptr, nullptr, nullptr};
+  BiState* bst = nullptr;       // device
+  BiState* bst_host = nullptr;  // pinned
+  hipGraphExec_t bgraph[3] = {nullptr, nullptr, nullptr};
+  int bgraph_iters[3] = {0, 0, 0};
+  double bgraph_k2[3] = {0, 0, 0};
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
   int graph_iters[3] = {0, 0, 0};
   double graph_k2[3] = {0, 0, 0};
@@ -170,14 +179,14 @@ void launch_iteration(lq_ctx* ctx, Work* w, int ip, double k2d, Prof* pf = nullp
   Field<PO> p = F<PO>(w->p[ip], nb), q = F<PO>(w->q[ip], nb), t = F<PO>(w->t[ip], nb);
   Field<PV> x = F<PV>(w->xl[ip], nb), r = F<PV>(w->r[ip], nb), rt = F<PV>(w->rt[ip], nb);
   if (pf) pf->begin();
-  hipLaunchKernelGGL((cg_k1<PO, false>), grid, blk, 0, ctx->cur, g, w->st, t, p, gp, ai);
+  hipLaunchKernelGGL((cg_k1<PO, false>), grid, blk, 0, ctx->cur, g, &w->st->active, t, p, gp, ai);
   if (pf) pf->end(LQ_K_HOP_OE), pf->begin();
   hipLaunchKernelGGL((cg_k2<PO>), grid, blk, 0, ctx->cur, g, w->st, q, t, p, gp, ae, k2, rb);
   if (pf) pf->end(LQ_K_HOP_EO);
   hipLaunchKernelGGL((finalize_kernel<1, FinAlpha>), dim3(1), dim3(256), 0, ctx->cur, rb,
                      (int)grid.x, FinAlpha{w->st});
   if (pf) pf->begin();
-  hipLaunchKernelGGL((cg_k1<PO, true>), grid, blk, 0, ctx->cur, g, w->st, t, q, gp, ai);
+  hipLaunchKernelGGL((cg_k1<PO, true>), grid, blk, 0, ctx->cur, g, &w->st->active, t, q, gp, ai);
   if (pf) pf->end(LQ_K_HOPD_OE), pf->begin();
   hipLaunchKernelGGL((cg_k4<PO, PV>), grid, blk, 0, ctx->cur, g, w->st, t, q, p, x, r, rt, gp,
                      ae, k2, rb);
@@ -386,6 +395,199 @@ bool run_cg(lq_ctx* ctx, Work* w, int inner, double target, double delta, int ma
   }
 }
 
+// ------------------------------------------------------------ BiCGStab
+void bicg_site_bytes(int po, int pv, double* total) {
+  const double L = link_site_bytes(po), S = spinor_site_bytes(po), C = clover_site_bytes(po);
+  const double Sv = spinor_site_bytes(pv);
+  *total = (8 * L + 2 * S + C) * 2      // B1, B4
+           + (8 * L + 3 * S + C + Sv)   // B2 (+ rh)
+           + (Sv + 2 * S)               // B3
+           + (8 * L + 3 * S + C)        // B5
+           + (3 * Sv + 3 * S + Sv)      // B6: x r/w, p, s, tt, r write, rh
+           + (Sv + 3 * S);              // B7
+}
+
+template <class PO, class PV>
+void launch_bi_iteration(lq_ctx* ctx, Work* w, int ip, double k2d) {
+  const Geo& g = ctx->geo;
+  const int64_t nb = g.nblk;
+  const dim3 grid(grid_for(g.vh, SBLK)), blk(SBLK);
+  using S = typename PO::S;
+  const S* gp = reinterpret_cast<const S*>(ctx->gauge[PO::id]);
+  const S* ai = reinterpret_cast<const S*>(ctx->clov.ainv_oo[PO::id]);
+  const S* ae = reinterpret_cast<const S*>(ctx->clov.a_ee[PO::id]);
+  const typename PO::R k2 = (typename PO::R)k2d;
+  RedBuf rb = red_buf(ctx);
+  Field<PO> p = F<PO>(w->p[ip], nb), v = F<PO>(w->q[ip], nb), t = F<PO>(w->t[ip], nb);
+  Field<PO> s = F<PO>(w->bs[ip], nb), tt = F<PO>(w->bt[ip], nb);
+  Field<PV> x = F<PV>(w->xl[ip], nb), r = F<PV>(w->r[ip], nb), rh = F<PV>(w->rt[ip], nb);
+  const int* act = &w->bst->active;
+  hipLaunchKernelGGL((cg_k1<PO, false>), grid, blk, 0, ctx->cur, g, act, t, p, gp, ai);
+  hipLaunchKernelGGL((bi_hop_eo<PO, PV, 0>), grid, blk, 0, ctx->cur, g, act, v, t, p, rh, gp, ae,
+                     k2, rb);
+  hipLaunchKernelGGL((finalize_kernel<3, FinBiAlpha>), dim3(1), dim3(256), 0, ctx->cur, rb,
+                     (int)grid.x, FinBiAlpha{w->bst});
+  hipLaunchKernelGGL((bi_s<PO, PV>), grid, blk, 0, ctx->cur, g, w->bst, s, r, v);
+  hipLaunchKernelGGL((cg_k1<PO, false>), grid, blk, 0, ctx->cur, g, act, t, s, gp, ai);
+  hipLaunchKernelGGL((bi_hop_eo<PO, PV, 1>), grid, blk, 0, ctx->cur, g, act, tt, t, s, rh, gp, ae,
+                     k2, rb);
+  hipLaunchKernelGGL((finalize_kernel<3, FinBiOmega>), dim3(1), dim3(256), 0, ctx->cur, rb,
+                     (int)grid.x, FinBiOmega{w->bst});
+  hipLaunchKernelGGL((bi_update<PO, PV>), grid, blk, 0, ctx->cur, g, w->bst, x, r, rh, p, s, tt,
+                     rb);
+  hipLaunchKernelGGL((finalize_kernel<3, FinBiRho>), dim3(1), dim3(256), 0, ctx->cur, rb,
+                     (int)grid.x, FinBiRho{w->bst});
+  hipLaunchKernelGGL((bi_p<PO, PV>), grid, blk, 0, ctx->cur, g, w->bst, p, r, v);
+  LQ_HIP(hipGetLastError());
+}
+
+template <class PO, class PV>
+void run_bi_iterations(lq_ctx* ctx, Work* w, int ip, double k2, int n, bool use_graph) {
+  if (!use_graph) {
+    for (int i = 0; i < n; ++i) launch_bi_iteration<PO, PV>(ctx, w, ip, k2);
+    return;
+  }
+  if (!w->bgraph[ip] || w->bgraph_iters[ip] != n || w->bgraph_k2[ip] != k2) {
+    if (w->bgraph[ip]) {
+      (void)hipGraphExecDestroy(w->bgraph[ip]);
+      w->bgraph[ip] = nullptr;
+    }
+    hipGraph_t gr = nullptr;
+    LQ_HIP(hipStreamBeginCapture(ctx->cur, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int i = 0; i < n; ++i) launch_bi_iteration<PO, PV>(ctx, w, ip, k2);
+    } catch (...) {
+      (void)hipStreamEndCapture(ctx->cur, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      throw;
+    }
+    LQ_HIP(hipStreamEndCapture(ctx->cur, &gr));
+    hipError_t e = hipGraphInstantiate(&w->bgraph[ip], gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    LQ_HIP(e);
+    w->bgraph_iters[ip] = n;
+    w->bgraph_k2[ip] = k2;
+  }
+  LQ_HIP(hipGraphLaunch(w->bgraph[ip], ctx->cur));
+}
+
+// BiCGStab on Mhat x_e = bhat; restarts (with the shadow residual reset to
+// the FP64 residual) at every reliable update, at a rho breakdown and when
+// the recurrence reports convergence that the FP64 residual does not confirm.
+template <class PO, class PV>
+bool bicgstab(lq_ctx* ctx, Work* w, double target, double delta, int maxiter, int check_every,
+              bool use_graph, int fault_inject, SolveStats& ss, bool& want_fallback) {
+  const int ip = PO::id;
+  const int64_t nb = ctx->geo.nblk;
+  const double k2 = ctx->clov.kappa * ctx->clov.kappa;
+  const double target2 = target * target;
+  want_fallback = false;
+  if (!w->bs[ip]) {
+    const size_t fo = parity_field_bytes(nb, PO::id);
+    w->bs[ip] = dalloc(fo);
+    w->bt[ip] = dalloc(fo);
+  }
+  if (!w->bst) {
+    w->bst = reinterpret_cast<BiState*>(dalloc(sizeof(BiState)));
+    LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->bst_host), sizeof(BiState),
+                         hipHostMallocDefault));
+  }
+  double bytes_it = 0.0;
+  bicg_site_bytes(PO::id, PV::id, &bytes_it);
+  bytes_it *= (double)ctx->geo.vh;
+  BiState& h = *w->bst_host;
+  double hist[6];
+  int nhist = 0, restarts = 0, counted = 0;
+  double rt2 = schur_residual(ctx, w, ss);
+  if (rt2 <= target2) return true;
+  zero<PV>(ctx, w->xl[ip]);
+  for (;;) {
+    // (re)start from the FP64 residual: r = rh = p = r64
+    axpby<P64, P64, PV>(ctx, w->r[ip], 1.0, w->r64, 0.0, w->r64);
+    axpby<P64, P64, PV>(ctx, w->rt[ip], 1.0, w->r64, 0.0, w->r64);
+    axpby<P64, P64, PO>(ctx, w->p[ip], 1.0, w->r64, 0.0, w->r64);
+    std::memset(&h, 0, sizeof(BiState));
+    h.rho[0] = rt2;
+    h.rr = rt2;
+    h.rr_max = rt2;
+    h.rrh = rt2;
+    h.target2 = target2;
+    h.delta2 = delta * delta;
+    h.active = 1;
+    h.iter = ss.iterations;
+    h.maxiter = maxiter;
+    counted = h.iter;
+    LQ_HIP(hipMemcpyAsync(w->bst, &h, sizeof(BiState), hipMemcpyHostToDevice, ctx->cur));
+    int ref_iter = h.iter;
+    double ref_rr = rt2;
+    bool stalled = false;
+    for (;;) {
+      run_bi_iterations<PO, PV>(ctx, w, ip, k2, check_every, use_graph);
+      LQ_HIP(hipMemcpyAsync(&h, w->bst, sizeof(BiState), hipMemcpyDeviceToHost, ctx->cur));
+      LQ_HIP(hipStreamSynchronize(ctx->cur));
+      ctx->bytes += (h.iter - counted) * bytes_it;
+      counted = h.iter;
+      if (!h.active) break;
+      if (h.rr <= 0.25 * ref_rr) {
+        ref_iter = h.iter;
+        ref_rr = h.rr;
+      } else if (h.iter - ref_iter >= 400) {
+        stalled = true;
+        break;
+      }
+    }
+    ss.iterations = h.iter;
+    if (!fault_inject) axpby<P64, PV, P64>(ctx, w->x, 1.0, w->x, 1.0, w->xl[ip]);
+    zero<PV>(ctx, w->xl[ip]);
+    rt2 = schur_residual(ctx, w, ss);
+    ss.reliable += 1;
+    if (!std::isfinite(rt2)) {
+      if (PO::id != LQ_F64) {
+        want_fallback = true;
+        return false;
+      }
+      throw Error(LQ_ENAN, "NaN in the FP64 residual");
+    }
+    if (rt2 <= target2) return true;
+    if (h.reason == R_MAXITER || h.iter >= maxiter) return false;
+    if (h.reason == R_NAN || stalled) restarts += 1;
+    if (nhist < 6) {
+      hist[nhist++] = rt2;
+    } else {
+      for (int i = 0; i < 5; ++i) hist[i] = hist[i + 1];
+      hist[5] = rt2;
+    }
+    const bool no_progress = nhist == 6 && std::fmin(std::fmin(hist[1], hist[2]),
+                                                     std::fmin(std::fmin(hist[3], hist[4]),
+                                                               hist[5])) > 0.25 * hist[0];
+    if (no_progress || restarts > 20) {
+      if (PO::id != LQ_F64) {
+        want_fallback = true;
+        return false;
+      }
+      if (restarts > 20) throw Error(LQ_ENAN, "BiCGStab broke down repeatedly");
+    }
+  }
+}
+
+bool run_inner(lq_ctx* ctx, Work* w, int solver, int inner, double target, double delta,
+               int maxiter, int check_every, bool use_graph, int fault_inject, SolveStats& ss,
+               bool& fb, Prof* pf) {
+  if (solver == LQ_CGNR)
+    return run_cg(ctx, w, inner, target, delta, maxiter, check_every, use_graph, fault_inject, ss,
+                  fb, pf);
+  switch (inner) {
+    case LQ_F64:
+      return bicgstab<P64, P64>(ctx, w, target, delta, maxiter, check_every, use_graph, 0, ss, fb);
+    case LQ_F32:
+      return bicgstab<P32, P32>(ctx, w, target, delta, maxiter, check_every, use_graph,
+                                fault_inject, ss, fb);
+    default:
+      return bicgstab<P16, P32>(ctx, w, target, delta, maxiter, check_every, use_graph,
+                                fault_inject, ss, fb);
+  }
+}
+
 // x_o = A_oo^-1 (b_o + kappa H_oe x_e); returns |b - M x|^2 over both parities.
 double reconstruct_and_residual(lq_ctx* ctx, Work* w, SolveStats& ss) {
   const int64_t nb = ctx->geo.nblk;
@@ -424,9 +626,14 @@ void free_work(lq_ctx* ctx) {
     for (void* p : {w->p[i], w->q[i], w->t[i], w->xl[i], w->r[i], w->rt[i]})
       if (p) (void)hipFree(p);
     if (w->graph[i]) (void)hipGraphExecDestroy(w->graph[i]);
+    for (void* p : {w->bs[i], w->bt[i]})
+      if (p) (void)hipFree(p);
+    if (w->bgraph[i]) (void)hipGraphExecDestroy(w->bgraph[i]);
   }
   if (w->st) (void)hipFree(w->st);
   if (w->st_host) (void)hipHostFree(w->st_host);
+  if (w->bst) (void)hipFree(w->bst);
+  if (w->bst_host) (void)hipHostFree(w->bst_host);
   delete w;
   ctx->work = nullptr;
 }
@@ -439,7 +646,9 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
   const int inner = p.inner_prec;
   LQ_CHECK(inner == LQ_F64 || inner == LQ_F32 || inner == LQ_F16, LQ_EINVAL,
            "bad inner precision");
-  LQ_CHECK(p.solver == LQ_CGNR, LQ_EINVAL, "this solver kind is not available in this build");
+  LQ_CHECK(p.solver == LQ_CGNR || p.solver == LQ_BICGSTAB, LQ_EINVAL,
+           "solver kind not available through lq_solve (learned-preconditioner solvers take a "
+           "net: lq_solve_net)");
   const int maxiter = p.maxiter > 0 ? p.maxiter : 20000;
   const double delta = inner == LQ_F64 ? 0.0 : (p.delta > 0.0 ? p.delta : 0.1);
   const int check_every = p.check_every > 0 ? p.check_every : 8;
@@ -514,7 +723,7 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
         bool fb = false;
         int left = maxiter - ss.iterations;
         SolveStats inner_ss;
-        bool conv = run_cg(ctx, w, ss.fallback ? LQ_F64 : inner, frac * tol * bhat_norm,
+        bool conv = run_inner(ctx, w, p.solver, ss.fallback ? LQ_F64 : inner, frac * tol * bhat_norm,
                            ss.fallback ? 0.0 : delta, left, check_every, use_graph,
                            p.fault_inject, inner_ss, fb, prof);
         ss.iterations += inner_ss.iterations;

@@ -61,10 +61,10 @@ __device__ __forceinline__ double site_norm2(const C<R> v[12]) {
 }
 
 template <class PO, bool DAG>
-LQ_HOP_KERNEL(PO) void cg_k1(Geo g, const CGState* __restrict__ st, Field<PO> t,
+LQ_HOP_KERNEL(PO) void cg_k1(Geo g, const int* __restrict__ active, Field<PO> t,
                                               Field<PO> in, const typename PO::S* __restrict__ gauge,
                                               const typename PO::S* __restrict__ ainv) {
-  if (!st->active) return;
+  if (!*active) return;
   const int64_t s = xcd_block(blockIdx.x, gridDim.x) * SBLK + threadIdx.x;
   if (s >= g.vh) return;
   C<typename PO::R> acc[12], y[12];

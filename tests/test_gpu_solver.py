@@ -121,3 +121,40 @@ def test_config1_mixed_fp32_16x32(lq):
     err = np.linalg.norm((x32 - x64).reshape(-1)) / np.linalg.norm(x64.reshape(-1))
     say(f"fp64 {r64[0]}\nfp32 {r32[0]}\nmixed vs plain relative difference {err:.2e}")
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("inner", [0, 1, 2])
+def test_bicgstab_solves(lq, inner):
+    """BiCGStab on the Schur operator: 4^4 Haar Wilson against the direct
+    solve, and an 8^4 smooth clover lattice checked by the oracle residual."""
+    say(f"bicgstab inner={inner}")
+    dims, kappa, csw = (4, 4, 4, 4), 0.12, 0.0
+    u = fields.gauge_field(dims, "haar", fields.SEED_GAUGE)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x, rep = lat.solve(b, kappa, csw, 1e-10, solver=lq.BICGSTAB, inner_prec=inner)
+    assert oracle_residual(u, kappa, csw, x, b) <= 1e-10
+    xr = direct(u, dims, kappa, csw, b)
+    assert np.linalg.norm(x.reshape(-1) - xr) <= 16e-10 * np.linalg.norm(xr)
+    dims, kappa, csw = (8, 8, 8, 8), 0.135, 1.0
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 1)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 1)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x, rep = lat.solve(b, kappa, csw, 1e-10, solver=lq.BICGSTAB, inner_prec=inner)
+    say(f"  8^4 clover: {rep[0].iterations} iterations, {rep[0].reliable_updates} restarts")
+    assert oracle_residual(u, kappa, csw, x, b) <= 1e-10
+
+
+def test_bicgstab_fault_injection_falls_back(lq):
+    dims, kappa, csw = (8, 8, 8, 8), 0.135, 1.0
+    say("bicgstab with forced stagnation")
+    u = fields.gauge_field(dims, "smooth", 9)
+    b = fields.gaussian_spinor(dims, 10)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x, rep = lat.solve(b, kappa, csw, 1e-10, solver=lq.BICGSTAB, inner_prec=1, fault_inject=1,
+                       raise_on_noconv=False)
+    assert rep[0].fallback == 1
+    assert oracle_residual(u, kappa, csw, x, b) <= 1e-10
