@@ -68,7 +68,11 @@ typedef enum {
   LQ_ENAN = -6      /* NaN or Inf met in a reduction; report filled */
 } lq_status;
 
-typedef enum { LQ_F64 = 0, LQ_F32 = 1, LQ_F16 = 2 } lq_prec;
+/* LQ_F16X: FP16 with the right-hand sides of one parity interleaved per site
+ * (up to 16 RHS in one field; the layout of the matrix-core multi-RHS
+ * operator).  Accepted by lq_field_bytes, lq_spinor_to_device/_to_host
+ * (parity EVEN or ODD), lq_dslash and lq_schur. */
+typedef enum { LQ_F64 = 0, LQ_F32 = 1, LQ_F16 = 2, LQ_F16X = 3 } lq_prec;
 typedef enum { LQ_EVEN = 0, LQ_ODD = 1, LQ_FULL = 2 } lq_parity;
 typedef enum {
   LQ_CGNR = 0,         /* CG on Mhat^dagger Mhat (plain FP64 when inner_prec = F64) */
@@ -91,6 +95,8 @@ typedef struct {
                             -1 launch each kernel directly */
   int fault_inject;      /* tests only: 1 = force the inner solve to stagnate */
   int profile;           /* 1: time every inner-iteration kernel with HIP events (no graph) */
+  int batched;           /* 1: solve all nrhs (<= 16) together through the multi-RHS operator
+                            (CGNR, inner_prec F16): one operator application serves every RHS */
 } lq_solver_params;
 
 /* Kernels of one inner CG iteration, in launch order (report index). */

@@ -41,6 +41,14 @@ void check_parity(int parity, bool allow_full) {
 void check_prec(int prec) {
   LQ_CHECK(prec == LQ_F64 || prec == LQ_F32 || prec == LQ_F16, LQ_EINVAL, "bad precision");
 }
+// LQ_F16X (multi-RHS interleaved) fields: one parity, at most 16 RHS
+bool multi_rhs(int prec, int parity, int nrhs) {
+  if (prec != LQ_F16X) return false;
+  LQ_CHECK(parity == LQ_EVEN || parity == LQ_ODD, LQ_EINVAL,
+           "multi-RHS fields hold one parity");
+  LQ_CHECK(nrhs >= 1 && nrhs <= 16, LQ_EINVAL, "multi-RHS fields hold 1..16 right-hand sides");
+  return true;
+}
 
 }  // namespace
 
@@ -133,6 +141,7 @@ void lq_destroy(lq_ctx* ctx) {
   else (void)hipDeviceSynchronize();
   (void)hipStreamSynchronize(ctx->sstream);
   lq::free_work(ctx);
+  lq::free_mrhs_work(ctx);
   lq::free_clover(ctx);
   for (int p = 0; p < 3; ++p)
     if (ctx->gauge[p]) (void)hipFree(ctx->gauge[p]);
@@ -148,8 +157,9 @@ const char* lq_last_error(const lq_ctx* ctx) {
 
 size_t lq_field_bytes(const lq_ctx* ctx, int parity, int prec, int nrhs) {
   if (!ctx || (parity != LQ_EVEN && parity != LQ_ODD && parity != LQ_FULL) || prec < 0 ||
-      prec > 2 || nrhs < 1)
+      prec > 3 || nrhs < 1)
     return 0;
+  if (prec == LQ_F16X) return (parity == LQ_FULL || nrhs > 16) ? 0 : lq::mr_field_bytes(ctx, nrhs);
   return lq::field_bytes(ctx, parity, prec, nrhs);
 }
 
@@ -175,6 +185,17 @@ lq_status lq_spinor_to_device(lq_ctx* ctx, void* dev, const double* host, int pa
   return guarded(ctx, [&] {
     LQ_CHECK(dev && host && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
     check_parity(parity, true);
+    if (multi_rhs(prec, parity, nrhs)) {
+      const size_t hb = (size_t)ctx->geo.vh * 12 * 16;
+      double2* st = reinterpret_cast<double2*>(lq::staging(ctx, hb));
+      for (int r = 0; r < nrhs; ++r) {
+        LQ_HIP(hipMemcpyAsync(st, host + (size_t)r * ctx->geo.vh * 24, hb, hipMemcpyHostToDevice,
+                              ctx->cur));
+        lq::mrhs_pack(ctx, dev, st, parity, LQ_F16, nrhs, r);
+      }
+      LQ_HIP(hipStreamSynchronize(ctx->cur));
+      return;
+    }
     check_prec(prec);
     const int full = parity == LQ_FULL;
     const int64_t nsites = full ? ctx->V : ctx->geo.vh;
@@ -195,6 +216,17 @@ lq_status lq_spinor_to_host(lq_ctx* ctx, double* host, const void* dev, int pari
   return guarded(ctx, [&] {
     LQ_CHECK(dev && host && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
     check_parity(parity, true);
+    if (multi_rhs(prec, parity, nrhs)) {
+      const size_t hb = (size_t)ctx->geo.vh * 12 * 16;
+      double2* st = reinterpret_cast<double2*>(lq::staging(ctx, hb));
+      for (int r = 0; r < nrhs; ++r) {
+        lq::mrhs_unpack(ctx, st, dev, parity, LQ_F16, nrhs, r);
+        LQ_HIP(hipMemcpyAsync(host + (size_t)r * ctx->geo.vh * 24, st, hb, hipMemcpyDeviceToHost,
+                              ctx->cur));
+        LQ_HIP(hipStreamSynchronize(ctx->cur));
+      }
+      return;
+    }
     check_prec(prec);
     const int full = parity == LQ_FULL;
     const int64_t nsites = full ? ctx->V : ctx->geo.vh;
@@ -217,6 +249,11 @@ lq_status lq_dslash(lq_ctx* ctx, void* dev_out, const void* dev_in, int out_pari
     LQ_CHECK(dev_out && dev_in && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
     LQ_CHECK(dev_out != dev_in, LQ_EINVAL, "dslash cannot run in place");
     check_parity(out_parity, false);
+    if (multi_rhs(prec, out_parity, nrhs)) {
+      LQ_CHECK(ctx->gauge[LQ_F16], LQ_ESTATE, "no FP16 gauge field");
+      lq::mrhs_dslash(ctx, dev_out, dev_in, out_parity, dagger, nrhs);
+      return;
+    }
     check_prec(prec);
     const size_t fb = lq::field_bytes(ctx, LQ_EVEN, prec, 1);
     for (int r = 0; r < nrhs; ++r)
@@ -246,6 +283,10 @@ lq_status lq_schur(lq_ctx* ctx, void* dev_out, const void* dev_in, void* dev_tmp
     LQ_CHECK(dev_out && dev_in && dev_tmp && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
     LQ_CHECK(dev_out != dev_in && dev_tmp != dev_in && dev_tmp != dev_out, LQ_EINVAL,
              "schur needs three distinct buffers");
+    if (multi_rhs(prec, LQ_EVEN, nrhs)) {
+      lq::mrhs_schur(ctx, dev_out, dev_in, dev_tmp, dagger, nrhs);
+      return;
+    }
     check_prec(prec);
     const size_t fb = lq::field_bytes(ctx, LQ_EVEN, prec, 1);
     for (int r = 0; r < nrhs; ++r)

@@ -266,7 +266,8 @@ struct Clover {
   bool valid = false;
 };
 
-struct Work;  // solver work space (solver.hip)
+struct Work;    // solver work space (solver.hip)
+struct MRWork;  // batched multi-RHS solver work space (mrhs.hip)
 
 }  // namespace lq
 
@@ -284,6 +285,7 @@ struct lq_ctx {
   size_t staging_bytes = 0;
   void* red = nullptr;      // reduction scratch (partials + counter + result)
   lq::Work* work = nullptr;
+  lq::MRWork* mrwork = nullptr;
   std::string err;
   double bytes = 0.0;       // algorithmic bytes of every kernel launched so far
 };
@@ -325,6 +327,26 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
            int nrhs, double kappa, double csw, double tol, const lq_solver_params* params,
            lq_solve_report* report);
 void free_work(lq_ctx* ctx);
+
+// mrhs.hip: multi-RHS interleaved FP16 fields (lq_prec LQ_F16X) and the
+// matrix-core hopping term; batched CG helpers
+size_t mr_field_bytes(const lq_ctx* ctx, int nrhs);
+void mrhs_pack(lq_ctx* ctx, void* dev, const double2* src_dev, int parity, int prec, int nrhs,
+               int r);
+void mrhs_unpack(lq_ctx* ctx, double2* dst_dev, const void* dev, int parity, int prec, int nrhs,
+                 int r);
+void mrhs_dslash(lq_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int nrhs);
+void mrhs_schur(lq_ctx* ctx, void* out, const void* in, void* tmp, int dagger, int nrhs);
+MRWork* mrhs_work(lq_ctx* ctx, int nrhs);
+void free_mrhs_work(lq_ctx* ctx);
+void mrhs_iterate(lq_ctx* ctx, MRWork* w, int check_every, bool use_graph);
+void mrhs_state_upload(lq_ctx* ctx, MRWork* w);
+void mrhs_state_download(lq_ctx* ctx, MRWork* w);
+double mrhs_iteration_site_bytes(int nrhs);
+void mrhs_slot_from_single(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single64,
+                           int r, double a, double b);
+void mrhs_single_from_slot(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single64,
+                           int r, double a, double b);
 
 inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
 

@@ -1,0 +1,500 @@
+// Multi-right-hand-side operator and batched CG (up to 16 right-hand sides
+// sharing every operator application; the hopping term runs on the matrix
+// cores, see mrhs_kernels.h).
+//
+// Batched CG: independent CG recurrences on Mhat^+ Mhat x_r = Mhat^+ bhat_r,
+// one per right-hand side, with per-RHS alpha/beta on the device.  The
+// operator fields (p, q, t, s) are FP16 multi-RHS fields, the vectors x and
+// r FP32 multi-RHS fields; the solutions are held in FP64 per RHS and
+// refreshed by reliable updates (FP64 residual from the single-RHS FP64
+// operator), triggered when any RHS's normal residual fell by delta since
+// its last update.  A converged RHS is frozen (alpha = beta = 0).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "mrhs_kernels.h"
+#include "solver_kernels.h"
+
+namespace lq {
+
+namespace {
+
+// ---------------------------------------------------------------- layout kernels
+// host canonical half field of RHS r (rank t among the parity's sites) ->
+// multi-RHS field slot r
+template <class P>
+__global__ void mr_pack_kernel(Geo g, int parity, MField<P> f, const double2* __restrict__ src,
+                               int r) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.vh) return;
+  int x[4];
+  canonical_coords(g, 2 * t, x);
+  x[0] += (parity + x[0] + x[1] + x[2] + x[3]) & 1;
+  const int64_t s = cb_index(g, x);
+  double2 v[12];  // host order spin * 3 + colour
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = src[t * 12 + c];
+  double m = 0.0;
+  if constexpr (P::has_norm) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmax(m, fmax(fabs(v[c].x), fabs(v[c].y)));
+    f.norm[s * f.nrhs + r] = (float)m;
+  }
+  const double inv = P::has_norm ? (m > 0.0 ? 1.0 / m : 0.0) : 1.0;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double2 w = v[sp * 3 + a];
+      if constexpr (P::has_norm) {
+        __half2 h;
+        h.x = __half((_Float16)(w.x * inv));
+        h.y = __half((_Float16)(w.y * inv));
+        f.d[mr_idx(s, f.nrhs, r, a * 4 + sp)] = h;
+      } else {
+        st<P>(f.d, mr_idx(s, f.nrhs, r, a * 4 + sp),
+              C<typename P::R>{(typename P::R)w.x, (typename P::R)w.y});
+      }
+    }
+}
+
+template <class P>
+__global__ void mr_unpack_kernel(Geo g, int parity, MField<P> f, double2* __restrict__ dst, int r) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.vh) return;
+  int x[4];
+  canonical_coords(g, 2 * t, x);
+  x[0] += (parity + x[0] + x[1] + x[2] + x[3]) & 1;
+  const int64_t s = cb_index(g, x);
+  const double n = P::has_norm ? (double)f.norm[s * f.nrhs + r] : 1.0;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const C<typename P::R> w = ld<P>(f.d, mr_idx(s, f.nrhs, r, a * 4 + sp));
+      dst[t * 12 + sp * 3 + a] = make_double2(n * (double)w.re, n * (double)w.im);
+    }
+}
+
+// single-RHS device field (precision PS) <-> slot r of a multi-RHS field:
+// dst_slot = a * src + b * dst_slot (to_slot) or single = a * slot + b * single.
+// A zero coefficient drops its operand unread, so a = b = 0 clears the
+// destination whatever the other memory holds.
+template <class PS, class PM>
+__global__ void mr_axpby_slot_kernel(Geo g, MField<PM> m, Field<PS> f, int r, double a, double b,
+                                     int to_slot) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.vh) return;
+  const double cf = to_slot ? a : b, cm = to_slot ? b : a;  // coefficients of single, slot
+  C<typename PS::R> fv[12];  // spin * 3 + colour
+  double fn = 0.0;
+  if (cf != 0.0) fn = (double)load_raw<PS>(f, s, fv);
+  const double mn = (cm != 0.0 && PM::has_norm) ? (double)m.norm[s * m.nrhs + r] : 1.0;
+  double re[12], im[12];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = sp * 3 + c;
+      re[k] = 0.0;
+      im[k] = 0.0;
+      if (cf != 0.0) {
+        re[k] += cf * fn * (double)fv[k].re;
+        im[k] += cf * fn * (double)fv[k].im;
+      }
+      if (cm != 0.0) {
+        const C<typename PM::R> w = ld<PM>(m.d, mr_idx(s, m.nrhs, r, c * 4 + sp));
+        re[k] += cm * mn * (double)w.re;
+        im[k] += cm * mn * (double)w.im;
+      }
+    }
+  if (to_slot) {
+    double mx = 0.0;
+    if constexpr (PM::has_norm) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) mx = fmax(mx, fmax(fabs(re[k]), fabs(im[k])));
+      m.norm[s * m.nrhs + r] = (float)mx;
+    }
+    const double inv = PM::has_norm ? (mx > 0.0 ? 1.0 / mx : 0.0) : 1.0;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int k = sp * 3 + c;
+        st<PM>(m.d, mr_idx(s, m.nrhs, r, c * 4 + sp),
+               C<typename PM::R>{(typename PM::R)(inv * re[k]), (typename PM::R)(inv * im[k])});
+      }
+  } else {
+    C<typename PS::R> o[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[k] = C<typename PS::R>{(typename PS::R)re[k], (typename PS::R)im[k]};
+    store_spinor<PS>(f, s, o);
+  }
+}
+
+struct MRFinAlpha {
+  MRState* st;
+  __device__ void operator()(const double* tot) const {
+    if (!st->active) return;
+    for (int r = 0; r < st->nrhs; ++r) {
+      const double qq = tot[r];
+      st->qq[r] = qq;
+      if (!st->on[r]) {
+        st->alpha[r] = 0.0;
+      } else if (!(qq > 0.0) || !isfinite(qq)) {
+        st->alpha[r] = 0.0;
+        st->reason = R_NAN;
+        st->active = 0;
+      } else {
+        st->alpha[r] = st->rr[r] / qq;
+      }
+    }
+  }
+};
+
+struct MRFinBeta {
+  MRState* st;
+  __device__ void operator()(const double* tot) const {
+    if (!st->active) return;
+    st->iter += 1;
+    int reason = R_RUN;
+    for (int r = 0; r < st->nrhs; ++r) {
+      if (!st->on[r]) {
+        st->beta[r] = 0.0;
+        continue;
+      }
+      const double rr = tot[r];
+      if (!isfinite(rr)) {
+        reason = R_NAN;
+        continue;
+      }
+      st->beta[r] = rr / st->rr[r];
+      st->rr[r] = rr;
+      if (rr <= st->target2[r] || (st->delta2 > 0.0 && rr < st->delta2 * st->rr_max[r]))
+        reason = reason == R_RUN ? R_RELIABLE : reason;
+      if (rr > st->rr_max[r]) st->rr_max[r] = rr;
+    }
+    if (reason == R_RUN && st->iter >= st->maxiter) reason = R_MAXITER;
+    if (reason != R_RUN) {
+      st->reason = reason;
+      st->active = 0;
+    }
+  }
+};
+
+// per-RHS totals of per-block partials part[block][MR_MAX]
+template <class Fin>
+__global__ __launch_bounds__(256) void mr_finalize_kernel(const double* __restrict__ part,
+                                                          int nparts, int nrhs, double* result,
+                                                          Fin fin) {
+  __shared__ double sh[MR_MAX][16];
+  double t[MR_MAX];
+  for (int r = 0; r < MR_MAX; ++r) t[r] = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+    for (int r = 0; r < nrhs; ++r) t[r] += part[(int64_t)b * MR_MAX + r];
+  block_sum<MR_MAX>(t, sh);
+  if (threadIdx.x == 0) {
+    for (int r = 0; r < nrhs; ++r) result[r] = t[r];
+    fin(t);
+  }
+}
+
+// x_r += alpha_r p_r;  r_r -= alpha_r s_r;  partial |r_r|^2.  Thread per (site, RHS).
+__global__ __launch_bounds__(256) void mr_cg_update(Geo g, const MRState* __restrict__ mst,
+                                                    MField<P32> x, MField<P32> rv, MField<P16> p,
+                                                    MField<P16> sv, double* __restrict__ part) {
+  __shared__ double sh[MR_MAX][16];
+  if (!mst->active) return;
+  const int nrhs = x.nrhs;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = t / nrhs;
+  const int r = (int)(t - s * nrhs);
+  double v[MR_MAX];
+  for (int k = 0; k < MR_MAX; ++k) v[k] = 0.0;
+  if (s < g.vh) {
+    const float al = (float)mst->alpha[r];
+    const float pn = p.norm[s * nrhs + r], sn = sv.norm[s * nrhs + r];
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const int64_t i = mr_idx(s, nrhs, r, c);
+      C<float> xv = ld<P32>(x.d, i), rvv = ld<P32>(rv.d, i);
+      xv = xv + (al * pn) * ld<P16>(p.d, i);
+      rvv = rvv - (al * sn) * ld<P16>(sv.d, i);
+      st<P32>(x.d, i, xv);
+      st<P32>(rv.d, i, rvv);
+      acc += (double)rvv.re * rvv.re + (double)rvv.im * rvv.im;
+    }
+    // per-RHS slot without dynamic register indexing
+#pragma unroll
+    for (int k = 0; k < MR_MAX; ++k) v[k] = (k == r) ? acc : 0.0;
+  }
+  block_sum<MR_MAX>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < MR_MAX; ++k) part[blockIdx.x * MR_MAX + k] = v[k];
+}
+
+// p_r = r_r + beta_r p_r.  Thread per (site, RHS).
+__global__ __launch_bounds__(256) void mr_p_update(Geo g, const MRState* __restrict__ mst,
+                                                   MField<P16> p, MField<P32> rv) {
+  if (!mst->active) return;
+  const int nrhs = p.nrhs;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = t / nrhs;
+  const int r = (int)(t - s * nrhs);
+  if (s >= g.vh) return;
+  const float be = (float)mst->beta[r];
+  const float pn = p.norm[s * nrhs + r];
+  C<float> o[12];
+  float mx = 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const int64_t i = mr_idx(s, nrhs, r, c);
+    o[c] = ld<P32>(rv.d, i) + (be * pn) * ld<P16>(p.d, i);
+    mx = fmaxf(mx, fmaxf(fabsf(o[c].re), fabsf(o[c].im)));
+  }
+  const float inv = mx > 0.f ? 1.f / mx : 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) st<P16>(p.d, mr_idx(s, nrhs, r, c), inv * o[c]);
+  p.norm[s * nrhs + r] = mx;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host helpers
+size_t mr_field_bytes(const lq_ctx* ctx, int nrhs) { return mrhs_field_bytes(ctx->geo.nblk, LQ_F16, nrhs); }
+
+namespace {
+
+int mr_hop_grid(const Geo& g) { return grid_for(g.vh, MR_SITES_PER_BLOCK); }
+
+void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, const void* in,
+            const void* x, int nrhs, double* part) {
+  const Geo& g = ctx->geo;
+  MField<P16> fo = mfield_at<P16>(out, g.nblk, nrhs);
+  MField<P16> fi = mfield_at<P16>(const_cast<void*>(in), g.nblk, nrhs);
+  MField<P16> fx = mfield_at<P16>(const_cast<void*>(x ? x : in), g.nblk, nrhs);
+  auto* gp = reinterpret_cast<const __half2*>(ctx->gauge[LQ_F16]);
+  const __half2* cl = nullptr;
+  if (epi == MR_EPI_CLOVINV) cl = reinterpret_cast<const __half2*>(ctx->clov.ainv_oo[LQ_F16]);
+  if (epi == MR_EPI_SCHUR2) cl = reinterpret_cast<const __half2*>(ctx->clov.a_ee[LQ_F16]);
+  const float k2 = (float)(ctx->clov.kappa * ctx->clov.kappa);
+  const dim3 grid(mr_hop_grid(g)), blk(MR_BLK);
+  // algorithmic bytes: 8 links, in and out per RHS, clover table, x per RHS
+  double sb = 8 * link_site_bytes(LQ_F16) + 2.0 * nrhs * spinor_site_bytes(LQ_F16);
+  if (epi != MR_EPI_NONE) sb += clover_site_bytes(LQ_F16);
+  if (epi == MR_EPI_SCHUR2) sb += nrhs * spinor_site_bytes(LQ_F16);
+  ctx->bytes += sb * (double)g.vh;
+#define LQ_MR_LAUNCH(D, E)                                                                    \
+  hipLaunchKernelGGL((mrhs_hop_kernel<D, E>), grid, blk, 0, ctx->cur, g, p, active, fo, fi, fx, \
+                     gp, cl, k2, part)
+  if (dag) {
+    if (epi == MR_EPI_NONE) LQ_MR_LAUNCH(true, MR_EPI_NONE);
+    else if (epi == MR_EPI_CLOVINV) LQ_MR_LAUNCH(true, MR_EPI_CLOVINV);
+    else LQ_MR_LAUNCH(true, MR_EPI_SCHUR2);
+  } else {
+    if (epi == MR_EPI_NONE) LQ_MR_LAUNCH(false, MR_EPI_NONE);
+    else if (epi == MR_EPI_CLOVINV) LQ_MR_LAUNCH(false, MR_EPI_CLOVINV);
+    else LQ_MR_LAUNCH(false, MR_EPI_SCHUR2);
+  }
+#undef LQ_MR_LAUNCH
+  LQ_HIP(hipGetLastError());
+}
+
+
+}  // namespace
+
+void mrhs_pack(lq_ctx* ctx, void* dev, const double2* src_dev, int parity, int prec, int nrhs,
+               int r) {
+  const Geo& g = ctx->geo;
+  ctx->bytes += (double)g.vh * (192.0 + spinor_site_bytes(prec));
+  if (prec == LQ_F16)
+    hipLaunchKernelGGL(mr_pack_kernel<P16>, dim3(grid_for(g.vh, 256)), dim3(256), 0, ctx->cur, g,
+                       parity, mfield_at<P16>(dev, g.nblk, nrhs), src_dev, r);
+  else
+    hipLaunchKernelGGL(mr_pack_kernel<P32>, dim3(grid_for(g.vh, 256)), dim3(256), 0, ctx->cur, g,
+                       parity, mfield_at<P32>(dev, g.nblk, nrhs), src_dev, r);
+  LQ_HIP(hipGetLastError());
+}
+
+void mrhs_unpack(lq_ctx* ctx, double2* dst_dev, const void* dev, int parity, int prec, int nrhs,
+                 int r) {
+  const Geo& g = ctx->geo;
+  ctx->bytes += (double)g.vh * (192.0 + spinor_site_bytes(prec));
+  void* d = const_cast<void*>(dev);
+  if (prec == LQ_F16)
+    hipLaunchKernelGGL(mr_unpack_kernel<P16>, dim3(grid_for(g.vh, 256)), dim3(256), 0, ctx->cur,
+                       g, parity, mfield_at<P16>(d, g.nblk, nrhs), dst_dev, r);
+  else
+    hipLaunchKernelGGL(mr_unpack_kernel<P32>, dim3(grid_for(g.vh, 256)), dim3(256), 0, ctx->cur,
+                       g, parity, mfield_at<P32>(d, g.nblk, nrhs), dst_dev, r);
+  LQ_HIP(hipGetLastError());
+}
+
+void mrhs_dslash(lq_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int nrhs) {
+  mr_hop(ctx, out_parity, dagger, MR_EPI_NONE, nullptr, out, in, nullptr, nrhs, nullptr);
+}
+
+void mrhs_schur(lq_ctx* ctx, void* out, const void* in, void* tmp, int dagger, int nrhs) {
+  mr_hop(ctx, LQ_ODD, dagger, MR_EPI_CLOVINV, nullptr, tmp, in, nullptr, nrhs, nullptr);
+  mr_hop(ctx, LQ_EVEN, dagger, MR_EPI_SCHUR2, nullptr, out, tmp, in, nrhs, nullptr);
+}
+
+// ---------------------------------------------------------------- batched CG
+namespace {
+
+template <class PS, class PM>
+void slot_axpby(lq_ctx* ctx, void* mfield, int nrhs, void* single, int r, double a, double b,
+                int to_slot) {
+  const Geo& g = ctx->geo;
+  ctx->bytes += (double)g.vh * (spinor_site_bytes(PS::id) * (to_slot ? 1 : 2) +
+                                spinor_site_bytes(PM::id) * (to_slot ? 2 : 1));
+  hipLaunchKernelGGL((mr_axpby_slot_kernel<PS, PM>), dim3(grid_for(g.vh, 256)), dim3(256), 0,
+                     ctx->cur, g, mfield_at<PM>(mfield, g.nblk, nrhs),
+                     field_at<PS>(single, g.nblk), r, a, b, to_slot);
+  LQ_HIP(hipGetLastError());
+}
+
+void mr_launch_iteration(lq_ctx* ctx, MRWork* w) {
+  const Geo& g = ctx->geo;
+  const int n = w->nrhs;
+  const int* act = &w->st->active;
+  mr_hop(ctx, LQ_ODD, 0, MR_EPI_CLOVINV, act, w->t, w->p, nullptr, n, nullptr);
+  mr_hop(ctx, LQ_EVEN, 0, MR_EPI_SCHUR2, act, w->q, w->t, w->p, n, w->part);
+  hipLaunchKernelGGL(mr_finalize_kernel<MRFinAlpha>, dim3(1), dim3(256), 0, ctx->cur, w->part,
+                     mr_hop_grid(g), n, w->res, MRFinAlpha{w->st});
+  mr_hop(ctx, LQ_ODD, 1, MR_EPI_CLOVINV, act, w->t, w->q, nullptr, n, nullptr);
+  mr_hop(ctx, LQ_EVEN, 1, MR_EPI_SCHUR2, act, w->s, w->t, w->q, n, w->part);
+  const int64_t nt = g.vh * n;
+  const int ug = grid_for(nt, 256);
+  hipLaunchKernelGGL(mr_cg_update, dim3(ug), dim3(256), 0, ctx->cur, g, w->st,
+                     mfield_at<P32>(w->x, g.nblk, n), mfield_at<P32>(w->r, g.nblk, n),
+                     mfield_at<P16>(w->p, g.nblk, n), mfield_at<P16>(w->s, g.nblk, n), w->part);
+  hipLaunchKernelGGL(mr_finalize_kernel<MRFinBeta>, dim3(1), dim3(256), 0, ctx->cur, w->part, ug,
+                     n, w->res, MRFinBeta{w->st});
+  hipLaunchKernelGGL(mr_p_update, dim3(ug), dim3(256), 0, ctx->cur, g, w->st,
+                     mfield_at<P16>(w->p, g.nblk, n), mfield_at<P32>(w->r, g.nblk, n));
+  LQ_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+MRWork* mrhs_work(lq_ctx* ctx, int nrhs) {
+  MRWork* w = ctx->mrwork;
+  if (w && w->nrhs != nrhs) {
+    free_mrhs_work(ctx);
+    w = nullptr;
+  }
+  if (!w) {
+    w = new MRWork();
+    ctx->mrwork = w;
+    w->nrhs = nrhs;
+    w->nblk = ctx->geo.nblk;
+    const size_t f16 = mrhs_field_bytes(w->nblk, LQ_F16, nrhs);
+    const size_t f32 = mrhs_field_bytes(w->nblk, LQ_F32, nrhs);
+    for (void** pp : {&w->p, &w->q, &w->t, &w->s}) LQ_HIP(hipMalloc(pp, f16));
+    for (void** pp : {&w->x, &w->r}) LQ_HIP(hipMalloc(pp, f32));
+    const size_t nparts = (size_t)std::max(grid_for(ctx->geo.vh, MR_SITES_PER_BLOCK),
+                                           grid_for(ctx->geo.vh * nrhs, 256));
+    LQ_HIP(hipMalloc(&w->part, nparts * MR_MAX * sizeof(double)));
+    LQ_HIP(hipMalloc(&w->res, MR_MAX * sizeof(double)));
+    LQ_HIP(hipMalloc(&w->st, sizeof(MRState)));
+    LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->st_host), sizeof(MRState),
+                         hipHostMallocDefault));
+    const size_t f64 = parity_field_bytes(w->nblk, LQ_F64);
+    for (int r = 0; r < nrhs; ++r) {
+      void *b = nullptr, *x = nullptr, *bh = nullptr;
+      LQ_HIP(hipMalloc(&b, 2 * f64));
+      LQ_HIP(hipMalloc(&x, 2 * f64));
+      LQ_HIP(hipMalloc(&bh, f64));
+      w->b64.push_back(b);
+      w->x64.push_back(x);
+      w->bhat.push_back(bh);
+    }
+  }
+  return w;
+}
+
+void free_mrhs_work(lq_ctx* ctx) {
+  MRWork* w = ctx->mrwork;
+  if (!w) return;
+  for (void* p : {w->p, w->q, w->t, w->s, w->x, w->r})
+    if (p) (void)hipFree(p);
+  if (w->part) (void)hipFree(w->part);
+  if (w->res) (void)hipFree(w->res);
+  if (w->st) (void)hipFree(w->st);
+  if (w->st_host) (void)hipHostFree(w->st_host);
+  for (auto* v : {&w->b64, &w->x64, &w->bhat})
+    for (void* p : *v) (void)hipFree(p);
+  if (w->graph) (void)hipGraphExecDestroy(w->graph);
+  delete w;
+  ctx->mrwork = nullptr;
+}
+
+// Run the batched iteration until an update is due; returns the state.
+void mrhs_iterate(lq_ctx* ctx, MRWork* w, int check_every, bool use_graph) {
+  if (!use_graph) {
+    for (int i = 0; i < check_every; ++i) mr_launch_iteration(ctx, w);
+    return;
+  }
+  if (!w->graph || w->graph_iters != check_every || w->graph_k2 != ctx->clov.kappa) {
+    if (w->graph) {
+      (void)hipGraphExecDestroy(w->graph);
+      w->graph = nullptr;
+    }
+    hipGraph_t gr = nullptr;
+    const double bytes0 = ctx->bytes;
+    LQ_HIP(hipStreamBeginCapture(ctx->cur, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int i = 0; i < check_every; ++i) mr_launch_iteration(ctx, w);
+    } catch (...) {
+      (void)hipStreamEndCapture(ctx->cur, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      throw;
+    }
+    ctx->bytes = bytes0;  // capture launches nothing; replays are counted by iteration
+    LQ_HIP(hipStreamEndCapture(ctx->cur, &gr));
+    hipError_t e = hipGraphInstantiate(&w->graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    LQ_HIP(e);
+    w->graph_iters = check_every;
+    w->graph_k2 = ctx->clov.kappa;
+  }
+  LQ_HIP(hipGraphLaunch(w->graph, ctx->cur));
+}
+
+void mrhs_state_upload(lq_ctx* ctx, MRWork* w) {
+  LQ_HIP(hipMemcpyAsync(w->st, w->st_host, sizeof(MRState), hipMemcpyHostToDevice, ctx->cur));
+}
+void mrhs_state_download(lq_ctx* ctx, MRWork* w) {
+  LQ_HIP(hipMemcpyAsync(w->st_host, w->st, sizeof(MRState), hipMemcpyDeviceToHost, ctx->cur));
+  LQ_HIP(hipStreamSynchronize(ctx->cur));
+}
+
+// Bytes of one batched iteration per site (all RHS), for the accounting.
+double mrhs_iteration_site_bytes(int nrhs) {
+  const double L = link_site_bytes(LQ_F16), S = spinor_site_bytes(LQ_F16),
+               C = clover_site_bytes(LQ_F16), S32 = spinor_site_bytes(LQ_F32);
+  const double hop = 8 * L + 2.0 * nrhs * S + C;
+  return 2 * hop + 2 * (hop + nrhs * S)          // two A^-1 H, two A x - k2 H t
+         + nrhs * (4 * S32 + 2 * S)               // x, r read/write, p, s read
+         + nrhs * (S32 + 2 * S);                  // p = r + beta p
+}
+
+void mrhs_slot_from_single(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single64,
+                           int r, double a, double b) {
+  if (prec == LQ_F16)
+    slot_axpby<P64, P16>(ctx, mfield, w->nrhs, single64, r, a, b, 1);
+  else
+    slot_axpby<P64, P32>(ctx, mfield, w->nrhs, single64, r, a, b, 1);
+}
+void mrhs_single_from_slot(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single64,
+                           int r, double a, double b) {
+  if (prec == LQ_F16)
+    slot_axpby<P64, P16>(ctx, mfield, w->nrhs, single64, r, a, b, 0);
+  else
+    slot_axpby<P64, P32>(ctx, mfield, w->nrhs, single64, r, a, b, 0);
+}
+
+}  // namespace lq

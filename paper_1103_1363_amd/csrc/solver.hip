@@ -12,11 +12,13 @@
 // Fallback: a NaN/breakdown in the inner iteration, or five consecutive
 // reliable updates without halving the FP64 residual, hands the solve to
 // the plain FP64 iteration, started from the current FP64 solution.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 
 #include "bicgstab_kernels.h"
+#include "mrhs_kernels.h"
 #include "solver_kernels.h"
 
 namespace lq {
@@ -638,6 +640,262 @@ void free_work(lq_ctx* ctx) {
   ctx->work = nullptr;
 }
 
+// ------------------------------------------------------------ batched solve
+// All right-hand sides through the multi-RHS operator (mrhs.hip).  The FP64
+// part (sources, reliable updates, reconstruction, final residuals) uses the
+// single-RHS FP64 kernels on each RHS's own FP64 fields.
+namespace {
+
+void solve_batched(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x,
+                   const void* dev_b, int nrhs, double tol, const lq_solver_params& p,
+                   lq_solve_report* report) {
+  LQ_CHECK(nrhs <= MR_MAX, LQ_EINVAL, "batched solves take at most 16 right-hand sides");
+  LQ_CHECK(p.solver == LQ_CGNR, LQ_EINVAL, "batched solves use CG on the normal equations");
+  auto t0 = std::chrono::steady_clock::now();
+  const double bytes0 = ctx->bytes;
+  Work* w = work(ctx, LQ_F64);
+  MRWork* mw = mrhs_work(ctx, nrhs);
+  const int64_t nb = ctx->geo.nblk;
+  const int64_t nsite = ctx->V;
+  const size_t hb = (size_t)nsite * 12 * 16;
+  const size_t fb = 2 * parity_field_bytes(nb, LQ_F64);
+  const double kappa = ctx->clov.kappa;
+  const int maxiter = p.maxiter > 0 ? p.maxiter : 20000;
+  const double delta = p.delta > 0.0 ? p.delta : 0.1;
+  const int check_every = p.check_every > 0 ? p.check_every : 8;
+  const bool use_graph = p.use_graph >= 0;
+  void* bhat_own = w->bhat;
+  std::vector<double> b2(nrhs), bhn(nrhs), res2(nrhs, 0.0), schur2(nrhs, 0.0);
+  std::vector<int> done(nrhs, 0);
+  SolveStats ss;
+  // sources
+  for (int r = 0; r < nrhs; ++r) {
+    if (host_b) {
+      double2* stg = reinterpret_cast<double2*>(staging(ctx, hb));
+      LQ_HIP(hipMemcpyAsync(stg, host_b + (size_t)r * nsite * 24, hb, hipMemcpyHostToDevice,
+                            ctx->cur));
+      pack_spinor(ctx, mw->b64[r], stg, LQ_F64, LQ_FULL);
+    } else {
+      LQ_HIP(hipMemcpyAsync(mw->b64[r], reinterpret_cast<const char*>(dev_b) + r * fb, fb,
+                            hipMemcpyDeviceToDevice, ctx->cur));
+    }
+    w->b = mw->b64[r];
+    w->x = mw->x64[r];
+    w->bhat = mw->bhat[r];
+    b2[r] = nrm2(ctx, w->b) + nrm2(ctx, odd_half(w->b, nb));
+    clover_apply(ctx, w->to, odd_half(w->b, nb), LQ_ODD, 1, LQ_F64);
+    dslash(ctx, w->te, w->to, LQ_EVEN, 0, LQ_F64);
+    axpby64(ctx, w->bhat, 1.0, w->b, kappa, w->te);
+    bhn[r] = std::sqrt(nrm2(ctx, w->bhat));
+    zero<P64>(ctx, w->x);
+    zero<P64>(ctx, odd_half(w->x, nb));
+    if (b2[r] == 0.0) done[r] = 1;
+  }
+  MRState& h = *mw->st_host;
+  const double it_bytes = mrhs_iteration_site_bytes(nrhs) * (double)ctx->geo.vh;
+  double frac = 0.5;
+  bool fell_back = false;
+  for (int round = 0; round < 4; ++round) {
+    // (re)start every unfinished RHS from its FP64 residual
+    std::memset(&h, 0, sizeof(MRState));
+    h.nrhs = nrhs;
+    h.delta2 = delta * delta;
+    h.maxiter = maxiter;
+    h.iter = ss.iterations;
+    int n_on = 0;
+    std::vector<double> rt2(nrhs, 0.0);
+    for (int r = 0; r < nrhs; ++r) {
+      mrhs_slot_from_single(ctx, mw, mw->x, LQ_F32, w->r64, r, 0.0, 0.0);
+      if (done[r]) {
+        mrhs_slot_from_single(ctx, mw, mw->p, LQ_F16, w->r64, r, 0.0, 0.0);
+        mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->r64, r, 0.0, 0.0);
+        continue;
+      }
+      w->x = mw->x64[r];
+      w->bhat = mw->bhat[r];
+      rt2[r] = schur_residual(ctx, w, ss);
+      const double target = frac * tol * bhn[r];
+      if (rt2[r] <= target * target) {
+        mrhs_slot_from_single(ctx, mw, mw->p, LQ_F16, w->r64, r, 0.0, 0.0);
+        mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->r64, r, 0.0, 0.0);
+        continue;
+      }
+      schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
+      ss.dslash += 2;
+      const double rr = nrm2(ctx, w->rn64);
+      mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->rn64, r, 1.0, 0.0);
+      mrhs_slot_from_single(ctx, mw, mw->p, LQ_F16, w->rn64, r, 1.0, 0.0);
+      h.on[r] = 1;
+      h.rr[r] = rr;
+      h.rr_max[r] = rr;
+      // the inner test is on the normal residual: scale the target by the
+      // ratio of the normal to the Schur residual measured here
+      h.target2[r] = target * target * rr / rt2[r] * 0.25;
+      ++n_on;
+    }
+    if (n_on > 0) {
+      h.active = 1;
+      mrhs_state_upload(ctx, mw);
+      int counted = h.iter;
+      // stagnation, as in the single-RHS solve: every iterating RHS's inner
+      // residual must quarter within STALL_ITERS iterations, and its FP64
+      // residual must halve within five reliable updates
+      constexpr int STALL_ITERS = 200;
+      std::vector<int> ref_iter(nrhs, h.iter);
+      std::vector<double> ref_rr(h.rr, h.rr + nrhs);
+      std::vector<std::vector<double>> hist(nrhs);
+      for (int r = 0; r < nrhs; ++r)
+        if (h.on[r]) hist[r].push_back(rt2[r]);
+      for (;;) {
+        const double bsave = ctx->bytes;
+        mrhs_iterate(ctx, mw, check_every, use_graph);
+        ctx->bytes = bsave;
+        mrhs_state_download(ctx, mw);
+        ctx->bytes += (h.iter - counted) * it_bytes;
+        counted = h.iter;
+        bool stalled = false;
+        for (int r = 0; r < nrhs; ++r) {
+          if (!h.on[r]) continue;
+          if (h.rr[r] <= 0.25 * ref_rr[r]) {
+            ref_rr[r] = h.rr[r];
+            ref_iter[r] = h.iter;
+          } else if (h.iter - ref_iter[r] >= STALL_ITERS) {
+            stalled = true;
+          }
+        }
+        if (stalled) {
+          for (int r = 0; r < nrhs; ++r)
+            if (h.on[r] && !p.fault_inject)
+              mrhs_single_from_slot(ctx, mw, mw->x, LQ_F32, mw->x64[r], r, 1.0, 1.0);
+          fell_back = true;
+          break;
+        }
+        if (h.active) continue;
+        if (h.reason == R_NAN) {
+          fell_back = true;
+          break;
+        }
+        // reliable update of every RHS still iterating
+        for (int r = 0; r < nrhs; ++r) {
+          if (!h.on[r]) continue;
+          if (!p.fault_inject)
+            mrhs_single_from_slot(ctx, mw, mw->x, LQ_F32, mw->x64[r], r, 1.0, 1.0);
+          mrhs_slot_from_single(ctx, mw, mw->x, LQ_F32, w->r64, r, 0.0, 0.0);
+        }
+        n_on = 0;
+        for (int r = 0; r < nrhs; ++r) {
+          if (!h.on[r]) continue;
+          w->x = mw->x64[r];
+          w->bhat = mw->bhat[r];
+          const double t2 = schur_residual(ctx, w, ss);
+          const double target = frac * tol * bhn[r];
+          if (t2 <= target * target) {
+            h.on[r] = 0;
+            h.alpha[r] = h.beta[r] = 0.0;
+            mrhs_slot_from_single(ctx, mw, mw->p, LQ_F16, w->r64, r, 0.0, 0.0);
+            mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->r64, r, 0.0, 0.0);
+            continue;
+          }
+          hist[r].push_back(t2);
+          if (hist[r].size() > 6) hist[r].erase(hist[r].begin());
+          if (hist[r].size() == 6 &&
+              *std::min_element(hist[r].begin() + 1, hist[r].end()) > 0.25 * hist[r][0]) {
+            fell_back = true;
+            break;
+          }
+          schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
+          ss.dslash += 2;
+          const double rr_new = nrm2(ctx, w->rn64);
+          const double beta = (h.rr[r] > 0.0 && h.beta[r] > 0.0) ? h.beta[r] * rr_new / h.rr[r] : 0.0;
+          mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->rn64, r, 1.0, 0.0);
+          mrhs_slot_from_single(ctx, mw, mw->p, LQ_F16, w->rn64, r, 1.0, beta);
+          h.rr[r] = rr_new;
+          h.rr_max[r] = rr_new;
+          h.target2[r] = target * target * rr_new / t2 * 0.25;
+          ref_rr[r] = rr_new;
+          ref_iter[r] = h.iter;
+          ++n_on;
+        }
+        ss.reliable += 1;
+        if (fell_back || n_on == 0) break;
+        if (h.reason == R_MAXITER || h.iter >= maxiter) break;
+        h.active = 1;
+        h.reason = R_RUN;
+        mrhs_state_upload(ctx, mw);
+      }
+      ss.iterations = h.iter;
+    }
+    // finish with plain FP64 CG where the batched iteration broke down
+    if (fell_back) {
+      ss.fallback = 1;
+      for (int r = 0; r < nrhs; ++r) {
+        if (done[r]) continue;
+        w->b = mw->b64[r];
+        w->x = mw->x64[r];
+        w->bhat = mw->bhat[r];
+        SolveStats f_ss;
+        bool fb = false;
+        run_cg(ctx, w, LQ_F64, frac * tol * bhn[r], 0.0, maxiter, check_every, use_graph, 0,
+               f_ss, fb, nullptr);
+        ss.iterations += f_ss.iterations;
+      }
+    }
+    // full-system check per RHS
+    bool all_ok = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (done[r] && b2[r] == 0.0) continue;
+      w->b = mw->b64[r];
+      w->x = mw->x64[r];
+      w->bhat = mw->bhat[r];
+      res2[r] = reconstruct_and_residual(ctx, w, ss);
+      done[r] = res2[r] <= tol * tol * b2[r];
+      all_ok = all_ok && done[r];
+    }
+    if (all_ok || fell_back || ss.iterations >= maxiter) break;
+    frac *= 0.5;
+  }
+  ss.dslash += 4 * ss.iterations;
+  // results
+  for (int r = 0; r < nrhs; ++r) {
+    w->x = mw->x64[r];
+    w->bhat = mw->bhat[r];
+    if (host_x) {
+      double2* stg = reinterpret_cast<double2*>(staging(ctx, hb));
+      unpack_spinor(ctx, stg, w->x, LQ_F64, LQ_FULL);
+      LQ_HIP(hipMemcpyAsync(host_x + (size_t)r * nsite * 24, stg, hb, hipMemcpyDeviceToHost,
+                            ctx->cur));
+      LQ_HIP(hipStreamSynchronize(ctx->cur));
+    } else {
+      LQ_HIP(hipMemcpyAsync(reinterpret_cast<char*>(dev_x) + r * fb, w->x, fb,
+                            hipMemcpyDeviceToDevice, ctx->cur));
+    }
+    schur2[r] = b2[r] == 0.0 ? 0.0 : schur_residual(ctx, w, ss);
+  }
+  LQ_HIP(hipStreamSynchronize(ctx->cur));
+  w->bhat = bhat_own;
+  auto t1 = std::chrono::steady_clock::now();
+  bool ok = true;
+  for (int r = 0; r < nrhs; ++r) {
+    const bool conv = b2[r] == 0.0 || res2[r] <= tol * tol * b2[r];
+    ok = ok && conv;
+    if (report) {
+      lq_solve_report& rep = report[r];
+      std::memset(&rep, 0, sizeof(rep));
+      rep.iterations = ss.iterations;
+      rep.reliable_updates = ss.reliable;
+      rep.fallback = ss.fallback;
+      rep.dslash_calls = ss.dslash;
+      rep.true_residual = b2[r] > 0.0 ? std::sqrt(res2[r] / b2[r]) : 0.0;
+      rep.schur_residual = bhn[r] > 0.0 ? std::sqrt(schur2[r]) / bhn[r] : 0.0;
+      rep.seconds = std::chrono::duration<double>(t1 - t0).count();
+      rep.bytes = ctx->bytes - bytes0;  // whole batch
+    }
+  }
+  if (!ok) throw Error(LQ_ENOCONV, "a right-hand side of the batch did not reach the tolerance");
+}
+
+}  // namespace
+
 void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const void* dev_b,
            int nrhs, double kappa, double csw, double tol, const lq_solver_params* prm,
            lq_solve_report* report) {
@@ -659,6 +917,11 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
   ctx->cur = ctx->sstream;
   if (!ctx->clov.valid || ctx->clov.kappa != kappa || ctx->clov.csw != csw)
     build_clover(ctx, kappa, csw);
+  if (p.batched && nrhs > 1) {
+    LQ_CHECK(inner == LQ_F16, LQ_EINVAL, "batched solves run their inner iteration in FP16");
+    solve_batched(ctx, host_x, host_b, dev_x, dev_b, nrhs, tol, p, report);
+    return;
+  }
   Work* w = work(ctx, inner);
   work(ctx, LQ_F64);
   const int64_t nsite = ctx->V;

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LQ_LIBRARY") or os.path.join(_HERE, "liblq.so")
 
 F64, F32, F16 = 0, 1, 2
+F16X = 3  # multi-RHS interleaved FP16 fields (one parity, up to 16 right-hand sides)
 EVEN, ODD, FULL = 0, 1, 2
 CGNR, BICGSTAB, FGMRES_NET, FCG_NET = 0, 1, 2, 3
 PREC = {"f64": F64, "f32": F32, "f16": F16}
@@ -34,7 +35,8 @@ class LQError(RuntimeError):
 class SolverParams(ct.Structure):
     _fields_ = [("solver", ct.c_int), ("inner_prec", ct.c_int), ("maxiter", ct.c_int),
                 ("delta", ct.c_double), ("restart", ct.c_int), ("check_every", ct.c_int),
-                ("use_graph", ct.c_int), ("fault_inject", ct.c_int), ("profile", ct.c_int)]
+                ("use_graph", ct.c_int), ("fault_inject", ct.c_int), ("profile", ct.c_int),
+                ("batched", ct.c_int)]
 
 
 class SolveReport(ct.Structure):
@@ -168,6 +170,7 @@ class Lattice:
                            device="cuda")
 
     def to_device(self, host, parity, prec, out=None):
+        """Host (nrhs?, sites, 4, 3) complex128 -> new (or given) device field."""
         host = np.ascontiguousarray(host, dtype=np.complex128)
         nsite = self.volume if parity == FULL else self.volume // 2
         nrhs = host.size // (nsite * 12)
@@ -225,14 +228,15 @@ class Lattice:
     # -- solver ---------------------------------------------------------
     def solve(self, b, kappa, csw, tol=1e-10, solver=CGNR, inner_prec=F64, maxiter=0,
               delta=0.0, restart=0, check_every=0, use_graph=0, fault_inject=0,
-              profile=0, raise_on_noconv=True):
-        """Solve M x = b on the full lattice; b has shape (nrhs?, V-sites..., 4, 3)."""
+              profile=0, batched=0, raise_on_noconv=True):
+        """Solve M x = b on the full lattice; b has shape (nrhs?, V-sites..., 4, 3).
+        batched=1 runs all right-hand sides through the multi-RHS operator."""
         b = np.ascontiguousarray(b, dtype=np.complex128)
         nrhs = b.size // (self.volume * 12)
         assert nrhs * self.volume * 12 == b.size
         x = np.zeros_like(b)
         p = SolverParams(solver, inner_prec, maxiter, delta, restart, check_every, use_graph,
-                         fault_inject, profile)
+                         fault_inject, profile, batched)
         reps = (SolveReport * nrhs)()
         rc = self._L.lq_solve(self._h, _dptr(x.view(np.float64)), _dptr(b.view(np.float64)),
                               nrhs, float(kappa), float(csw), float(tol), ct.byref(p), reps)
@@ -243,10 +247,11 @@ class Lattice:
 
     def solve_device(self, dev_x, dev_b, kappa, csw, tol=1e-10, nrhs=1, solver=CGNR,
                      inner_prec=F64, maxiter=0, delta=0.0, restart=0, check_every=0,
-                     use_graph=0, fault_inject=0, profile=0, raise_on_noconv=True):
+                     use_graph=0, fault_inject=0, profile=0, batched=0,
+                     raise_on_noconv=True):
         """Solve with device-resident full-lattice FP64 fields (see lq_solve_device)."""
         p = SolverParams(solver, inner_prec, maxiter, delta, restart, check_every, use_graph,
-                         fault_inject, profile)
+                         fault_inject, profile, batched)
         reps = (SolveReport * nrhs)()
         rc = self._L.lq_solve_device(self._h, ct.c_void_p(dev_x.data_ptr()),
                                      ct.c_void_p(dev_b.data_ptr()), nrhs, float(kappa),

@@ -1,0 +1,188 @@
+"""GPU parity of the multi-right-hand-side operator (FP16 interleaved fields,
+hopping term on the matrix cores) and of the batched CG against the FP64
+oracle, through the C ABI.
+
+The operator is checked RHS by RHS against the oracle's hopping term and
+Schur operator on the unrounded FP64 inputs, for a full batch of 16, the
+12 spin-colour RHS of a propagator and ragged batches, on lattices whose
+half volume leaves a ragged last block of sites; the batched solver's
+solutions are checked by the oracle's own residual of the full system.
+"""
+import numpy as np
+import pytest
+
+from gen import fields
+from oracle import dirac, evenodd
+from tests.gpu_common import TOL, case, rel, say
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(4, 4, 4, 4), (6, 2, 2, 2), (10, 6, 4, 6), (16, 16, 16, 32)]
+TOL16 = TOL[2]
+
+
+@pytest.fixture(scope="module")
+def lq():
+    from paper_1103_1363_amd import lq as _lq
+    return _lq
+
+
+def spinors(dims, nrhs, seed=7):
+    full = fields.gaussian_spinor(dims, fields.SEED_SOURCE + seed, nrhs=nrhs)
+    halves = [evenodd.split(full[r], dims) for r in range(nrhs)]
+    return np.stack([h[0] for h in halves]), np.stack([h[1] for h in halves])
+
+
+def lattice(lq, dims, kind="smooth", seed=0):
+    u, _, _, _ = case(dims, kind, seed)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    return lat, u
+
+
+CASES = [(d, n) for d in DIMS[:3] for n in (16, 12, 5, 1)] + [(DIMS[3], 12)]
+
+
+@pytest.mark.parametrize("dims,nrhs", CASES)
+def test_mrhs_dslash_parity(lq, dims, nrhs):
+    say(f"mrhs dslash parity dims={dims} nrhs={nrhs}")
+    lat, u = lattice(lq, dims, "haar" if dims == (4, 4, 4, 4) else "smooth")
+    wc = evenodd.WilsonClover(u, 0.12, 0.0)
+    e, o = spinors(dims, nrhs)
+    for out_par, src in ((evenodd.EVEN, o), (evenodd.ODD, e)):
+        din = lat.to_device(src, 1 - out_par, lq.F16X)
+        dout = lat.new_field(out_par, lq.F16X, nrhs)
+        for dag in (False, True):
+            lat.dslash(dout, din, out_par, dag, lq.F16X, nrhs)
+            got = lat.to_host(dout, out_par, lq.F16X, nrhs).reshape((nrhs,) + src.shape[1:])
+            for r in range(nrhs):
+                ref = wc.hop_block(src[r], out_par, dagger=dag)
+                err = rel(got[r], ref)
+                assert err <= TOL16, (dims, nrhs, out_par, dag, r, err)
+
+
+def test_mrhs_dslash_scale_and_locality(lq):
+    """RHS of very different magnitudes and a point source in one batch:
+    every RHS keeps its own relative accuracy (per-site, per-RHS scaling)."""
+    dims = (8, 4, 4, 8)
+    say(f"mrhs dslash scales dims={dims}")
+    lat, u = lattice(lq, dims, "haar", seed=1)
+    wc = evenodd.WilsonClover(u, 0.12, 0.0)
+    e, o = spinors(dims, 6, seed=9)
+    scale = np.array([1.0, 1e-12, 1e6, 1e-30, 3.0, 1.0])
+    o = o * scale[:, None, None, None]
+    o[5] = 0.0
+    o[5][3, 2, 1] = 1.0  # one odd site, one spin-colour component
+    din = lat.to_device(o, evenodd.ODD, lq.F16X)
+    dout = lat.new_field(evenodd.EVEN, lq.F16X, 6)
+    lat.dslash(dout, din, evenodd.EVEN, False, lq.F16X, 6)
+    got = lat.to_host(dout, evenodd.EVEN, lq.F16X, 6)
+    for r in range(6):
+        ref = wc.hop_block(o[r], evenodd.EVEN)
+        err = rel(got[r], ref)
+        assert err <= TOL16, (r, scale[r], err)
+
+
+def test_mrhs_roundtrip(lq):
+    dims = (10, 6, 4, 6)
+    lat, _ = lattice(lq, dims)
+    e, _ = spinors(dims, 7, seed=3)
+    d = lat.to_device(e, evenodd.EVEN, lq.F16X)
+    assert d.numel() == lat.field_bytes(evenodd.EVEN, lq.F16X, 7)
+    got = lat.to_host(d, evenodd.EVEN, lq.F16X, 7)
+    for r in range(7):
+        # FP16 with a per-site scale: half an ulp of 2^-10 relative to the site maximum
+        assert rel(got[r], e[r]) <= 2.0 ** -11, r
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (10, 6, 4, 6), (16, 16, 16, 32)])
+def test_mrhs_schur_parity(lq, dims):
+    kappa, csw = 0.13, 1.0
+    nrhs = 12
+    say(f"mrhs schur parity dims={dims}")
+    lat, u = lattice(lq, dims, "smooth", seed=1)
+    lat.set_clover(kappa, csw)
+    wc = evenodd.WilsonClover(u, kappa, csw)
+    e, _ = spinors(dims, nrhs, seed=5)
+    din = lat.to_device(e, evenodd.EVEN, lq.F16X)
+    dout = lat.new_field(evenodd.EVEN, lq.F16X, nrhs)
+    tmp = lat.new_field(evenodd.ODD, lq.F16X, nrhs)
+    for dag in (False, True):
+        lat.schur(dout, din, tmp, dag, lq.F16X, nrhs)
+        got = lat.to_host(dout, evenodd.EVEN, lq.F16X, nrhs)
+        for r in range(nrhs):
+            ref = wc.schur(e[r], dagger=dag)
+            err = rel(got[r], ref)
+            assert err <= TOL16, (dims, dag, r, err)
+
+
+def test_mrhs_rejects_bad_shapes(lq):
+    dims = (4, 4, 4, 4)
+    lat, _ = lattice(lq, dims)
+    assert lat.field_bytes(evenodd.EVEN, lq.F16X, 17) == 0
+    assert lat.field_bytes(lq.FULL, lq.F16X, 4) == 0
+    a = lat.new_field(evenodd.EVEN, lq.F16X, 16)
+    b = lat.new_field(evenodd.EVEN, lq.F16X, 16)
+    with pytest.raises(lq.LQError):
+        lat.dslash(a, b, evenodd.EVEN, False, lq.F16X, 17)
+    with pytest.raises(lq.LQError):
+        lat.dslash(a, b, lq.FULL, False, lq.F16X, 4)
+
+
+def oracle_residuals(u, kappa, csw, x, b):
+    wc = evenodd.WilsonClover(u, kappa, csw)
+    return [dirac.norm(b[r] - wc.M(x[r])) / dirac.norm(b[r]) for r in range(b.shape[0])]
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 16, 32)])
+def test_batched_solve_point_sources(lq, dims):
+    """The 12 spin-colour point sources of a propagator, solved together."""
+    kappa, csw, tol = 0.135, 1.0, 1e-10
+    say(f"batched solve 12 point sources dims={dims}")
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 1)
+    b = fields.point_sources_12(dims)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x, reps = lat.solve(b, kappa, csw, tol, inner_prec=lq.F16, batched=1)
+    res = oracle_residuals(u, kappa, csw, x, b)
+    say(f"  iterations={reps[0].iterations} updates={reps[0].reliable_updates} "
+        f"fallback={reps[0].fallback} max_res={max(res):.3e}")
+    assert max(res) <= tol, res
+    assert reps[0].fallback == 0
+    for r in range(12):
+        assert abs(reps[r].true_residual - res[r]) <= 0.1 * res[r] + 1e-14
+
+
+def test_batched_matches_sequential_and_zero_rhs(lq):
+    """Ragged batch (5 RHS, one of them zero): same solutions as one-by-one
+    FP64 solves, within the tolerance, and x = 0 for b = 0."""
+    dims, kappa, csw, tol = (10, 6, 4, 6), 0.135, 1.0, 1e-10
+    say(f"batched vs sequential dims={dims}")
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 1)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 11, nrhs=5)
+    b[3] = 0.0
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    xb, reps = lat.solve(b, kappa, csw, tol, inner_prec=lq.F16, batched=1)
+    xs, _ = lat.solve(b[[0, 1, 2, 4]], kappa, csw, 1e-12, inner_prec=lq.F64)
+    assert np.all(xb[3] == 0)
+    for k, r in enumerate([0, 1, 2, 4]):
+        err = np.linalg.norm((xb[r] - xs[k]).reshape(-1)) / np.linalg.norm(xs[k].reshape(-1))
+        assert err <= 1e3 * tol, (r, err)  # cond(M) tol bound
+    res = oracle_residuals(u, kappa, csw, xb[[0, 1, 2, 4]], b[[0, 1, 2, 4]])
+    assert max(res) <= tol, res
+
+
+def test_batched_fault_injection_falls_back(lq):
+    """With the inner corrections withheld the batched solve stagnates; the
+    stagnation test hands every RHS to the FP64 CG, which converges."""
+    dims, kappa, csw, tol = (4, 4, 4, 4), 0.12, 1.0, 1e-10
+    say("batched fault injection")
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 1)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 12, nrhs=3)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x, reps = lat.solve(b, kappa, csw, tol, inner_prec=lq.F16, batched=1, fault_inject=1)
+    assert reps[0].fallback == 1
+    res = oracle_residuals(u, kappa, csw, x, b)
+    assert max(res) <= tol, res
