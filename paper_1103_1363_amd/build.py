@@ -24,6 +24,8 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+    # matrix-core results in ordinary VGPRs (no accumulator-register copies)
+    "-Xarch_device", "-mllvm=-amdgpu-mfma-vgpr-form",
     "-I" + os.path.join(HERE, "..", "include"),
 ]
 

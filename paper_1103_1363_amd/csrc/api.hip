@@ -142,6 +142,7 @@ void lq_destroy(lq_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->sstream);
   lq::free_work(ctx);
   lq::free_mrhs_work(ctx);
+  lq::free_mrhs_tables(ctx);
   lq::free_clover(ctx);
   for (int p = 0; p < 3; ++p)
     if (ctx->gauge[p]) (void)hipFree(ctx->gauge[p]);

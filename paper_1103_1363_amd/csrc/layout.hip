@@ -203,6 +203,7 @@ void upload_gauge(lq_ctx* ctx, const double* host_U) {
   }
   ctx->have_gauge = true;
   ctx->clov.valid = false;
+  ctx->mr_links_ok = ctx->mr_clov_ok = false;
 }
 
 void pack_spinor(lq_ctx* ctx, void* dev, const double2* src, int prec, int parity) {

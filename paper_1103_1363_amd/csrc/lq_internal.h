@@ -286,6 +286,11 @@ struct lq_ctx {
   void* red = nullptr;      // reduction scratch (partials + counter + result)
   lq::Work* work = nullptr;
   lq::MRWork* mrwork = nullptr;
+  // FP16 site-major operator copies of the multi-RHS kernels (mrhs.hip)
+  void* mr_links = nullptr;
+  void* mr_nbr = nullptr;  // neighbour table (geometry only)
+  void* mr_clov[2] = {nullptr, nullptr};  // A_ee (even sites), A_oo^-1 (odd sites)
+  bool mr_links_ok = false, mr_clov_ok = false;
   std::string err;
   double bytes = 0.0;       // algorithmic bytes of every kernel launched so far
 };
@@ -339,6 +344,8 @@ void mrhs_dslash(lq_ctx* ctx, void* out, const void* in, int out_parity, int dag
 void mrhs_schur(lq_ctx* ctx, void* out, const void* in, void* tmp, int dagger, int nrhs);
 MRWork* mrhs_work(lq_ctx* ctx, int nrhs);
 void free_mrhs_work(lq_ctx* ctx);
+void mrhs_tables(lq_ctx* ctx, bool clover);  // build the FP16 operator copies if stale
+void free_mrhs_tables(lq_ctx* ctx);
 void mrhs_iterate(lq_ctx* ctx, MRWork* w, int check_every, bool use_graph);
 void mrhs_state_upload(lq_ctx* ctx, MRWork* w);
 void mrhs_state_download(lq_ctx* ctx, MRWork* w);

@@ -77,6 +77,72 @@ __global__ void mr_unpack_kernel(Geo g, int parity, MField<P> f, double2* __rest
     }
 }
 
+// Neighbour table of the multi-RHS kernels: for site s of parity p the
+// device numbers of its eight neighbours (x+0, x-0, x+1, ..., x-3), with
+// bit 31 set where the hop crosses the antiperiodic time boundary.
+__global__ void mr_nbr_kernel(Geo g, int* __restrict__ out) {
+  const int64_t nsite = g.nblk * 64;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (p, s)
+  if (t >= 2 * nsite) return;
+  const int p = t >= nsite ? 1 : 0;
+  const int64_t s = t - p * nsite;
+  int* o = out + t * 8;
+  if (s >= g.vh) {  // padding sites: harmless in-range entries
+    for (int h = 0; h < 8; ++h) o[h] = 0;
+    return;
+  }
+  int l[4], tc[4];
+  site_local(g, p, s, l, tc);
+  const int x3 = tc[3] * g.T[3] + l[3];
+  for (int mu = 0; mu < 4; ++mu) {
+    const int64_t f = neighbour(g, s, l, tc, mu, true), b = neighbour(g, s, l, tc, mu, false);
+    const bool ff = mu == 3 && g.apt && x3 == g.L[3] - 1;
+    const bool fb = mu == 3 && g.apt && x3 == 0;
+    o[2 * mu] = (int)f | (ff ? (int)0x80000000 : 0);
+    o[2 * mu + 1] = (int)b | (fb ? (int)0x80000000 : 0);
+  }
+}
+
+// FP16 site-major copy of the links: all nine entries of U_mu(s), row 2
+// rebuilt from the FP64 compressed field.
+__global__ void mr_links_kernel(Geo g, const double2* __restrict__ g64, unsigned* __restrict__ out) {
+  const int64_t nsite = g.nblk * 64;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (p, s, mu)
+  if (t >= 2 * nsite * 4) return;
+  const int mu = (int)(t & 3);
+  const int64_t ps = t >> 2;
+  const int p = ps >= nsite ? 1 : 0;
+  const int64_t s = ps - p * nsite;
+  C<double> u[9];
+  load_link<P64>(g64, g.nblk, p, mu, s, u);
+#pragma unroll
+  for (int e = 0; e < 9; ++e)
+    out[t * 9 + e] =
+        __builtin_bit_cast(unsigned, mr_half2{(_Float16)u[e].re, (_Float16)u[e].im});
+}
+
+// FP16 site-major copy of a clover table (36 complex per site: per block
+// three packed diagonal pairs then the upper triangle) with the diagonal
+// unpacked to (d_k, 0).
+__global__ void mr_clov_kernel(Geo g, const double2* __restrict__ c64, unsigned* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.nblk * 64) return;
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    unsigned* o = out + s * MR_CLOV_SITE + cb * MR_CLOV_BLOCK;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double2 v = c64[clov_idx(s, 18 * cb + (k >> 1))];
+      o[k] = __builtin_bit_cast(unsigned, mr_half2{(_Float16)((k & 1) ? v.y : v.x), (_Float16)0});
+    }
+#pragma unroll
+    for (int t = 0; t < 15; ++t) {
+      const double2 v = c64[clov_idx(s, 18 * cb + 3 + t)];
+      o[6 + t] = __builtin_bit_cast(unsigned, mr_half2{(_Float16)v.x, (_Float16)v.y});
+    }
+  }
+}
+
 // single-RHS device field (precision PS) <-> slot r of a multi-RHS field:
 // dst_slot = a * src + b * dst_slot (to_slot) or single = a * slot + b * single.
 // A zero coefficient drops its operand unread, so a = b = 0 clears the
@@ -272,23 +338,25 @@ int mr_hop_grid(const Geo& g) { return grid_for(g.vh, MR_SITES_PER_BLOCK); }
 void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, const void* in,
             const void* x, int nrhs, double* part) {
   const Geo& g = ctx->geo;
+  LQ_CHECK(ctx->mr_links_ok && ctx->mr_nbr && (epi == MR_EPI_NONE || ctx->mr_clov_ok),
+           LQ_ESTATE, "multi-RHS operator tables not built");
   MField<P16> fo = mfield_at<P16>(out, g.nblk, nrhs);
   MField<P16> fi = mfield_at<P16>(const_cast<void*>(in), g.nblk, nrhs);
   MField<P16> fx = mfield_at<P16>(const_cast<void*>(x ? x : in), g.nblk, nrhs);
-  auto* gp = reinterpret_cast<const __half2*>(ctx->gauge[LQ_F16]);
-  const __half2* cl = nullptr;
-  if (epi == MR_EPI_CLOVINV) cl = reinterpret_cast<const __half2*>(ctx->clov.ainv_oo[LQ_F16]);
-  if (epi == MR_EPI_SCHUR2) cl = reinterpret_cast<const __half2*>(ctx->clov.a_ee[LQ_F16]);
+  auto* lk = reinterpret_cast<const unsigned*>(ctx->mr_links);
+  auto* nb = reinterpret_cast<const int*>(ctx->mr_nbr);
+  const unsigned* cl = nullptr;
+  if (epi != MR_EPI_NONE) cl = reinterpret_cast<const unsigned*>(ctx->mr_clov[p]);
   const float k2 = (float)(ctx->clov.kappa * ctx->clov.kappa);
   const dim3 grid(mr_hop_grid(g)), blk(MR_BLK);
-  // algorithmic bytes: 8 links, in and out per RHS, clover table, x per RHS
+  // algorithmic bytes: 8 links (12 reals), in and out per RHS, clover table, x per RHS
   double sb = 8 * link_site_bytes(LQ_F16) + 2.0 * nrhs * spinor_site_bytes(LQ_F16);
   if (epi != MR_EPI_NONE) sb += clover_site_bytes(LQ_F16);
   if (epi == MR_EPI_SCHUR2) sb += nrhs * spinor_site_bytes(LQ_F16);
   ctx->bytes += sb * (double)g.vh;
 #define LQ_MR_LAUNCH(D, E)                                                                    \
   hipLaunchKernelGGL((mrhs_hop_kernel<D, E>), grid, blk, 0, ctx->cur, g, p, active, fo, fi, fx, \
-                     gp, cl, k2, part)
+                     lk, cl, nb, k2, part)
   if (dag) {
     if (epi == MR_EPI_NONE) LQ_MR_LAUNCH(true, MR_EPI_NONE);
     else if (epi == MR_EPI_CLOVINV) LQ_MR_LAUNCH(true, MR_EPI_CLOVINV);
@@ -301,7 +369,6 @@ void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, 
 #undef LQ_MR_LAUNCH
   LQ_HIP(hipGetLastError());
 }
-
 
 }  // namespace
 
@@ -332,11 +399,56 @@ void mrhs_unpack(lq_ctx* ctx, double2* dst_dev, const void* dev, int parity, int
   LQ_HIP(hipGetLastError());
 }
 
+void mrhs_tables(lq_ctx* ctx, bool clover) {
+  const Geo& g = ctx->geo;
+  const int64_t nsite = g.nblk * 64;
+  LQ_CHECK(g.vh < ((int64_t)1 << 31), LQ_EINVAL, "lattice too large for the multi-RHS kernels");
+  if (!ctx->mr_nbr) {  // depends on the geometry only
+    LQ_HIP(hipMalloc(&ctx->mr_nbr, (size_t)nsite * 2 * 8 * 4));
+    hipLaunchKernelGGL(mr_nbr_kernel, dim3(grid_for(2 * nsite, 256)), dim3(256), 0, ctx->cur, g,
+                       (int*)ctx->mr_nbr);
+    LQ_HIP(hipGetLastError());
+  }
+  if (!ctx->mr_links_ok) {
+    LQ_CHECK(ctx->have_gauge, LQ_ESTATE, "no gauge field uploaded");
+    if (!ctx->mr_links) LQ_HIP(hipMalloc(&ctx->mr_links, (size_t)nsite * 2 * 4 * 9 * 4));
+    const int64_t n = nsite * 2 * 4;
+    hipLaunchKernelGGL(mr_links_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur, g,
+                       (const double2*)ctx->gauge[LQ_F64], (unsigned*)ctx->mr_links);
+    LQ_HIP(hipGetLastError());
+    ctx->mr_links_ok = true;
+  }
+  if (clover && !ctx->mr_clov_ok) {
+    LQ_CHECK(ctx->clov.valid, LQ_ESTATE, "no clover term (call lq_set_clover)");
+    const void* src[2] = {ctx->clov.a64[LQ_EVEN], ctx->clov.ainv64[LQ_ODD]};
+    for (int p = 0; p < 2; ++p) {
+      if (!ctx->mr_clov[p]) LQ_HIP(hipMalloc(&ctx->mr_clov[p], (size_t)nsite * MR_CLOV_SITE * 4));
+      hipLaunchKernelGGL(mr_clov_kernel, dim3(grid_for(nsite, 256)), dim3(256), 0, ctx->cur, g,
+                         (const double2*)src[p], (unsigned*)ctx->mr_clov[p]);
+      LQ_HIP(hipGetLastError());
+    }
+    ctx->mr_clov_ok = true;
+  }
+}
+
+void free_mrhs_tables(lq_ctx* ctx) {
+  if (ctx->mr_nbr) (void)hipFree(ctx->mr_nbr);
+  ctx->mr_nbr = nullptr;
+  if (ctx->mr_links) (void)hipFree(ctx->mr_links);
+  for (void* c : ctx->mr_clov)
+    if (c) (void)hipFree(c);
+  ctx->mr_links = nullptr;
+  ctx->mr_clov[0] = ctx->mr_clov[1] = nullptr;
+  ctx->mr_links_ok = ctx->mr_clov_ok = false;
+}
+
 void mrhs_dslash(lq_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int nrhs) {
+  mrhs_tables(ctx, false);
   mr_hop(ctx, out_parity, dagger, MR_EPI_NONE, nullptr, out, in, nullptr, nrhs, nullptr);
 }
 
 void mrhs_schur(lq_ctx* ctx, void* out, const void* in, void* tmp, int dagger, int nrhs) {
+  mrhs_tables(ctx, true);
   mr_hop(ctx, LQ_ODD, dagger, MR_EPI_CLOVINV, nullptr, tmp, in, nullptr, nrhs, nullptr);
   mr_hop(ctx, LQ_EVEN, dagger, MR_EPI_SCHUR2, nullptr, out, tmp, in, nrhs, nullptr);
 }

@@ -5,21 +5,33 @@
 //   data[(site * nrhs + r) * 12 + colour * 4 + spin],  FP16 norms[site * nrhs + r].
 // A wavefront handles one site at a time for all right-hand sides.
 //
-// For one site and one hop, the contribution to the output of every RHS is
-//   out[s_out, a, r] += sum_{s_h, b} R[s_out, s_h] U'[a, b] h[s_h, b, r],
-// with h the spin-projected neighbour (two spins), U' the link (or its
-// adjoint) and R the 4x2 spin reconstruction (entries 0, +-1, +-i).  Written
-// with real and imaginary parts separated this is a real (24 x 12) x
-// (12 x nrhs) product: rows (a, s_out, re/im), columns r, contraction over
-// (b, s_h, re/im).  Two v_mfma_f32_16x16x16f16 (rows 0-15 and 16-23) per
-// hop accumulate all eight hops in FP32; the link and the reconstruction
-// are folded into the A operand, the projected spinors form the B operand.
+// One hop of the hopping term maps the neighbour spinor psi (4 spins x 3
+// colours, per RHS) to (1 - S gamma_mu) U' psi, U' the link or its adjoint.
+// Its upper two spins are h' = P U' psi with P the 2 x 4 spin projector
+// (rows s_h, entries 1 at s_in = s_h and a coefficient c in {+-1, +-i} at
+// one lower spin), and its lower two spins follow from h' by the fixed
+// reconstruction of the direction.  With real and imaginary parts
+// separated, h' for all RHS is one real product
+//   h'[(a, s_h, re/im)][r] = sum_(b, s_in, re/im) A[(a, s_h, ro)][(b, s_in, ri)] psi[(b, s_in, ri)][r]
+// of a 12 x 24 matrix A = real form of (P x U') and the 24 x nrhs block of
+// neighbour spinors, which is the B operand exactly as stored (colour b of
+// RHS r is 4 spins x (re, im) = 8 halves).  One v_mfma_f32_16x16x32_f16 per
+// hop computes it; rows 12-15 and the K range 24-31 are zero padding.
 //
-// Operand layouts of v_mfma_f32_16x16x16f16 (64 lanes, lane l, i = l % 16,
-// g = l / 16): A[i][4g + j] and B[4g + j][i] (j = 0..3, one half4 per lane),
-// D[4g + j][i] (one float4 per lane).  Here i is the RHS column for B and D,
-// and the contraction group g is the colour b of the neighbour (g = 3 is
-// zero padding).
+// Operand layout of v_mfma_f32_16x16x32_f16 (lane l, i = l % 16,
+// g = l / 16): A[i][8 g + j] and B[8 g + j][i] (j = 0..7, eight halves per
+// lane), D[4 g + j][i] (j = 0..3).  With rows ordered (a, s_h, re/im) the
+// lane (g, i) receives h' of colour a = g for RHS i, so the reconstruction,
+// the per-site FP16 scale of each neighbour (applied to D in FP32) and the
+// accumulation of the eight hops stay inside the lane.  A lane of the A
+// operand needs one link element U'[a][b] (a gather of 4 bytes from an
+// uncompressed FP16 copy of the links) and places it, in real form, at the
+// two spin slots its row s_h selects: a permute, an xor and four selects.
+//
+// The clover epilogues use v_mfma_f32_16x16x16f16 on each 6 x 6 chirality
+// block in the same lane layout (rows (a, spin-in-block, re/im), K groups
+// colour): the lane holding colour a of RHS r supplies and receives the two
+// spins of that block, again without data exchange between lanes.
 #pragma once
 
 #include <vector>
@@ -32,8 +44,12 @@ namespace lq {
 
 constexpr int MR_MAX = 16;  // right-hand sides per multi-RHS field
 
+typedef _Float16 mr_half8 __attribute__((ext_vector_type(8)));
 typedef _Float16 mr_half4 __attribute__((ext_vector_type(4)));
+typedef _Float16 mr_half2 __attribute__((ext_vector_type(2)));
 typedef float mr_float4 __attribute__((ext_vector_type(4)));
+typedef unsigned mr_u4 __attribute__((ext_vector_type(4)));
+typedef unsigned mr_u2 __attribute__((ext_vector_type(2)));
 
 template <class P>
 struct MField {
@@ -62,143 +78,153 @@ __host__ __device__ inline int64_t mr_idx(int64_t s, int nrhs, int r, int c) {
   return ((s * nrhs) + r) * 12 + c;
 }
 
-// Spin reconstruction coefficient R[s_out][s_h] of the hop in direction MU
-// with projector sign S (see dslash_core.h); 0, +-1 or +-i.
-template <int MU, int S>
-__device__ __forceinline__ C<float> recon_coeff(int s_out, int s_h) {
-  if (s_out < 2) return C<float>{s_out == s_h ? 1.f : 0.f, 0.f};
-  const float sf = (float)S;
-  if constexpr (MU == 0) {  // lower: (-S i h1, -S i h0)
-    return (s_out == 2) == (s_h == 1) ? C<float>{0.f, -sf} : C<float>{0.f, 0.f};
-  } else if constexpr (MU == 1) {  // (-S h1, +S h0)
-    if (s_out == 2) return s_h == 1 ? C<float>{-sf, 0.f} : C<float>{0.f, 0.f};
-    return s_h == 0 ? C<float>{sf, 0.f} : C<float>{0.f, 0.f};
-  } else if constexpr (MU == 2) {  // (-S i h0, +S i h1)
-    if (s_out == 2) return s_h == 0 ? C<float>{0.f, -sf} : C<float>{0.f, 0.f};
-    return s_h == 1 ? C<float>{0.f, sf} : C<float>{0.f, 0.f};
-  } else {  // (-S h0, -S h1)
-    return (s_out - 2) == s_h ? C<float>{-sf, 0.f} : C<float>{0.f, 0.f};
-  }
+// FP16 copies of the operator for the multi-RHS kernels, site-major:
+// links[((p * nsite + s) * 4 + mu) * 9 + 3 a + b] = U_mu(s)[a][b] of parity p
+// (all nine entries), clover[s * 42 + 21 cb + k]: per chirality block the
+// diagonal (d_k, 0) for k < 6, then the upper triangle in tri_idx order.
+constexpr int MR_CLOV_SITE = 42;
+constexpr int MR_CLOV_BLOCK = 21;
+
+// half2 bit patterns: low half = real part, high half = imaginary part
+constexpr unsigned MR_SGN_HI = 0x80000000u, MR_SGN_LO = 0x00008000u,
+                   MR_SGN_BOTH = 0x80008000u;
+constexpr unsigned MR_SEL_ID = 0x03020100u, MR_SEL_SWAP = 0x01000302u;  // v_perm_b32
+
+__device__ __forceinline__ unsigned mr_perm(unsigned v, unsigned sel) {
+  return __builtin_amdgcn_perm(v, v, sel);
 }
 
-// Spin projection of one colour: p[spin] -> (h0, h1).
-template <int MU, int S>
-__device__ __forceinline__ void project1(const C<float> p[4], C<float>& h0, C<float>& h1) {
-  if constexpr (MU == 0) {
-    h0 = S > 0 ? p[0] + times_i(p[3]) : p[0] - times_i(p[3]);
-    h1 = S > 0 ? p[1] + times_i(p[2]) : p[1] - times_i(p[2]);
-  } else if constexpr (MU == 1) {
-    h0 = S > 0 ? p[0] + p[3] : p[0] - p[3];
-    h1 = S > 0 ? p[1] - p[2] : p[1] + p[2];
-  } else if constexpr (MU == 2) {
-    h0 = S > 0 ? p[0] + times_i(p[2]) : p[0] - times_i(p[2]);
-    h1 = S > 0 ? p[1] - times_i(p[3]) : p[1] + times_i(p[3]);
-  } else {
-    h0 = S > 0 ? p[0] - p[2] : p[0] + p[2];
-    h1 = S > 0 ? p[1] - p[3] : p[1] + p[3];
-  }
+// Load at a wave-uniform base plus a 32-bit per-lane byte offset (the
+// scalar-base addressing form of global loads).
+template <class T>
+__device__ __forceinline__ T mr_ld(const void* base, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
 }
 
-// Neighbour of the local site (l, tc, x3) in direction MU (forward or
-// backward) as a checkerboard index; `sign` is the antiperiodic time phase.
-template <int MU, bool BACK>
-__device__ __forceinline__ int64_t mr_neighbour(const Geo& g, const int l[4], const int tc[4],
-                                                int x3, float& sign) {
-  sign = 1.f;
-  if constexpr (MU == 3) {
-    if (g.apt && x3 == (BACK ? 0 : g.L[3] - 1)) sign = -1.f;
+// Lane constants of the A operands.  A row (a, s, ro) of the real form of
+// a complex matrix z holds (Re z, -Im z) for ro = 0 and (Im z, Re z) for
+// ro = 1 against the (re, im) parts of the K side; as half2 bits that is
+// z ^ SGN_HI or swap(z), and for conj(z) it is z or swap(z) ^ SGN_LO.
+struct MRLane {
+  unsigned selX, selYi;  // selectors: real form of z, of i z
+  unsigned mXf, mXb;     // xor masks: real form of z, of conj(z)
+  unsigned mYf, mYb;     // xor masks: real form of i z, of i conj(z)
+  unsigned msh;          // SGN_BOTH on rows with s_h = 1
+  bool c0, c1;           // valid A row with s_h = 0 / s_h = 1
+  unsigned ef, eb;       // byte offset of link entry U[a][b] / U[b][a]
+  unsigned cslot[2];     // clover: byte offset of entry (k, l) for K spin 0 / 1
+  unsigned cm[2];        // clover: xor mask of that entry (conjugated below the diagonal)
+};
+
+__device__ __forceinline__ MRLane mr_lane(int li, int grp) {
+  MRLane q;
+  const int a = li >> 2, sh = (li >> 1) & 1, ro = li & 1;
+  const bool row = li < 12 && grp < 3;
+  q.c0 = row && sh == 0;
+  q.c1 = row && sh == 1;
+  const int ac = a < 3 ? a : 0, bc = grp < 3 ? grp : 0;
+  q.ef = (unsigned)(ac * 3 + bc) * 4u;
+  q.eb = (unsigned)(bc * 3 + ac) * 4u;
+  q.selX = ro ? MR_SEL_SWAP : MR_SEL_ID;
+  q.selYi = ro ? MR_SEL_ID : MR_SEL_SWAP;
+  q.mXf = ro ? 0u : MR_SGN_HI;
+  q.mXb = ro ? MR_SGN_LO : 0u;
+  q.mYf = ro ? MR_SGN_HI : MR_SGN_BOTH;
+  q.mYb = ro ? 0u : MR_SGN_HI;
+  q.msh = sh ? MR_SGN_BOTH : 0u;
+  // clover rows (a_out, sib_out, ro) = (a, sh, ro); K (a_in = grp, sib_in, ri)
+  const int k = sh * 3 + ac;
+#pragma unroll
+  for (int si = 0; si < 2; ++si) {
+    const int l = si * 3 + bc;
+    if (k == l) {
+      q.cslot[si] = 4u * k;
+      q.cm[si] = q.mXf;
+    } else if (k < l) {
+      q.cslot[si] = 4u * (6 + tri_idx(k, l));
+      q.cm[si] = q.mXf;
+    } else {
+      q.cslot[si] = 4u * (6 + tri_idx(l, k));
+      q.cm[si] = q.mXb;
+    }
   }
-  int y[4] = {tc[0] * g.T[0] + l[0], tc[1] * g.T[1] + l[1], tc[2] * g.T[2] + l[2], x3};
-  if constexpr (!BACK)
-    y[MU] = (y[MU] + 1 == g.L[MU]) ? 0 : y[MU] + 1;
-  else
-    y[MU] = (y[MU] == 0) ? g.L[MU] - 1 : y[MU] - 1;
-  return cb_index(g, y);
+  return q;
 }
 
-// One hop of the multi-RHS hopping term for site s with neighbour sy,
-// accumulated into the two D tiles.  lane_i = lane % 16, g = lane / 16.
-// `sc` scales the neighbour's FP16 data into the column scale of RHS lane_i
-// (its stored norm times the time phase over the column scale), so that the
-// B operand stays in [-2, 2] whatever the field's magnitude.
+// One hop (direction MU, projector sign S, BACK: from x - mu with U^+) of
+// the multi-RHS hopping term, given its gathered operands: v = the lane's
+// link entry (half2 bits), B = the lane's 8 halves of neighbour spinor data,
+// n = the neighbour's FP16 scale times the time boundary phase.  Builds the
+// A operand, multiplies, and accumulates n * (upper, reconstructed lower
+// spins) into acc[spin][re/im] of the lane's colour and RHS.
 template <int MU, int S, bool BACK>
-__device__ __forceinline__ void mrhs_hop_dir(const Geo& g, const MField<P16>& in,
-                                             const __half2* __restrict__ gauge, int p, int64_t s,
-                                             int64_t sy, float sc, int lane_i, int grp,
-                                             mr_float4& acc0, mr_float4& acc1) {
-  // B operand: projected neighbour spinor, colour b = grp, column = RHS lane_i
-  mr_half4 B = {(_Float16)0, (_Float16)0, (_Float16)0, (_Float16)0};
-  if (grp < 3 && lane_i < in.nrhs) {
-    const int64_t base = mr_idx(sy, in.nrhs, lane_i, grp * 4);
-    C<float> pv[4];
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp) pv[sp] = ld<P16>(in.d, base + sp);
-    C<float> h0, h1;
-    project1<MU, S>(pv, h0, h1);
-    B = mr_half4{(_Float16)(sc * h0.re), (_Float16)(sc * h0.im), (_Float16)(sc * h1.re),
-                 (_Float16)(sc * h1.im)};
+__device__ __forceinline__ void mr_hop1(unsigned v, mr_u4 B, float n, const MRLane& q,
+                                        float acc[8]) {
+  constexpr bool IMAG = (MU == 0 || MU == 2);     // c = +-i
+  constexpr bool NEG = MU == 3 ? (S > 0) : (S < 0);  // sign of c on rows s_h = 0
+  constexpr bool SHDEP = (MU == 1 || MU == 2);       // c changes sign with s_h
+  const unsigned X = mr_perm(v, q.selX) ^ (BACK ? q.mXb : q.mXf);
+  unsigned Y = IMAG ? (mr_perm(v, q.selYi) ^ (BACK ? q.mYb : q.mYf)) : X;
+  if constexpr (NEG) Y ^= MR_SGN_BOTH;
+  if constexpr (SHDEP) Y ^= q.msh;
+  mr_u4 A;
+  A[0] = q.c0 ? X : 0u;
+  A[1] = q.c1 ? X : 0u;
+  if constexpr (MU <= 1) {  // second slot 3 - s_h
+    A[2] = q.c1 ? Y : 0u;
+    A[3] = q.c0 ? Y : 0u;
+  } else {  // second slot 2 + s_h
+    A[2] = q.c0 ? Y : 0u;
+    A[3] = q.c1 ? Y : 0u;
   }
-  // A operand: (R x U') in real form; rows m = (a * 4 + s_out) * 2 + re/im,
-  // columns (b, s_h, re/im) with b = grp
-  C<float> u[9];
-  if constexpr (!BACK)
-    load_link<P16>(gauge, g.nblk, p, MU, s, u);
-  else
-    load_link<P16>(gauge, g.nblk, 1 - p, MU, sy, u);
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int m = lane_i + 16 * t;
-    mr_half4 A = {(_Float16)0, (_Float16)0, (_Float16)0, (_Float16)0};
-    if (m < 24 && grp < 3) {
-      const int a = m >> 3, s_out = (m >> 1) & 3, ro = m & 1, b = grp;
-      // U'[a][b]: U[a][b] forward, conj(U[b][a]) backward
-      C<float> uab = {0.f, 0.f};
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        const int ka = BACK ? k % 3 : k / 3, kb = BACK ? k / 3 : k % 3;
-        if (ka == a && kb == b) uab = BACK ? conj(u[k]) : u[k];
-      }
-      float e[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const C<float> z = recon_coeff<MU, S>(s_out, j >> 1) * uab;
-        const int ri = j & 1;
-        e[j] = ro == 0 ? (ri == 0 ? z.re : -z.im) : (ri == 0 ? z.im : z.re);
-      }
-      A = mr_half4{(_Float16)e[0], (_Float16)e[1], (_Float16)e[2], (_Float16)e[3]};
-    }
-    if (t == 0)
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x16f16(A, B, acc0, 0, 0, 0);
-    else
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x16f16(A, B, acc1, 0, 0, 0);
+  const mr_float4 z = {0.f, 0.f, 0.f, 0.f};
+  const mr_float4 D = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+      __builtin_bit_cast(mr_half8, A), __builtin_bit_cast(mr_half8, B), z, 0, 0, 0);
+  const float x0 = n * D[0], y0 = n * D[1], x1 = n * D[2], y1 = n * D[3];
+  acc[0] += x0;
+  acc[1] += y0;
+  acc[2] += x1;
+  acc[3] += y1;
+  constexpr float sf = (float)S;
+  if constexpr (MU == 0) {  // lower (-S i h1, -S i h0)
+    acc[4] += sf * y1;
+    acc[5] -= sf * x1;
+    acc[6] += sf * y0;
+    acc[7] -= sf * x0;
+  } else if constexpr (MU == 1) {  // (-S h1, +S h0)
+    acc[4] -= sf * x1;
+    acc[5] -= sf * y1;
+    acc[6] += sf * x0;
+    acc[7] += sf * y0;
+  } else if constexpr (MU == 2) {  // (-S i h0, +S i h1)
+    acc[4] += sf * y0;
+    acc[5] -= sf * x0;
+    acc[6] -= sf * y1;
+    acc[7] += sf * x1;
+  } else {  // (-S h0, -S h1)
+    acc[4] -= sf * x0;
+    acc[5] -= sf * y0;
+    acc[6] -= sf * x1;
+    acc[7] -= sf * y1;
   }
 }
 
-// Multiply one chirality block (6 complex, index spin_in_block * 3 + colour)
-// by the clover table block cb of site s.
-template <class P>
-__device__ __forceinline__ void clover_block(const typename P::S* __restrict__ cl, int64_t s,
-                                             int cb, const C<float> x[6], C<float> y[6]) {
-  C<float> m[18];
-#pragma unroll
-  for (int k = 0; k < 18; ++k) {
-    const C<typename P::R> v = ldnt<P>(cl, clov_idx(s, 18 * cb + k));
-    m[k] = C<float>{(float)v.re, (float)v.im};
-  }
-#pragma unroll
-  for (int rr = 0; rr < 6; ++rr) {
-    const float d = (rr & 1) ? m[rr >> 1].im : m[rr >> 1].re;
-    C<float> acc = d * x[rr];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      if (c == rr) continue;
-      if (rr < c)
-        acc = acc + m[3 + tri_idx(rr, c)] * x[c];
-      else
-        acc = acc + cmul_conj(m[3 + tri_idx(c, rr)], x[c]);
-    }
-    y[rr] = acc;
-  }
+// Chirality block cb of the clover table times the two spins (2 cb, 2 cb + 1)
+// the lane holds as FP16 half2 bits in b, given the lane's two gathered
+// table entries e (half2 bits): returns the lane's two output spins of its
+// colour.
+__device__ __forceinline__ mr_float4 mr_clover(const unsigned e[2], const MRLane& q, mr_u2 b) {
+  const bool row = q.c0 || q.c1;
+  mr_u2 A;
+  A[0] = row ? (mr_perm(e[0], q.selX) ^ q.cm[0]) : 0u;
+  A[1] = row ? (mr_perm(e[1], q.selX) ^ q.cm[1]) : 0u;
+  const mr_float4 z = {0.f, 0.f, 0.f, 0.f};
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(mr_half4, A),
+                                               __builtin_bit_cast(mr_half4, b), z, 0, 0, 0);
+}
+
+__device__ __forceinline__ unsigned mr_pack(float re, float im) {
+  return __builtin_bit_cast(unsigned, mr_half2{(_Float16)re, (_Float16)im});
 }
 
 // State of the batched CG iteration (device, mirrored in pinned host memory).
@@ -234,125 +260,159 @@ struct MRWork {
 
 enum { MR_EPI_NONE = 0, MR_EPI_CLOVINV = 1, MR_EPI_SCHUR2 = 2 };
 constexpr int MR_BLK = 256;
-constexpr int MR_SITES_PER_BLOCK = 32;  // 8 sites per wavefront
+#ifndef LQ_MR_SITES_PER_BLOCK
+#define LQ_MR_SITES_PER_BLOCK 32
+#endif
+constexpr int MR_SITES_PER_BLOCK = LQ_MR_SITES_PER_BLOCK;  // 4 waves, each every 4th site
 
 // out = H in (EPI_NONE), A^-1 H in (EPI_CLOVINV) or A x - k2 H in
 // (EPI_SCHUR2, with per-workgroup partial |out|^2 per RHS in part[block][r]),
 // for the sites of parity p of all right-hand sides.  `active`: skip when 0.
+// links / clov: the FP16 site-major copies (clov: the table of parity p).
 template <bool DAG, int EPI>
 __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
     Geo g, int p, const int* __restrict__ active, MField<P16> out, MField<P16> in,
-    MField<P16> x, const __half2* __restrict__ gauge, const __half2* __restrict__ cl, float k2,
-    double* __restrict__ part) {
-  __shared__ C<float> stage[4][MR_MAX][12];
+    MField<P16> x, const unsigned* __restrict__ links, const unsigned* __restrict__ clov,
+    const int* __restrict__ nbr, float k2, double* __restrict__ part) {
   __shared__ double red[4][MR_MAX];
   if (active && !*active) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int lane_i = lane & 15, grp = lane >> 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, grp = lane >> 4;
   const int nrhs = in.nrhs;
+  const MRLane q = mr_lane(li, grp);
+  const bool bl = grp < 3 && li < nrhs;  // lane holds colour grp of RHS li
+  // Lanes outside the batch (li >= nrhs, grp = 3) read a valid column and
+  // colour (finite data): their K range has zero A entries and their D
+  // columns are never stored.
+  const int lic = li < nrhs ? li : nrhs - 1, grc = grp < 3 ? grp : 2;
+  const unsigned bofs = (unsigned)(lic * 12 + grc * 4) * 4u;  // lane byte offset in a site's RHS block
+  const unsigned* ind = reinterpret_cast<const unsigned*>(in.d);
+  const int64_t nsite = g.nblk * 64;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   constexpr int SF = DAG ? -1 : 1;
+  constexpr int NIT = MR_SITES_PER_BLOCK / 4;
+  const int sblk = nrhs * 12;  // dwords per site of a multi-RHS field
+  const int* nbase = nbr + (int64_t)p * nsite * 8;
   double nsum = 0.0;
-  for (int it = 0; it < MR_SITES_PER_BLOCK / 4; ++it) {
-    const int64_t s = blk * MR_SITES_PER_BLOCK + it * 4 + wave;
+  int64_t s = blk * MR_SITES_PER_BLOCK + wave;
+  // neighbour rows are read one site ahead (scalar loads)
+  int nt[8];
+#pragma unroll
+  for (int h = 0; h < 8; ++h) nt[h] = s < g.vh ? nbase[s * 8 + h] : 0;
+  for (int it = 0; it < NIT; ++it, s += 4) {
     if (s >= g.vh) break;  // uniform across the wavefront
-    int l[4], tc[4];
-    site_local(g, p, s, l, tc);
-    const int x3 = tc[3] * g.T[3] + l[3];
-    // neighbours, and the column scale of RHS lane_i: the largest of the
-    // eight neighbour norms
-    int64_t sy[8];
-    float sg[8], nb[8];
-    sy[0] = mr_neighbour<0, false>(g, l, tc, x3, sg[0]);
-    sy[1] = mr_neighbour<0, true>(g, l, tc, x3, sg[1]);
-    sy[2] = mr_neighbour<1, false>(g, l, tc, x3, sg[2]);
-    sy[3] = mr_neighbour<1, true>(g, l, tc, x3, sg[3]);
-    sy[4] = mr_neighbour<2, false>(g, l, tc, x3, sg[4]);
-    sy[5] = mr_neighbour<2, true>(g, l, tc, x3, sg[5]);
-    sy[6] = mr_neighbour<3, false>(g, l, tc, x3, sg[6]);
-    sy[7] = mr_neighbour<3, true>(g, l, tc, x3, sg[7]);
-    float colmax = 0.f;
+    int sy[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) sy[h] = nt[h] & 0x7fffffff;
+    const bool tf = nt[6] < 0, tb = nt[7] < 0;  // hops across the antiperiodic time boundary
+    if (it + 1 < NIT && s + 4 < g.vh) {
+#pragma unroll
+      for (int h = 0; h < 8; ++h) nt[h] = nbase[(s + 4) * 8 + h];
+    }
+    // gather every operand of the site first (one memory round trip):
+    // neighbour scales, neighbour spinor blocks, link entries
+    const unsigned* lf = links + ((int64_t)p * nsite + s) * 36;
+    const unsigned* lb = links + (int64_t)(1 - p) * nsite * 36;
+    float nb[8];
+    mr_u4 bv[8];
+    unsigned lv[8];
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
-      nb[h] = lane_i < nrhs ? in.norm[sy[h] * nrhs + lane_i] : 0.f;
-      colmax = fmaxf(colmax, nb[h]);
+      nb[h] = mr_ld<float>(in.norm + (int64_t)sy[h] * nrhs, 4u * (unsigned)lic);
+      bv[h] = mr_ld<mr_u4>(ind + (int64_t)sy[h] * sblk, bofs);
+      const unsigned* lk = (h & 1) ? lb + (int64_t)sy[h] * 36 + 9 * (h >> 1) : lf + 9 * (h >> 1);
+      lv[h] = mr_ld<unsigned>(lk, (h & 1) ? q.eb : q.ef);
     }
-    const float cinv = colmax > 0.f ? 1.f / colmax : 0.f;
+    // clover entries of the lane (two per block) and the x block
+    unsigned ce[2][2] = {{0u, 0u}, {0u, 0u}};
+    mr_u4 xv = {0u, 0u, 0u, 0u};
+    float xn = 0.f;
+    if constexpr (EPI != MR_EPI_NONE) {
+      const unsigned* cl = clov + s * MR_CLOV_SITE;
 #pragma unroll
-    for (int h = 0; h < 8; ++h) nb[h] *= sg[h] * cinv;
-    mr_float4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    mrhs_hop_dir<0, SF, false>(g, in, gauge, p, s, sy[0], nb[0], lane_i, grp, acc0, acc1);
-    mrhs_hop_dir<0, -SF, true>(g, in, gauge, p, s, sy[1], nb[1], lane_i, grp, acc0, acc1);
-    mrhs_hop_dir<1, SF, false>(g, in, gauge, p, s, sy[2], nb[2], lane_i, grp, acc0, acc1);
-    mrhs_hop_dir<1, -SF, true>(g, in, gauge, p, s, sy[3], nb[3], lane_i, grp, acc0, acc1);
-    mrhs_hop_dir<2, SF, false>(g, in, gauge, p, s, sy[4], nb[4], lane_i, grp, acc0, acc1);
-    mrhs_hop_dir<2, -SF, true>(g, in, gauge, p, s, sy[5], nb[5], lane_i, grp, acc0, acc1);
-    mrhs_hop_dir<3, SF, false>(g, in, gauge, p, s, sy[6], nb[6], lane_i, grp, acc0, acc1);
-    mrhs_hop_dir<3, -SF, true>(g, in, gauge, p, s, sy[7], nb[7], lane_i, grp, acc0, acc1);
-    acc0 *= colmax;
-    acc1 *= colmax;
-    // D rows 4 grp .. 4 grp + 3 of column lane_i: two complex numbers
-    // (colour a, spins sp, sp + 1) per tile
-    if (lane_i < nrhs) {
-      const int sp = 2 * (grp & 1);
-      const int a0 = grp >> 1;
-      stage[wave][lane_i][a0 * 4 + sp] = C<float>{acc0[0], acc0[1]};
-      stage[wave][lane_i][a0 * 4 + sp + 1] = C<float>{acc0[2], acc0[3]};
-      if (grp < 2) {
-        stage[wave][lane_i][2 * 4 + sp] = C<float>{acc1[0], acc1[1]};
-        stage[wave][lane_i][2 * 4 + sp + 1] = C<float>{acc1[2], acc1[3]};
-      }
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+          ce[cb][k] = mr_ld<unsigned>(cl + MR_CLOV_BLOCK * cb, q.cslot[k]);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // epilogue: lane = 2 r + cb handles chirality block cb of RHS r
-    const int r = lane >> 1, cb = lane & 1;
-    const bool on = r < nrhs;
-    C<float> hv[6], yv[6];
-    if (on) {
+    if constexpr (EPI == MR_EPI_SCHUR2) {
+      xv = mr_ld<mr_u4>(reinterpret_cast<const unsigned*>(x.d) + s * sblk, bofs);
+      xn = mr_ld<float>(x.norm + s * nrhs, 4u * (unsigned)lic);
+    }
+    // keep the gather ahead of the arithmetic (the scheduler would otherwise
+    // sink loads towards their uses and serialise the memory latency)
+    __builtin_amdgcn_sched_barrier(0);
+    float colmax = 0.f;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) hv[k] = stage[wave][r][(k % 3) * 4 + 2 * cb + k / 3];
-      if constexpr (EPI == MR_EPI_NONE) {
+    for (int h = 0; h < 8; ++h) colmax = fmaxf(colmax, nb[h]);
+    if (tf) nb[6] = -nb[6];
+    if (tb) nb[7] = -nb[7];
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    mr_hop1<0, SF, false>(lv[0], bv[0], nb[0], q, acc);
+    mr_hop1<0, -SF, true>(lv[1], bv[1], nb[1], q, acc);
+    mr_hop1<1, SF, false>(lv[2], bv[2], nb[2], q, acc);
+    mr_hop1<1, -SF, true>(lv[3], bv[3], nb[3], q, acc);
+    mr_hop1<2, SF, false>(lv[4], bv[4], nb[4], q, acc);
+    mr_hop1<2, -SF, true>(lv[5], bv[5], nb[5], q, acc);
+    mr_hop1<3, SF, false>(lv[6], bv[6], nb[6], q, acc);
+    mr_hop1<3, -SF, true>(lv[7], bv[7], nb[7], q, acc);
+    // epilogue: y[spin][re/im] of colour grp, RHS li
+    float y[8];
+    if constexpr (EPI == MR_EPI_NONE) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) yv[k] = hv[k];
-      } else if constexpr (EPI == MR_EPI_CLOVINV) {
-        clover_block<P16>(cl, s, cb, hv, yv);
+      for (int k = 0; k < 8; ++k) y[k] = acc[k];
+    } else {
+      mr_u2 xb[2];
+      if constexpr (EPI == MR_EPI_SCHUR2) {
+        xb[0] = mr_u2{xv[0], xv[1]};
+        xb[1] = mr_u2{xv[2], xv[3]};
       } else {
-        C<float> xv[6];
-        const float xn = x.norm[s * nrhs + r];
+        // FP16 operand: the hop sum scaled by 1 / (largest neighbour scale)
+        const float cs = colmax > 0.f ? __builtin_amdgcn_rcpf(colmax) : 0.f;
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-          xv[k] = xn * ld<P16>(x.d, mr_idx(s, nrhs, r, (k % 3) * 4 + 2 * cb + k / 3));
-        clover_block<P16>(cl, s, cb, xv, yv);
+        for (int cb = 0; cb < 2; ++cb)
+          xb[cb] = mr_u2{mr_pack(cs * acc[4 * cb], cs * acc[4 * cb + 1]),
+                         mr_pack(cs * acc[4 * cb + 2], cs * acc[4 * cb + 3])};
+      }
 #pragma unroll
-        for (int k = 0; k < 6; ++k) yv[k] = yv[k] - k2 * hv[k];
+      for (int cb = 0; cb < 2; ++cb) {
+        const mr_float4 d = mr_clover(ce[cb], q, xb[cb]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if constexpr (EPI == MR_EPI_SCHUR2)
+            y[4 * cb + j] = xn * d[j] - k2 * acc[4 * cb + j];
+          else
+            y[4 * cb + j] = colmax * d[j];
+        }
       }
     }
     float mx = 0.f;
-    double n2 = 0.0;
-    if (on) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        mx = fmaxf(mx, fmaxf(fabsf(yv[k].re), fabsf(yv[k].im)));
-        n2 += (double)yv[k].re * yv[k].re + (double)yv[k].im * yv[k].im;
+    for (int k = 0; k < 8; ++k) mx = fmaxf(mx, fabsf(y[k]));
+    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    if (bl) {
+      const float inv = mx > 0.f ? __builtin_amdgcn_rcpf(mx) : 0.f;
+      mr_u4 o;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[k] = mr_pack(inv * y[2 * k], inv * y[2 * k + 1]);
+      *reinterpret_cast<mr_u4*>(reinterpret_cast<char*>(reinterpret_cast<unsigned*>(out.d) +
+                                                        s * sblk) + bofs) = o;
+      if (grp == 0) out.norm[s * nrhs + li] = mx;
+      if constexpr (EPI == MR_EPI_SCHUR2) {
+        double n2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) n2 += (double)y[k] * y[k];
+        nsum += n2;
       }
     }
-    mx = fmaxf(mx, __shfl_xor(mx, 1, 64));
-    if (on) {
-      const float inv = mx > 0.f ? 1.f / mx : 0.f;
-#pragma unroll
-      for (int k = 0; k < 6; ++k)
-        st<P16>(out.d, mr_idx(s, nrhs, r, (k % 3) * 4 + 2 * cb + k / 3), inv * yv[k]);
-      if (cb == 0) out.norm[s * nrhs + r] = mx;
-      nsum += n2;
-    }
-    __builtin_amdgcn_wave_barrier();
   }
   if (EPI == MR_EPI_SCHUR2 && part) {
-    // per-RHS totals: pair the two chirality lanes, then the four waves
-    nsum += __shfl_xor(nsum, 1, 64);
-    if ((lane & 1) == 0 && (lane >> 1) < MR_MAX) red[wave][lane >> 1] = nsum;
+    // per-RHS totals: the three colour lanes of a column, then the four waves
+    nsum += __shfl_xor(nsum, 16, 64);
+    nsum += __shfl_xor(nsum, 32, 64);
+    if (grp == 0) red[wave][li] = nsum;
     __syncthreads();
     if (threadIdx.x < (unsigned)nrhs) {
       const int r = threadIdx.x;

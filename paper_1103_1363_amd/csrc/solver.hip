@@ -655,6 +655,7 @@ void solve_batched(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_
   const double bytes0 = ctx->bytes;
   Work* w = work(ctx, LQ_F64);
   MRWork* mw = mrhs_work(ctx, nrhs);
+  mrhs_tables(ctx, true);  // before any graph capture
   const int64_t nb = ctx->geo.nblk;
   const int64_t nsite = ctx->V;
   const size_t hb = (size_t)nsite * 12 * 16;
