@@ -17,7 +17,15 @@ Printed (one JSON line):
                 profiled solve, priced against the 8 TB/s HBM peak;
   plain_fp64    the same solve with plain FP64 CG, for comparison;
   dslash_gbs    stand-alone hopping-term sweeps per precision (HIP events);
+  batched_12rhs the 12 spin-colour point sources of a propagator solved
+                together through the multi-RHS operator (FP16 on the matrix
+                cores), beside one point source solved alone (plain FP64 and
+                mixed FP16) scaled by 12;
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample.
+
+roofline.traffic is the HBM traffic per launch of the roofline kernel from
+the committed counter summary (profiles/traffic_*.txt), reported only while
+the library sources still match the digest recorded there.
 """
 from __future__ import annotations
 
@@ -33,8 +41,6 @@ sys.path.insert(0, ROOT)
 KAPPA, CSW, TOL = 0.135, 1.0, 1e-10
 KNAMES = ["hop_oe+clover_inv", "hop_eo+clover+norm", "hop_oe_dag+clover_inv",
           "hop_eo_dag+clover+cg_update", "p_update"]
-# rocprofv3 names of the iteration kernels (template arguments elided)
-KSYMBOLS = ["cg_k1<false>", "cg_k2", "cg_k1<true>", "cg_k4", "cg_k5"]
 
 
 def log(msg):
@@ -89,6 +95,89 @@ def copy_rate(torch, nbytes=1 << 30, nrep=20):
             "GB/s": round(2 * nbytes / s / 1e9, 1)}
 
 
+def mrhs_rate(lq, lat, torch, nrhs=12, nrep=30):
+    """Stand-alone multi-RHS hopping sweep H_eo on nrhs interleaved FP16
+    right-hand sides (algorithmic bytes: 8 links of 24 B plus 104 B of
+    spinor in and out per RHS and output site)."""
+    import numpy as np
+    vh = lat.volume // 2
+    rng = np.random.default_rng(7)
+    o = rng.standard_normal((nrhs, vh, 4, 3)) + 1j * rng.standard_normal((nrhs, vh, 4, 3))
+    din = lat.to_device(o, lq.ODD, lq.F16X)
+    dout = lat.new_field(lq.EVEN, lq.F16X, nrhs)
+    for _ in range(5):
+        lat.dslash(dout, din, lq.EVEN, False, lq.F16X, nrhs)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(nrep):
+        lat.dslash(dout, din, lq.EVEN, False, lq.F16X, nrhs)
+    b.record()
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) * 1e3 / nrep
+    per_site = 8 * 24 + nrhs * 104
+    gbs = per_site * vh / (us * 1e-6) / 1e9
+    del din, dout
+    return {"nrhs": nrhs, "us": round(us, 2), "bytes_per_site": per_site, "GB/s": round(gbs, 1),
+            "frac_hbm": round(gbs / 8000, 3),
+            "GFLOP/s": round(1320 * nrhs * vh / (us * 1e-6) / 1e9, 1)}
+
+
+def batched_point_sources(lq, lat, torch, dims):
+    """The 12 point sources at the origin solved as one batch, against one of
+    them solved alone (plain FP64 CG and mixed FP16 CG) times 12."""
+    from gen import fields
+    b = fields.point_sources_12(dims)
+    db = lat.to_device(b, lq.FULL, lq.F64)
+    dx = lat.new_field(lq.FULL, lq.F64, 12)
+    lat.solve_device(dx, db, KAPPA, CSW, TOL, nrhs=12, inner_prec=lq.F16, batched=1)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = lat.solve_device(dx, db, KAPPA, CSW, TOL, nrhs=12, inner_prec=lq.F16, batched=1)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    one = lat.field_bytes(lq.FULL, lq.F64)
+    db1, dx1 = db[:one], lat.new_field(lq.FULL, lq.F64)
+    single = {}
+    for name, prec in (("plain_fp64", lq.F64), ("mixed_f16", lq.F16)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lat.solve_device(dx1, db1, KAPPA, CSW, TOL, inner_prec=prec)[0]
+        torch.cuda.synchronize()
+        single[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 2),
+                        "iterations": r.iterations, "true_residual": r.true_residual}
+    out = {"rhs": 12, "sources": "point sources at the origin, one per (spin, colour)",
+           "solve_ms": round(tb * 1e3, 2), "ms_per_rhs": round(tb * 1e3 / 12, 2),
+           "iterations": reps[0].iterations, "reliable_updates": reps[0].reliable_updates,
+           "fallback": reps[0].fallback,
+           "max_true_residual": max(r.true_residual for r in reps),
+           "one_source_alone": single,
+           "speedup_vs_12x_plain_fp64": round(12 * single["plain_fp64"]["ms"] / (tb * 1e3), 3),
+           "speedup_vs_12x_mixed_f16": round(12 * single["mixed_f16"]["ms"] / (tb * 1e3), 3)}
+    del db, dx, dx1
+    return out
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the sources changed since it was taken."""
+    from paper_1103_1363_amd.prof_summary import source_digest
+    import glob
+    digest = source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.txt"))):
+        lines = open(path).read().splitlines()
+        rec = [ln.split(":", 1)[1].strip() for ln in lines if ln.startswith("# source_digest:")]
+        if not rec or rec[0] != digest:
+            continue
+        for ln in lines:
+            parts = ln.rsplit(None, 3)
+            if len(parts) == 4 and parts[0].replace(" ", "") == kernel.replace(" ", ""):
+                return {"bytes_per_launch": float(parts[2]) + float(parts[3]),
+                        "fetch_bytes": float(parts[2]), "write_bytes": float(parts[3]),
+                        "source": os.path.basename(path)}
+    return None
+
+
 def cpu_baseline(u, b, dims):
     """The FP64 oracle on the host: one even-odd hopping sweep H_eo of the same
     32^3x64 workload (a bounded sample of the solve, whose iterations each make
@@ -117,6 +206,7 @@ def main():
     ap.add_argument("--dims", default="32,32,32,64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): this build has no "
@@ -215,13 +305,21 @@ def main():
     k = int(np.argmax(rprof.kernel_ms))
     avg_s = rprof.kernel_ms[k] / rprof.kernel_calls[k] * 1e-3
     achieved = rprof.kernel_bytes[k] / avg_s / 1e9
+    po, pv = {"f32": ("P32", "P32"), "f16": ("P16", "P32")}[a.inner]
+    symbol = [f"cg_k1<{po}, false>", f"cg_k2<{po}>", f"cg_k1<{po}, true>", f"cg_k4<{po}, {pv}>",
+              f"cg_k5<{po}, {pv}>"][k]
+    tr = recorded_traffic(symbol)
     result["roofline"] = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-        "frac": round(achieved / 8000.0, 4), "traffic": None,
-        "kernel": f"{KSYMBOLS[k]} ({KNAMES[k]}, {a.inner})",
+        "frac": round(achieved / 8000.0, 4),
+        "traffic": round(tr["bytes_per_launch"] / 1e9, 4) if tr else None,
+        "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "kernel": f"{symbol} ({KNAMES[k]})",
         "bytes_per_launch": rprof.kernel_bytes[k], "avg_us": round(avg_s * 1e6, 2),
         "launches_timed": rprof.kernel_calls[k],
     }
+    if tr:
+        result["roofline"]["traffic_source"] = tr["source"]
     result["kernels"] = {
         KNAMES[i]: {"avg_us": round(rprof.kernel_ms[i] / max(1, rprof.kernel_calls[i]) * 1e3, 2),
                     "GB/s": round(rprof.kernel_bytes[i] /
@@ -231,7 +329,11 @@ def main():
 
     log("stand-alone hopping-term sweeps")
     result["dslash_gbs"] = dslash_rates(lq, lat, torch, b)
+    result["dslash_gbs"]["f16x12"] = mrhs_rate(lq, lat, torch, 12)
     result["hbm_copy"] = copy_rate(torch)
+    if not a.no_batched:
+        log("12 point sources: batched solve, and one source alone")
+        result["batched_12rhs"] = batched_point_sources(lq, lat, torch, dims)
 
     if not a.no_cpu_baseline:
         log("CPU baseline (oracle)")

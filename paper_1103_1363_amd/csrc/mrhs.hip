@@ -249,81 +249,160 @@ struct MRFinBeta {
   }
 };
 
-// per-RHS totals of per-block partials part[block][MR_MAX]
+// Reductions of per-block, per-RHS partial sums part[row][MR_MAX] in two
+// deterministic stages: mr_rows_kernel sums fixed contiguous ranges of rows
+// (one range per workgroup), mr_finalize_kernel sums those (one workgroup)
+// and applies the solver step.  Threads of the 256-thread reduction blocks
+// are (column = tid % 16, lane = tid / 16).
+__device__ __forceinline__ double mr_sum16(double v, double (*red)[MR_MAX]) {
+  // sum over the 16 lanes of each column: in-wave (4 lanes) then across waves
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  const int c = threadIdx.x & 15, w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) < 16) red[w][c] = v;
+  __syncthreads();
+  return red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
+constexpr int MR_ROWS2 = 256;      // rows after the first reduction stage
+constexpr int MR_UPD_BLOCKS = 1024;  // workgroups of the batched vector updates
+
+__global__ __launch_bounds__(256) void mr_rows_kernel(const double* __restrict__ in, int nrows,
+                                                      double* __restrict__ out) {
+  __shared__ double red[4][MR_MAX];
+  const int c = threadIdx.x & 15, l = threadIdx.x >> 4;
+  const int chunk = (nrows + gridDim.x - 1) / gridDim.x;
+  const int lo = blockIdx.x * chunk, hi = min(lo + chunk, nrows);
+  double t = 0.0;
+  for (int i = lo + l; i < hi; i += 16) t += in[(int64_t)i * MR_MAX + c];
+  t = mr_sum16(t, red);
+  if (threadIdx.x < 16) out[blockIdx.x * MR_MAX + c] = t;
+}
+
 template <class Fin>
 __global__ __launch_bounds__(256) void mr_finalize_kernel(const double* __restrict__ part,
-                                                          int nparts, int nrhs, double* result,
-                                                          Fin fin) {
-  __shared__ double sh[MR_MAX][16];
-  double t[MR_MAX];
-  for (int r = 0; r < MR_MAX; ++r) t[r] = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x)
-    for (int r = 0; r < nrhs; ++r) t[r] += part[(int64_t)b * MR_MAX + r];
-  block_sum<MR_MAX>(t, sh);
-  if (threadIdx.x == 0) {
-    for (int r = 0; r < nrhs; ++r) result[r] = t[r];
-    fin(t);
+                                                          int nparts, double* result, Fin fin) {
+  __shared__ double red[4][MR_MAX];
+  __shared__ double tot[MR_MAX];
+  const int c = threadIdx.x & 15, l = threadIdx.x >> 4;
+  double t = 0.0;
+  for (int i = l; i < nparts; i += 16) t += part[i * MR_MAX + c];
+  t = mr_sum16(t, red);
+  if (threadIdx.x < 16) {
+    tot[c] = t;
+    result[c] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) fin(tot);
+}
+
+// The batched vector kernels: threadIdx.x = RHS (16 lanes), threadIdx.y =
+// site (16 per step), grid-stride over sites.  Per (site, RHS) the 12
+// complex of an FP32 field are six 16-byte words, of an FP16 field three.
+// (the word is taken by value and split with shifts: element access through
+// a reference to a vector in global memory read only its first element here)
+__device__ __forceinline__ void mr_h2f(const mr_u4 w, float f[8]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const unsigned u = w[k];
+    f[2 * k] = (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xffffu));
+    f[2 * k + 1] = (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
   }
 }
 
-// x_r += alpha_r p_r;  r_r -= alpha_r s_r;  partial |r_r|^2.  Thread per (site, RHS).
+// x_r += alpha_r p_r;  r_r -= alpha_r s_r;  per-block partial |r_r|^2.
 __global__ __launch_bounds__(256) void mr_cg_update(Geo g, const MRState* __restrict__ mst,
                                                     MField<P32> x, MField<P32> rv, MField<P16> p,
                                                     MField<P16> sv, double* __restrict__ part) {
-  __shared__ double sh[MR_MAX][16];
-  if (!mst->active) return;
+  __shared__ double red[4][MR_MAX];
+  const int r = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int nrhs = x.nrhs;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t s = t / nrhs;
-  const int r = (int)(t - s * nrhs);
-  double v[MR_MAX];
-  for (int k = 0; k < MR_MAX; ++k) v[k] = 0.0;
-  if (s < g.vh) {
+  double acc = 0.0;
+  if (mst->active && r < nrhs) {
     const float al = (float)mst->alpha[r];
-    const float pn = p.norm[s * nrhs + r], sn = sv.norm[s * nrhs + r];
-    double acc = 0.0;
+    for (int64_t s = (int64_t)blockIdx.x * 16 + ty; s < g.vh; s += (int64_t)gridDim.x * 16) {
+      const int64_t i0 = mr_idx(s, nrhs, r, 0);
+      const float ap = al * p.norm[s * nrhs + r], as = al * sv.norm[s * nrhs + r];
+      float4* xp = reinterpret_cast<float4*>(x.d + i0);
+      float4* rp = reinterpret_cast<float4*>(rv.d + i0);
+      const mr_u4* pp = reinterpret_cast<const mr_u4*>(p.d + i0);
+      const mr_u4* sp = reinterpret_cast<const mr_u4*>(sv.d + i0);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      const int64_t i = mr_idx(s, nrhs, r, c);
-      C<float> xv = ld<P32>(x.d, i), rvv = ld<P32>(rv.d, i);
-      xv = xv + (al * pn) * ld<P16>(p.d, i);
-      rvv = rvv - (al * sn) * ld<P16>(sv.d, i);
-      st<P32>(x.d, i, xv);
-      st<P32>(rv.d, i, rvv);
-      acc += (double)rvv.re * rvv.re + (double)rvv.im * rvv.im;
+      for (int k = 0; k < 3; ++k) {
+        float pf[8], sf[8];
+        const mr_u4 pw = pp[k], sw = sp[k];
+        mr_h2f(pw, pf);
+        mr_h2f(sw, sf);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          float4 xv = xp[2 * k + h], rr = rp[2 * k + h];
+          xv.x += ap * pf[4 * h];
+          xv.y += ap * pf[4 * h + 1];
+          xv.z += ap * pf[4 * h + 2];
+          xv.w += ap * pf[4 * h + 3];
+          rr.x -= as * sf[4 * h];
+          rr.y -= as * sf[4 * h + 1];
+          rr.z -= as * sf[4 * h + 2];
+          rr.w -= as * sf[4 * h + 3];
+          xp[2 * k + h] = xv;
+          rp[2 * k + h] = rr;
+          acc += (double)rr.x * rr.x + (double)rr.y * rr.y + (double)rr.z * rr.z +
+                 (double)rr.w * rr.w;
+        }
+      }
     }
-    // per-RHS slot without dynamic register indexing
-#pragma unroll
-    for (int k = 0; k < MR_MAX; ++k) v[k] = (k == r) ? acc : 0.0;
   }
-  block_sum<MR_MAX>(v, sh);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < MR_MAX; ++k) part[blockIdx.x * MR_MAX + k] = v[k];
+  // column r of this workgroup: lanes of equal r are 16 apart in the block
+  acc += __shfl_xor(acc, 16, 64);
+  acc += __shfl_xor(acc, 32, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) < 16) red[w][r] = acc;
+  __syncthreads();
+  if (threadIdx.x < 16) part[blockIdx.x * MR_MAX + r] = red[0][r] + red[1][r] + red[2][r] + red[3][r];
 }
 
-// p_r = r_r + beta_r p_r.  Thread per (site, RHS).
+// p_r = r_r + beta_r p_r, stored in FP16 with a new per-(site, RHS) scale.
 __global__ __launch_bounds__(256) void mr_p_update(Geo g, const MRState* __restrict__ mst,
                                                    MField<P16> p, MField<P32> rv) {
-  if (!mst->active) return;
+  const int r = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int nrhs = p.nrhs;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t s = t / nrhs;
-  const int r = (int)(t - s * nrhs);
-  if (s >= g.vh) return;
+  if (!mst->active || r >= nrhs) return;
   const float be = (float)mst->beta[r];
-  const float pn = p.norm[s * nrhs + r];
-  C<float> o[12];
-  float mx = 0.f;
+  for (int64_t s = (int64_t)blockIdx.x * 16 + ty; s < g.vh; s += (int64_t)gridDim.x * 16) {
+    const int64_t i0 = mr_idx(s, nrhs, r, 0);
+    const float bp = be * p.norm[s * nrhs + r];
+    const float4* rp = reinterpret_cast<const float4*>(rv.d + i0);
+    mr_u4* pp = reinterpret_cast<mr_u4*>(p.d + i0);
+    float o[24];
+    float mx = 0.f;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const int64_t i = mr_idx(s, nrhs, r, c);
-    o[c] = ld<P32>(rv.d, i) + (be * pn) * ld<P16>(p.d, i);
-    mx = fmaxf(mx, fmaxf(fabsf(o[c].re), fabsf(o[c].im)));
+    for (int k = 0; k < 3; ++k) {
+      float pf[8];
+      const mr_u4 pw = pp[k];
+      mr_h2f(pw, pf);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float4 rr = rp[2 * k + h];
+        o[8 * k + 4 * h] = rr.x + bp * pf[4 * h];
+        o[8 * k + 4 * h + 1] = rr.y + bp * pf[4 * h + 1];
+        o[8 * k + 4 * h + 2] = rr.z + bp * pf[4 * h + 2];
+        o[8 * k + 4 * h + 3] = rr.w + bp * pf[4 * h + 3];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 24; ++k) mx = fmaxf(mx, fabsf(o[k]));
+    const float inv = mx > 0.f ? 1.f / mx : 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      mr_u4 wv;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        wv[j] = __builtin_bit_cast(unsigned, mr_half2{(_Float16)(inv * o[8 * k + 2 * j]),
+                                                      (_Float16)(inv * o[8 * k + 2 * j + 1])});
+      pp[k] = wv;
+    }
+    p.norm[s * nrhs + r] = mx;
   }
-  const float inv = mx > 0.f ? 1.f / mx : 0.f;
-#pragma unroll
-  for (int c = 0; c < 12; ++c) st<P16>(p.d, mr_idx(s, nrhs, r, c), inv * o[c]);
-  p.norm[s * nrhs + r] = mx;
 }
 
 }  // namespace
@@ -468,24 +547,29 @@ void slot_axpby(lq_ctx* ctx, void* mfield, int nrhs, void* single, int r, double
   LQ_HIP(hipGetLastError());
 }
 
+// partial rows (one per workgroup) -> MRState via the two reduction stages
+template <class Fin>
+void mr_reduce(lq_ctx* ctx, MRWork* w, int nrows, Fin fin) {
+  hipLaunchKernelGGL(mr_rows_kernel, dim3(MR_ROWS2), dim3(256), 0, ctx->cur, w->part, nrows,
+                     w->part2);
+  hipLaunchKernelGGL(mr_finalize_kernel<Fin>, dim3(1), dim3(256), 0, ctx->cur, w->part2,
+                     MR_ROWS2, w->res, fin);
+}
+
 void mr_launch_iteration(lq_ctx* ctx, MRWork* w) {
   const Geo& g = ctx->geo;
   const int n = w->nrhs;
   const int* act = &w->st->active;
   mr_hop(ctx, LQ_ODD, 0, MR_EPI_CLOVINV, act, w->t, w->p, nullptr, n, nullptr);
   mr_hop(ctx, LQ_EVEN, 0, MR_EPI_SCHUR2, act, w->q, w->t, w->p, n, w->part);
-  hipLaunchKernelGGL(mr_finalize_kernel<MRFinAlpha>, dim3(1), dim3(256), 0, ctx->cur, w->part,
-                     mr_hop_grid(g), n, w->res, MRFinAlpha{w->st});
+  mr_reduce(ctx, w, mr_hop_grid(g), MRFinAlpha{w->st});
   mr_hop(ctx, LQ_ODD, 1, MR_EPI_CLOVINV, act, w->t, w->q, nullptr, n, nullptr);
-  mr_hop(ctx, LQ_EVEN, 1, MR_EPI_SCHUR2, act, w->s, w->t, w->q, n, w->part);
-  const int64_t nt = g.vh * n;
-  const int ug = grid_for(nt, 256);
-  hipLaunchKernelGGL(mr_cg_update, dim3(ug), dim3(256), 0, ctx->cur, g, w->st,
+  mr_hop(ctx, LQ_EVEN, 1, MR_EPI_SCHUR2, act, w->s, w->t, w->q, n, nullptr);
+  hipLaunchKernelGGL(mr_cg_update, dim3(MR_UPD_BLOCKS), dim3(256), 0, ctx->cur, g, w->st,
                      mfield_at<P32>(w->x, g.nblk, n), mfield_at<P32>(w->r, g.nblk, n),
                      mfield_at<P16>(w->p, g.nblk, n), mfield_at<P16>(w->s, g.nblk, n), w->part);
-  hipLaunchKernelGGL(mr_finalize_kernel<MRFinBeta>, dim3(1), dim3(256), 0, ctx->cur, w->part, ug,
-                     n, w->res, MRFinBeta{w->st});
-  hipLaunchKernelGGL(mr_p_update, dim3(ug), dim3(256), 0, ctx->cur, g, w->st,
+  mr_reduce(ctx, w, MR_UPD_BLOCKS, MRFinBeta{w->st});
+  hipLaunchKernelGGL(mr_p_update, dim3(MR_UPD_BLOCKS), dim3(256), 0, ctx->cur, g, w->st,
                      mfield_at<P16>(w->p, g.nblk, n), mfield_at<P32>(w->r, g.nblk, n));
   LQ_HIP(hipGetLastError());
 }
@@ -508,8 +592,9 @@ MRWork* mrhs_work(lq_ctx* ctx, int nrhs) {
     for (void** pp : {&w->p, &w->q, &w->t, &w->s}) LQ_HIP(hipMalloc(pp, f16));
     for (void** pp : {&w->x, &w->r}) LQ_HIP(hipMalloc(pp, f32));
     const size_t nparts = (size_t)std::max(grid_for(ctx->geo.vh, MR_SITES_PER_BLOCK),
-                                           grid_for(ctx->geo.vh * nrhs, 256));
+                                           MR_UPD_BLOCKS);
     LQ_HIP(hipMalloc(&w->part, nparts * MR_MAX * sizeof(double)));
+    LQ_HIP(hipMalloc(&w->part2, (size_t)MR_ROWS2 * MR_MAX * sizeof(double)));
     LQ_HIP(hipMalloc(&w->res, MR_MAX * sizeof(double)));
     LQ_HIP(hipMalloc(&w->st, sizeof(MRState)));
     LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->st_host), sizeof(MRState),
@@ -534,6 +619,7 @@ void free_mrhs_work(lq_ctx* ctx) {
   for (void* p : {w->p, w->q, w->t, w->s, w->x, w->r})
     if (p) (void)hipFree(p);
   if (w->part) (void)hipFree(w->part);
+  if (w->part2) (void)hipFree(w->part2);
   if (w->res) (void)hipFree(w->res);
   if (w->st) (void)hipFree(w->st);
   if (w->st_host) (void)hipHostFree(w->st_host);

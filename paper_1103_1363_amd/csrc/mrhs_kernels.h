@@ -247,7 +247,8 @@ struct MRWork {
   int64_t nblk = 0;
   void *p = nullptr, *q = nullptr, *t = nullptr, *s = nullptr;  // FP16 multi-RHS
   void *x = nullptr, *r = nullptr;                              // FP32 multi-RHS
-  double* part = nullptr;  // per-block partials [blocks][MR_MAX]
+  double* part = nullptr;   // per-block partials [blocks][MR_MAX]
+  double* part2 = nullptr;  // first reduction stage [MR_ROWS2][MR_MAX]
   double* res = nullptr;   // totals
   MRState* st = nullptr;
   MRState* st_host = nullptr;
@@ -264,6 +265,9 @@ constexpr int MR_BLK = 256;
 #define LQ_MR_SITES_PER_BLOCK 32
 #endif
 constexpr int MR_SITES_PER_BLOCK = LQ_MR_SITES_PER_BLOCK;  // 4 waves, each every 4th site
+#ifndef LQ_MR_MASKED_LOADS
+#define LQ_MR_MASKED_LOADS 0
+#endif
 
 // out = H in (EPI_NONE), A^-1 H in (EPI_CLOVINV) or A x - k2 H in
 // (EPI_SCHUR2, with per-workgroup partial |out|^2 per RHS in part[block][r]),
@@ -317,6 +321,20 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
     float nb[8];
     mr_u4 bv[8];
     unsigned lv[8];
+#if LQ_MR_MASKED_LOADS
+    // only lanes whose data is used issue the loads
+    const bool arow = q.c0 || q.c1;
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      nb[h] = 0.f;
+      bv[h] = mr_u4{0u, 0u, 0u, 0u};
+      lv[h] = 0u;
+      if (li < nrhs) nb[h] = mr_ld<float>(in.norm + (int64_t)sy[h] * nrhs, 4u * (unsigned)lic);
+      if (bl) bv[h] = mr_ld<mr_u4>(ind + (int64_t)sy[h] * sblk, bofs);
+      const unsigned* lk = (h & 1) ? lb + (int64_t)sy[h] * 36 + 9 * (h >> 1) : lf + 9 * (h >> 1);
+      if (arow) lv[h] = mr_ld<unsigned>(lk, (h & 1) ? q.eb : q.ef);
+    }
+#else
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       nb[h] = mr_ld<float>(in.norm + (int64_t)sy[h] * nrhs, 4u * (unsigned)lic);
@@ -324,6 +342,7 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
       const unsigned* lk = (h & 1) ? lb + (int64_t)sy[h] * 36 + 9 * (h >> 1) : lf + 9 * (h >> 1);
       lv[h] = mr_ld<unsigned>(lk, (h & 1) ? q.eb : q.ef);
     }
+#endif
     // clover entries of the lane (two per block) and the x block
     unsigned ce[2][2] = {{0u, 0u}, {0u, 0u}};
     mr_u4 xv = {0u, 0u, 0u, 0u};
@@ -414,7 +433,7 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
     nsum += __shfl_xor(nsum, 32, 64);
     if (grp == 0) red[wave][li] = nsum;
     __syncthreads();
-    if (threadIdx.x < (unsigned)nrhs) {
+    if (threadIdx.x < (unsigned)MR_MAX) {  // columns past nrhs hold zeros
       const int r = threadIdx.x;
       part[blockIdx.x * MR_MAX + r] = red[0][r] + red[1][r] + red[2][r] + red[3][r];
     }

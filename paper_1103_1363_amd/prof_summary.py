@@ -1,6 +1,8 @@
-"""Summarise a rocprofv3 kernel trace (SQLite .db or kernel_trace.csv).
+"""Summarise a rocprofv3 kernel trace (SQLite .db or kernel_trace.csv), or
+turn two counter runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per launch.
 
 Usage: python -m paper_1103_1363_amd.prof_summary TRACE [--top N]
+       python -m paper_1103_1363_amd.prof_summary --pmc FETCH_CSV WRITE_CSV [--kernel SUBSTR]
 
 For every kernel: launches, total and average duration, and the average over
 "working" launches only.  The solvers replay captured graphs of several CG
@@ -57,11 +59,74 @@ def summary(path, top=20):
     return "\n".join(out)
 
 
+def source_digest():
+    """sha256 of every source file of the library (any change invalidates
+    counter figures taken on an older build)."""
+    import hashlib
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(here)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(here, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_counters(path, counter):
+    """Per-dispatch totals of one counter: {kernel short name: [KiB per dispatch]}."""
+    per = defaultdict(float)
+    names = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            d = int(row["Dispatch_Id"])
+            per[d] += float(row["Counter_Value"])
+            names[d] = short(row["Kernel_Name"])
+    out = defaultdict(list)
+    for d, v in per.items():
+        out[names[d]].append(v)
+    return out
+
+
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_BYTES = 1 << 30  # the benchmark's reference copy: 1 GiB read and 1 GiB written
+
+
+def pmc_traffic(fetch_csv, write_csv, kernel=None):
+    """HBM bytes per launch per kernel from FETCH_SIZE and WRITE_SIZE (KiB),
+    each scaled so that the reference copy of COPY_BYTES reads and writes
+    exactly that many bytes (the largest copyBuffer dispatch is taken as it)."""
+    fetch = pmc_counters(fetch_csv, "FETCH_SIZE")
+    write = pmc_counters(write_csv, "WRITE_SIZE")
+    cf = COPY_BYTES / (max(fetch[COPY_KERNEL]) * 1024.0)
+    cw = COPY_BYTES / (max(write[COPY_KERNEL]) * 1024.0)
+    rows = []
+    for name in sorted(fetch):
+        if kernel and kernel not in name:
+            continue
+        f = statistics.median(fetch[name]) * 1024.0 * cf
+        w = statistics.median(write.get(name, [0.0])) * 1024.0 * cw
+        rows.append((name, len(fetch[name]), f, w))
+    return cf, cw, rows
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("trace")
+    ap.add_argument("trace", nargs="?")
     ap.add_argument("--top", type=int, default=20)
+    ap.add_argument("--pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--kernel")
     a = ap.parse_args()
+    if a.pmc:
+        cf, cw, rows = pmc_traffic(a.pmc[0], a.pmc[1], a.kernel)
+        print(f"# counter scale (bytes per KiB counted): FETCH {cf:.3f}, WRITE {cw:.3f} "
+              f"(from the {COPY_BYTES >> 20} MiB reference copy)")
+        print(f"# source_digest: {source_digest()}")
+        print(f"{'kernel':58s} {'dispatches':>10s} {'fetch_bytes':>14s} {'write_bytes':>14s}")
+        for name, n, f, w in rows:
+            print(f"{name[:58]:58s} {n:10d} {f:14.4g} {w:14.4g}")
+        return
     print(f"# source: {os.path.basename(a.trace)} (durations in ns in the trace)")
     print(summary(a.trace, a.top))
 
