@@ -196,6 +196,68 @@ lq_status lq_solve_device(lq_ctx* ctx, void* dev_x, const void* dev_b, int nrhs,
                           double csw, double tol, const lq_solver_params* params,
                           lq_solve_report* report);
 
+/* ------------------------------------------------------------------------
+ * Learned preconditioner.  The paper's solvers are flexible Krylov methods
+ * (its FGCR, equivalent to FGMRES, around a preconditioner that is itself an
+ * iteration: section 5), which admit a preconditioner that is not a fixed
+ * matrix.  This library supplies as such a preconditioner a linear,
+ * gauge-covariant net of nlayers layers on full-lattice spinors,
+ *
+ *   psi_{l+1}(x) = W0 psi_l(x) + sum_mu [ Wp_mu U_mu(x) psi_l(x+mu)
+ *                                        + Wm_mu U_mu(x-mu)^+ psi_l(x-mu) ],
+ *
+ * with complex 4x4 spin matrices W (colour-blind) and the fermion boundary
+ * phase of the hopping term.  On the even-odd system it acts as
+ * N_e = P_e N E_e (embed an even field with zeros on the odd sites, apply,
+ * keep the even sites).  Weights on the host: double[nlayers][9][4][4][2]
+ * (re, im), index k = 0: W0, 1 + 2 mu: Wp_mu, 2 + 2 mu: Wm_mu, matrix row =
+ * output spin.  Device fields of the net calls are LQ_F32 even fields
+ * (lq_field_bytes(ctx, LQ_EVEN, LQ_F32, n)), caller-owned.  A net holds FP32
+ * weights, Adam moments, activations of one sample and its gradient; it
+ * uses the gauge field its context holds at each call.  Errors are reported
+ * through the context's lq_last_error.
+ * ------------------------------------------------------------------------ */
+typedef struct lq_net lq_net;
+
+/* A net of nlayers (1..16) layers with zero weights; needs a gauge field. */
+lq_status lq_net_create(lq_ctx* ctx, int nlayers, lq_net** out);
+void lq_net_destroy(lq_net* net);
+
+/* Copy weights in (EINVAL on non-finite values; resets the Adam state) or out. */
+lq_status lq_net_set_weights(lq_net* net, const double* host_w);
+lq_status lq_net_get_weights(lq_net* net, double* host_w);
+
+/* dev_out = N_e dev_in, or N_e^+ dev_in when adjoint != 0 (distinct buffers). */
+lq_status lq_net_apply(lq_net* net, void* dev_out, const void* dev_in, int adjoint);
+
+/* Training loss over npairs (source b_i, target x_i) pairs, each a set of
+ * npairs consecutive even fields:  loss = mean_i ||N_e b_i - x_i||^2 / ||x_i||^2.
+ * Its gradient dL/dconj(W) (Wirtinger convention; the real gradient is
+ * 2 Re, 2 Im of it) replaces the net's stored gradient and, if host_grad is
+ * not NULL, is copied there (layout of the weights). */
+lq_status lq_net_loss_grad(lq_net* net, const void* dev_b, const void* dev_x, int npairs,
+                           double* loss, double* host_grad);
+
+/* One Adam step on the real parameters (Re W, Im W) with the stored
+ * gradient, which is then cleared. */
+lq_status lq_net_adam_step(lq_net* net, double lr, double beta1, double beta2, double eps);
+
+/* epochs of Adam (beta = 0.9, 0.999; eps = 1e-8) over the pairs in batches of
+ * `batch` drawn by a seeded permutation per epoch; loss_history (may be
+ * NULL) receives the mean loss of each epoch. */
+lq_status lq_net_train(lq_net* net, const void* dev_b, const void* dev_x, int npairs, int epochs,
+                       int batch, double lr, unsigned seed, double* loss_history);
+
+/* lq_solve with a learned-preconditioner solver: params->solver =
+ * LQ_FGMRES_NET (FGMRES(restart) on Mhat, right preconditioner N_e) or
+ * LQ_FCG_NET (flexible CG on Mhat^+ Mhat with N_e N_e^+).  Inner cycles in
+ * FP32, restarted from the FP64 Schur residual; when the flexible solver
+ * stagnates, breaks down or exhausts maxiter, the plain mixed CG finishes
+ * the solve and report->fallback is set.  The net must belong to ctx. */
+lq_status lq_solve_net(lq_ctx* ctx, lq_net* net, double* host_x, const double* host_b, int nrhs,
+                       double kappa, double csw, double tol, const lq_solver_params* params,
+                       lq_solve_report* report);
+
 #ifdef __cplusplus
 }
 #endif

@@ -94,6 +94,12 @@ void ensure_red(lq_ctx* ctx) {
 
 }  // namespace lq
 
+// the public net handle: the library net and the context it belongs to
+struct lq_net {
+  lq_ctx* ctx;
+  lq::Net* impl;
+};
+
 extern "C" {
 
 lq_status lq_create(const int dims[4], int t_antiperiodic, void* hip_stream, lq_ctx** out) {
@@ -338,6 +344,95 @@ lq_status lq_solve_device(lq_ctx* ctx, void* dev_x, const void* dev_b, int nrhs,
     LQ_CHECK(kappa > 0.0 && kappa < 0.25 && csw >= 0.0, LQ_EINVAL, "bad kappa or csw");
     LQ_CHECK(tol > 0.0 && tol < 1.0, LQ_EINVAL, "tol must lie in (0, 1)");
     lq::solve(ctx, nullptr, nullptr, dev_x, dev_b, nrhs, kappa, csw, tol, params, report);
+  });
+}
+
+// ------------------------------------------------------------ learned preconditioner
+lq_status lq_net_create(lq_ctx* ctx, int nlayers, lq_net** out) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(out, LQ_EINVAL, "null pointer");
+    lq::Net* n = lq::net_create(ctx, nlayers);
+    *out = new lq_net{ctx, n};
+  });
+}
+
+void lq_net_destroy(lq_net* net) {
+  if (!net) return;
+  (void)hipStreamSynchronize(net->ctx->cur);
+  lq::net_destroy(net->impl);
+  delete net;
+}
+
+lq_status lq_net_set_weights(lq_net* net, const double* host_w) {
+  if (!net) return LQ_EINVAL;
+  return guarded(net->ctx, [&] {
+    LQ_CHECK(host_w, LQ_EINVAL, "null pointer");
+    lq::net_set_weights(net->impl, host_w);
+  });
+}
+
+lq_status lq_net_get_weights(lq_net* net, double* host_w) {
+  if (!net) return LQ_EINVAL;
+  return guarded(net->ctx, [&] {
+    LQ_CHECK(host_w, LQ_EINVAL, "null pointer");
+    lq::net_get_weights(net->impl, host_w);
+  });
+}
+
+lq_status lq_net_apply(lq_net* net, void* dev_out, const void* dev_in, int adjoint) {
+  if (!net) return LQ_EINVAL;
+  return guarded(net->ctx, [&] {
+    LQ_CHECK(dev_out && dev_in && dev_out != dev_in, LQ_EINVAL,
+             "null or identical device pointers");
+    lq::net_apply_even(net->impl, dev_out, dev_in, adjoint != 0);
+    LQ_HIP(hipStreamSynchronize(net->ctx->cur));
+  });
+}
+
+lq_status lq_net_loss_grad(lq_net* net, const void* dev_b, const void* dev_x, int npairs,
+                           double* loss, double* host_grad) {
+  if (!net) return LQ_EINVAL;
+  return guarded(net->ctx, [&] {
+    LQ_CHECK(dev_b && dev_x && loss && npairs >= 1, LQ_EINVAL, "null pointer or npairs < 1");
+    *loss = lq::net_loss_grad(net->impl, dev_b, dev_x, npairs);
+    if (host_grad) lq::net_get_grad(net->impl, host_grad);
+  });
+}
+
+lq_status lq_net_adam_step(lq_net* net, double lr, double beta1, double beta2, double eps) {
+  if (!net) return LQ_EINVAL;
+  return guarded(net->ctx, [&] {
+    LQ_CHECK(lr > 0.0 && beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0,
+             LQ_EINVAL, "bad Adam parameters");
+    lq::net_adam(net->impl, lr, beta1, beta2, eps);
+    LQ_HIP(hipStreamSynchronize(net->ctx->cur));
+  });
+}
+
+lq_status lq_net_train(lq_net* net, const void* dev_b, const void* dev_x, int npairs, int epochs,
+                       int batch, double lr, unsigned seed, double* loss_history) {
+  if (!net) return LQ_EINVAL;
+  return guarded(net->ctx, [&] {
+    LQ_CHECK(dev_b && dev_x, LQ_EINVAL, "null pointer");
+    LQ_CHECK(lr > 0.0, LQ_EINVAL, "bad learning rate");
+    lq::net_train(net->impl, dev_b, dev_x, npairs, epochs, batch, lr, seed, loss_history);
+    LQ_HIP(hipStreamSynchronize(net->ctx->cur));
+  });
+}
+
+lq_status lq_solve_net(lq_ctx* ctx, lq_net* net, double* host_x, const double* host_b, int nrhs,
+                       double kappa, double csw, double tol, const lq_solver_params* params,
+                       lq_solve_report* report) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(net && host_x && host_b && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
+    LQ_CHECK(net->ctx == ctx, LQ_EINVAL, "the net belongs to another context");
+    LQ_CHECK(params && (params->solver == LQ_FGMRES_NET || params->solver == LQ_FCG_NET),
+             LQ_EINVAL, "params->solver must be LQ_FGMRES_NET or LQ_FCG_NET");
+    LQ_CHECK(ctx->have_gauge, LQ_ESTATE, "no gauge field uploaded");
+    LQ_CHECK(kappa > 0.0 && kappa < 0.25 && csw >= 0.0, LQ_EINVAL, "bad kappa or csw");
+    LQ_CHECK(tol > 0.0 && tol < 1.0, LQ_EINVAL, "tol must lie in (0, 1)");
+    lq::solve(ctx, host_x, host_b, nullptr, nullptr, nrhs, kappa, csw, tol, params, report,
+              net->impl);
   });
 }
 

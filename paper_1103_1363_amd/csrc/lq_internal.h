@@ -268,6 +268,7 @@ struct Clover {
 
 struct Work;    // solver work space (solver.hip)
 struct MRWork;  // batched multi-RHS solver work space (mrhs.hip)
+struct Net;     // learned preconditioner (net.hip)
 
 }  // namespace lq
 
@@ -330,7 +331,7 @@ void dot(lq_ctx* ctx, double* out_host, const void* a, const void* b, int prec);
 // device fields); the unused pair is null.
 void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const void* dev_b,
            int nrhs, double kappa, double csw, double tol, const lq_solver_params* params,
-           lq_solve_report* report);
+           lq_solve_report* report, Net* net = nullptr);
 void free_work(lq_ctx* ctx);
 
 // mrhs.hip: multi-RHS interleaved FP16 fields (lq_prec LQ_F16X) and the
@@ -346,6 +347,25 @@ MRWork* mrhs_work(lq_ctx* ctx, int nrhs);
 void free_mrhs_work(lq_ctx* ctx);
 void mrhs_tables(lq_ctx* ctx, bool clover);  // build the FP16 operator copies if stale
 void free_mrhs_tables(lq_ctx* ctx);
+
+// net.hip: learned gauge-covariant preconditioner (FP32 even fields)
+Net* net_create(lq_ctx* ctx, int nlayers);
+void net_destroy(Net* n);
+int net_layers(const Net* n);
+lq_ctx* net_ctx(const Net* n);
+void net_set_weights(Net* n, const double* host);  // [L][9][4][4] complex
+void net_get_weights(Net* n, double* host);
+void net_get_grad(Net* n, double* host);            // dL/dconj(W) of the last loss
+void net_zero_grad(Net* n);
+void net_apply_even(Net* n, void* y_e, const void* x_e, bool adjoint);
+double net_loss_grad(Net* n, const void* b, const void* x, int npairs);
+void net_adam(Net* n, double lr, double b1, double b2, double eps);
+void net_train(Net* n, const void* b, const void* x, int npairs, int epochs, int batch, double lr,
+               unsigned seed, double* hist);
+// complex BLAS on one-parity fields (elementwise over complex entries)
+void caxpy_f32(lq_ctx* ctx, void* y, double cr, double ci, const void* x);        // y += c x
+void caxpy_64_32(lq_ctx* ctx, void* y64, double cr, double ci, const void* x32);  // y += c x
+void axpby_f32(lq_ctx* ctx, void* out, double a, const void* x, double b, const void* y);
 void mrhs_iterate(lq_ctx* ctx, MRWork* w, int check_every, bool use_graph);
 void mrhs_state_upload(lq_ctx* ctx, MRWork* w);
 void mrhs_state_download(lq_ctx* ctx, MRWork* w);

@@ -1,0 +1,570 @@
+// Learned gauge-covariant preconditioner: a stack of linear layers
+//
+//   psi_{l+1}(x) = W0 psi_l(x) + sum_mu [ Wp_mu U_mu(x) psi_l(x+mu)
+//                                        + Wm_mu U_mu(x-mu)^+ psi_l(x-mu) ],
+//
+// each W a complex 4x4 matrix on spin (colour-blind, so the layer commutes
+// with gauge transformations), with the fermion boundary phase of the
+// hopping term on hops across the time boundary.  No bias, no nonlinearity:
+// the net is a linear operator N, used on the even-odd system as
+// N_e = P_e N E_e (embed an even field with zeros on the odd sites, apply,
+// keep the even sites) inside flexible Krylov solvers, which tolerate a
+// preconditioner that changes between iterations (section 5 of the paper,
+// the flexible outer solver of its SAP preconditioning).
+//
+// Fields are FP32 full lattices (even half then odd half, site-blocked);
+// weights FP32, gradients accumulated in FP64.  Weight index k per layer:
+// 0 = W0, 1 + 2 mu = Wp_mu, 2 + 2 mu = Wm_mu; W[s_out * 4 + t_in].
+//
+// Gradients (Wirtinger convention): for y = sum_k W_k T_k psi and an upstream
+// g = dL/dconj(y),  dL/dconj(W_k) = sum_{x, colour} g(x) (T_k psi)(x)^+  and
+// dL/dconj(psi) = sum_k T_k^+ W_k^+ g.  Since T_{mu+}^+ = T_{mu-}, the
+// adjoint layer is a layer with weights W0^+, Wm_mu^+ (forward hop) and
+// Wp_mu^+ (backward hop).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dslash_core.h"
+#include "lq_internal.h"
+#include "reduce.h"
+
+namespace lq {
+
+constexpr int NET_K = 9;
+constexpr int NET_W = NET_K * 16;  // complex weights per layer
+constexpr int NET_BLK = 128;
+
+struct Net {
+  lq_ctx* ctx = nullptr;
+  int L = 0;
+  float2* w = nullptr;      // [L][9][16]
+  float2* wadj = nullptr;   // adjoint layers [L][9][16]
+  float2* m1 = nullptr;     // Adam first moments (re, im)
+  float2* m2 = nullptr;     // Adam second moments
+  double2* grad = nullptr;  // accumulated dL/dconj(W) [L][9][16]
+  double* part = nullptr;   // weight-gradient partials [9][blocks][32]
+  int nblk_grad = 0;
+  void* act = nullptr;      // (L + 1) full FP32 fields
+  void* gbuf[2] = {nullptr, nullptr};
+  int64_t step = 0;
+  bool adj_ok = false;
+};
+
+namespace {
+
+size_t full32(const lq_ctx* ctx) { return 2 * parity_field_bytes(ctx->geo.nblk, LQ_F32); }
+char* half32(void* full, const lq_ctx* ctx, int p) {
+  return reinterpret_cast<char*>(full) + (p ? parity_field_bytes(ctx->geo.nblk, LQ_F32) : 0);
+}
+
+// acc[s][a] += c * sum_t W[s][t] v[t][a]  (component index spin * 3 + colour)
+__device__ __forceinline__ void spin_mix_add(const C<float>* __restrict__ W, const C<float> v[12],
+                                             float c, C<float> acc[12]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const C<float> wst = c * W[s * 4 + t];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc[s * 3 + a] = acc[s * 3 + a] + wst * v[t * 3 + a];
+    }
+}
+
+// T psi at site s of parity p for hop (MU, BACK): the neighbour spinor of
+// the other parity carried by the link (all four spins), times the time
+// boundary phase.
+template <int MU, bool BACK>
+__device__ __forceinline__ void transport(const Geo& g, const Field<P32>& other,
+                                          const float2* __restrict__ gauge, int p, int64_t s,
+                                          const int l[4], const int tc[4], int x3,
+                                          C<float> w[12]) {
+  float sign = 1.f;
+  if constexpr (MU == 3) {
+    if (g.apt && x3 == (BACK ? 0 : g.L[3] - 1)) sign = -1.f;
+  }
+  int y[4] = {tc[0] * g.T[0] + l[0], tc[1] * g.T[1] + l[1], tc[2] * g.T[2] + l[2], x3};
+  if constexpr (!BACK)
+    y[MU] = (y[MU] + 1 == g.L[MU]) ? 0 : y[MU] + 1;
+  else
+    y[MU] = (y[MU] == 0) ? g.L[MU] - 1 : y[MU] - 1;
+  const int64_t sy = cb_index(g, y);
+  C<float> v[12];
+  load_raw<P32>(other, sy, v);
+  C<float> u[9];
+  if constexpr (!BACK)
+    load_link<P32>(gauge, g.nblk, p, MU, s, u);
+  else
+    load_link<P32>(gauge, g.nblk, 1 - p, MU, sy, u);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C<float> z = {0.f, 0.f};
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        z = z + (BACK ? cmul_conj(u[3 * b + a], v[t * 3 + b]) : u[3 * a + b] * v[t * 3 + b]);
+      w[t * 3 + a] = sign * z;
+    }
+}
+
+template <int MU, bool BACK>
+__device__ __forceinline__ void layer_hop(const Geo& g, const Field<P32>& other,
+                                          const float2* __restrict__ gauge, int p, int64_t s,
+                                          const int l[4], const int tc[4], int x3,
+                                          const C<float>* __restrict__ W, C<float> acc[12]) {
+  C<float> w[12];
+  transport<MU, BACK>(g, other, gauge, p, s, l, tc, x3, w);
+  spin_mix_add(W + 16 * (BACK ? 2 + 2 * MU : 1 + 2 * MU), w, 1.f, acc);
+}
+
+// out (parity p) = layer(in) restricted to parity p; same = in at parity p,
+// other = in at parity 1 - p, W = the layer's 9 x 16 complex weights.
+__global__ __launch_bounds__(NET_BLK) void net_layer_kernel(Geo g, int p, Field<P32> out,
+                                                            Field<P32> same, Field<P32> other,
+                                                            const float2* __restrict__ gauge,
+                                                            const float2* __restrict__ W) {
+  __shared__ C<float> ws[NET_W];
+  for (int i = threadIdx.x; i < NET_W; i += blockDim.x) ws[i] = C<float>{W[i].x, W[i].y};
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.vh) return;
+  C<float> acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = C<float>{0.f, 0.f};
+  {
+    C<float> v[12];
+    load_raw<P32>(same, s, v);
+    spin_mix_add(ws, v, 1.f, acc);
+  }
+  int l[4], tc[4];
+  site_local(g, p, s, l, tc);
+  const int x3 = tc[3] * g.T[3] + l[3];
+  layer_hop<0, false>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+  layer_hop<0, true>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+  layer_hop<1, false>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+  layer_hop<1, true>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+  layer_hop<2, false>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+  layer_hop<2, true>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+  layer_hop<3, false>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+  layer_hop<3, true>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+  store_spinor<P32>(out, s, acc);
+}
+
+// Per-workgroup partial of sum_{x in parity p, colour} g(x) (T_k psi)(x)^+
+// for k = blockIdx.y: 16 complex as 32 doubles, part[(k * nblocks + b) * 32 + j].
+__global__ __launch_bounds__(256) void net_wgrad_kernel(Geo g, int p, Field<P32> up,
+                                                        Field<P32> same, Field<P32> other,
+                                                        const float2* __restrict__ gauge,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[32][16];
+  const int k = blockIdx.y;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double o[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) o[j] = 0.0;
+  if (s < g.vh) {
+    C<float> t[12], gv[12];
+    if (k == 0) {
+      load_raw<P32>(same, s, t);
+    } else {
+      int l[4], tc[4];
+      site_local(g, p, s, l, tc);
+      const int x3 = tc[3] * g.T[3] + l[3];
+      switch (k) {
+        case 1: transport<0, false>(g, other, gauge, p, s, l, tc, x3, t); break;
+        case 2: transport<0, true>(g, other, gauge, p, s, l, tc, x3, t); break;
+        case 3: transport<1, false>(g, other, gauge, p, s, l, tc, x3, t); break;
+        case 4: transport<1, true>(g, other, gauge, p, s, l, tc, x3, t); break;
+        case 5: transport<2, false>(g, other, gauge, p, s, l, tc, x3, t); break;
+        case 6: transport<2, true>(g, other, gauge, p, s, l, tc, x3, t); break;
+        case 7: transport<3, false>(g, other, gauge, p, s, l, tc, x3, t); break;
+        default: transport<3, true>(g, other, gauge, p, s, l, tc, x3, t); break;
+      }
+    }
+    load_raw<P32>(up, s, gv);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {  // g[a][c] * conj(t[b][c])
+          const C<float> x = gv[a * 3 + c], y = t[b * 3 + c];
+          re += (double)x.re * y.re + (double)x.im * y.im;
+          im += (double)x.im * y.re - (double)x.re * y.im;
+        }
+        o[2 * (a * 4 + b)] = re;
+        o[2 * (a * 4 + b) + 1] = im;
+      }
+  }
+  block_sum<32>(o, sh);
+  if (threadIdx.x == 0) {
+    double* dst = part + ((int64_t)k * gridDim.x + blockIdx.x) * 32;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) dst[j] = o[j];
+  }
+}
+
+// grad[k][j] += sum over blocks of part[k][block][j]; workgroup k, threads
+// (column = tid % 32, lane = tid / 32).
+__global__ __launch_bounds__(256) void net_wgrad_finalize(const double* __restrict__ part,
+                                                          int nblocks, double2* __restrict__ grad) {
+  __shared__ double sh[8][32];
+  const int k = blockIdx.x, col = threadIdx.x & 31, lane = threadIdx.x >> 5;
+  double t = 0.0;
+  for (int b = lane; b < nblocks; b += 8) t += part[((int64_t)k * nblocks + b) * 32 + col];
+  sh[lane][col] = t;
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    double tot = 0.0;
+    for (int q = 0; q < 8; ++q) tot += sh[q][col];
+    double* gd = reinterpret_cast<double*>(grad + k * 16);
+    gd[col] += tot;
+  }
+}
+
+// Adjoint weight sets: W0^+, and forward/backward hop weights swapped and
+// conjugate-transposed.
+__global__ void net_adjoint_kernel(const float2* __restrict__ w, float2* __restrict__ wa, int L) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L * NET_W) return;
+  const int l = i / NET_W, r = i % NET_W, k = r / 16, st = r % 16, s = st / 4, t = st % 4;
+  const int ks = k == 0 ? 0 : ((k & 1) ? k + 1 : k - 1);
+  const float2 v = w[l * NET_W + ks * 16 + t * 4 + s];
+  wa[i] = make_float2(v.x, -v.y);
+}
+
+// Adam on the real parameters (Re W, Im W) with gradient 2 (Re, Im) dL/dconj(W);
+// clears the accumulated gradient.
+__global__ void net_adam_kernel(float2* __restrict__ w, float2* __restrict__ m1,
+                                float2* __restrict__ m2, double2* __restrict__ grad, int n,
+                                float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gr = (float)(2.0 * grad[i].x), gi = (float)(2.0 * grad[i].y);
+  float2 a = m1[i], b = m2[i], x = w[i];
+  a.x = b1 * a.x + (1.f - b1) * gr;
+  a.y = b1 * a.y + (1.f - b1) * gi;
+  b.x = b2 * b.x + (1.f - b2) * gr * gr;
+  b.y = b2 * b.y + (1.f - b2) * gi * gi;
+  x.x -= lr * (a.x / c1) / (sqrtf(b.x / c2) + eps);
+  x.y -= lr * (a.y / c1) / (sqrtf(b.y / c2) + eps);
+  m1[i] = a;
+  m2[i] = b;
+  w[i] = x;
+  grad[i] = make_double2(0.0, 0.0);
+}
+
+// FP32 full-field helpers
+__global__ void net_zero_kernel(float4* __restrict__ p, int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n4) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+void zero_bytes(lq_ctx* ctx, void* p, size_t bytes) {
+  const int64_t n4 = (int64_t)(bytes / 16);
+  hipLaunchKernelGGL(net_zero_kernel, dim3(grid_for(n4, 256)), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<float4*>(p), n4);
+  LQ_HIP(hipGetLastError());
+}
+
+// out = a x + b y on FP32 fields of `bytes` bytes (elementwise; layout-free)
+__global__ void net_axpby_kernel(float4* __restrict__ out, float a, const float4* __restrict__ x,
+                                 float b, const float4* __restrict__ y, int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  const float4 u = x[i], v = y[i];
+  out[i] = make_float4(a * u.x + b * v.x, a * u.y + b * v.y, a * u.z + b * v.z, a * u.w + b * v.w);
+}
+
+void axpby_f32_impl(lq_ctx* ctx, void* out, double a, const void* x, double b, const void* y) {
+  const int64_t n4 = (int64_t)(parity_field_bytes(ctx->geo.nblk, LQ_F32) / 16);
+  hipLaunchKernelGGL(net_axpby_kernel, dim3(grid_for(n4, 256)), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<float4*>(out), (float)a, reinterpret_cast<const float4*>(x),
+                     (float)b, reinterpret_cast<const float4*>(y), n4);
+  LQ_HIP(hipGetLastError());
+}
+
+// y += c x for complex c, elementwise over the complex entries of two
+// fields of one parity (FP32 y and x, or FP64 y and FP32 x): the component
+// order is the same in every precision.
+template <class TY>
+__global__ void net_caxpy_kernel(TY* __restrict__ y, double cr, double ci,
+                                 const float2* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float2 v = x[i];
+  TY o = y[i];
+  o.x += (cr * v.x - ci * v.y);
+  o.y += (cr * v.y + ci * v.x);
+  y[i] = o;
+}
+
+void copy_bytes(lq_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  LQ_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->cur));
+}
+
+// one layer on full fields: out = layer(in) with weight set W (both parities)
+void layer(lq_ctx* ctx, const float2* W, void* out, void* in) {
+  const Geo& g = ctx->geo;
+  const auto* gauge = reinterpret_cast<const float2*>(ctx->gauge[LQ_F32]);
+  for (int p = 0; p < 2; ++p)
+    hipLaunchKernelGGL(net_layer_kernel, dim3(grid_for(g.vh, NET_BLK)), dim3(NET_BLK), 0,
+                       ctx->cur, g, p, field_at<P32>(half32(out, ctx, p), g.nblk),
+                       field_at<P32>(half32(in, ctx, p), g.nblk),
+                       field_at<P32>(half32(in, ctx, 1 - p), g.nblk), gauge, W);
+  LQ_HIP(hipGetLastError());
+  // bytes: 8 neighbours and the site read (with reuse: twice per site), 8 FP32 links, write
+  ctx->bytes += (double)ctx->V * (2.0 * 96 + 8 * 48 + 96);
+}
+
+void ensure_adjoint(Net* n) {
+  if (n->adj_ok) return;
+  const int tot = n->L * NET_W;
+  hipLaunchKernelGGL(net_adjoint_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, n->ctx->cur, n->w,
+                     n->wadj, n->L);
+  LQ_HIP(hipGetLastError());
+  n->adj_ok = true;
+}
+
+// full-field forward through all layers, keeping the activations act[0..L];
+// act[0] must hold the input
+void forward_all(Net* n) {
+  lq_ctx* ctx = n->ctx;
+  const size_t fb = full32(ctx);
+  char* a = reinterpret_cast<char*>(n->act);
+  for (int l = 0; l < n->L; ++l) layer(ctx, n->w + l * NET_W, a + (l + 1) * fb, a + l * fb);
+}
+
+}  // namespace
+
+Net* net_create(lq_ctx* ctx, int L) {
+  LQ_CHECK(L >= 1 && L <= 16, LQ_EINVAL, "a net has 1..16 layers");
+  LQ_CHECK(ctx->have_gauge, LQ_ESTATE, "no gauge field uploaded");
+  Net* n = new Net();
+  n->ctx = ctx;
+  n->L = L;
+  try {
+    const size_t wb = (size_t)L * NET_W * sizeof(float2);
+    LQ_HIP(hipMalloc(&n->w, wb));
+    LQ_HIP(hipMalloc(&n->wadj, wb));
+    LQ_HIP(hipMalloc(&n->m1, wb));
+    LQ_HIP(hipMalloc(&n->m2, wb));
+    LQ_HIP(hipMalloc(&n->grad, (size_t)L * NET_W * sizeof(double2)));
+    LQ_HIP(hipMemset(n->w, 0, wb));
+    LQ_HIP(hipMemset(n->m1, 0, wb));
+    LQ_HIP(hipMemset(n->m2, 0, wb));
+    LQ_HIP(hipMemset(n->grad, 0, (size_t)L * NET_W * sizeof(double2)));
+    n->nblk_grad = grid_for(ctx->geo.vh, 256);
+    LQ_HIP(hipMalloc(&n->part, (size_t)NET_K * n->nblk_grad * 32 * sizeof(double)));
+    const size_t fb = full32(ctx);
+    LQ_HIP(hipMalloc(&n->act, (size_t)(L + 1) * fb));
+    LQ_HIP(hipMalloc(&n->gbuf[0], fb));
+    LQ_HIP(hipMalloc(&n->gbuf[1], fb));
+  } catch (...) {
+    net_destroy(n);
+    throw;
+  }
+  return n;
+}
+
+void net_destroy(Net* n) {
+  if (!n) return;
+  for (void* p : {(void*)n->w, (void*)n->wadj, (void*)n->m1, (void*)n->m2, (void*)n->grad,
+                  (void*)n->part, n->act, n->gbuf[0], n->gbuf[1]})
+    if (p) (void)hipFree(p);
+  delete n;
+}
+
+int net_layers(const Net* n) { return n->L; }
+lq_ctx* net_ctx(const Net* n) { return n->ctx; }
+
+void net_set_weights(Net* n, const double* host) {
+  std::vector<float2> h((size_t)n->L * NET_W);
+  for (size_t i = 0; i < h.size(); ++i) {
+    h[i] = make_float2((float)host[2 * i], (float)host[2 * i + 1]);
+    LQ_CHECK(std::isfinite(host[2 * i]) && std::isfinite(host[2 * i + 1]), LQ_EINVAL,
+             "non-finite weight");
+  }
+  LQ_HIP(hipMemcpy(n->w, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice));
+  LQ_HIP(hipMemset(n->m1, 0, h.size() * sizeof(float2)));
+  LQ_HIP(hipMemset(n->m2, 0, h.size() * sizeof(float2)));
+  LQ_HIP(hipMemset(n->grad, 0, h.size() * sizeof(double2)));
+  n->step = 0;
+  n->adj_ok = false;
+}
+
+void net_get_weights(Net* n, double* host) {
+  std::vector<float2> h((size_t)n->L * NET_W);
+  LQ_HIP(hipStreamSynchronize(n->ctx->cur));
+  LQ_HIP(hipMemcpy(h.data(), n->w, h.size() * sizeof(float2), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < h.size(); ++i) {
+    host[2 * i] = h[i].x;
+    host[2 * i + 1] = h[i].y;
+  }
+}
+
+void net_get_grad(Net* n, double* host) {
+  LQ_HIP(hipStreamSynchronize(n->ctx->cur));
+  LQ_HIP(hipMemcpy(host, n->grad, (size_t)n->L * NET_W * sizeof(double2), hipMemcpyDeviceToHost));
+}
+
+void net_zero_grad(Net* n) {
+  LQ_HIP(hipMemsetAsync(n->grad, 0, (size_t)n->L * NET_W * sizeof(double2), n->ctx->cur));
+}
+
+// y_e = N_e x_e (adjoint: N_e^+ x_e) on FP32 even fields
+void net_apply_even(Net* n, void* y_e, const void* x_e, bool adjoint) {
+  lq_ctx* ctx = n->ctx;
+  const size_t hb = parity_field_bytes(ctx->geo.nblk, LQ_F32);
+  const size_t fb = full32(ctx);
+  if (adjoint) ensure_adjoint(n);
+  const float2* W = adjoint ? n->wadj : n->w;
+  // ping-pong between two full fields; the adjoint of E_e ... P_e runs the
+  // adjoint layers in reverse order
+  char* bufs[2] = {reinterpret_cast<char*>(n->gbuf[0]), reinterpret_cast<char*>(n->gbuf[1])};
+  copy_bytes(ctx, bufs[0], x_e, hb);
+  zero_bytes(ctx, bufs[0] + hb, fb - hb);
+  int cur = 0;
+  for (int i = 0; i < n->L; ++i) {
+    const int l = adjoint ? n->L - 1 - i : i;
+    layer(ctx, W + l * NET_W, bufs[1 - cur], bufs[cur]);
+    cur = 1 - cur;
+  }
+  copy_bytes(ctx, y_e, bufs[cur], hb);
+}
+
+// One pair's term of the loss, weight * |N_e b - x|^2 / |x|^2, and the
+// accumulation of its gradient (FP32 even fields b, x).
+double loss_grad_one(Net* n, const void* b, const void* x, double weight) {
+  lq_ctx* ctx = n->ctx;
+  const Geo& g = ctx->geo;
+  const size_t hb = parity_field_bytes(g.nblk, LQ_F32);
+  const size_t fb = full32(ctx);
+  ensure_adjoint(n);
+  char* act = reinterpret_cast<char*>(n->act);
+  const auto* gauge = reinterpret_cast<const float2*>(ctx->gauge[LQ_F32]);
+  copy_bytes(ctx, act, b, hb);
+  zero_bytes(ctx, act + hb, fb - hb);
+  forward_all(n);
+  char* out = act + (size_t)n->L * fb;
+  // upstream gradient: E_e (y_e - x) weight / |x|^2, held in gbuf[0]
+  char* up = reinterpret_cast<char*>(n->gbuf[0]);
+  double xn = 0.0, dn = 0.0;
+  norm2(ctx, &xn, x, LQ_F32);
+  LQ_CHECK(xn > 0.0, LQ_EINVAL, "zero training target");
+  axpby_f32_impl(ctx, up, 1.0, out, -1.0, x);
+  norm2(ctx, &dn, up, LQ_F32);
+  axpby_f32_impl(ctx, up, weight / xn, up, 0.0, up);
+  zero_bytes(ctx, up + hb, fb - hb);
+  // backward through the layers
+  int cur = 0;
+  for (int l = n->L - 1; l >= 0; --l) {
+    char* gl = reinterpret_cast<char*>(n->gbuf[cur]);
+    char* al = act + (size_t)l * fb;
+    for (int p = 0; p < 2; ++p) {
+      hipLaunchKernelGGL(net_wgrad_kernel, dim3(n->nblk_grad, NET_K), dim3(256), 0, ctx->cur, g,
+                         p, field_at<P32>(half32(gl, ctx, p), g.nblk),
+                         field_at<P32>(half32(al, ctx, p), g.nblk),
+                         field_at<P32>(half32(al, ctx, 1 - p), g.nblk), gauge, n->part);
+      hipLaunchKernelGGL(net_wgrad_finalize, dim3(NET_K), dim3(256), 0, ctx->cur, n->part,
+                         n->nblk_grad, n->grad + l * NET_W);
+    }
+    LQ_HIP(hipGetLastError());
+    if (l > 0) {
+      layer(ctx, n->wadj + l * NET_W, n->gbuf[1 - cur], gl);
+      cur = 1 - cur;
+    }
+  }
+  return weight * dn / xn;
+}
+
+// Loss mean_i |N_e b_i - x_i|^2 / |x_i|^2 over npairs pairs of FP32 even
+// fields (npairs consecutive fields each); the gradient of this loss
+// replaces the accumulated one.
+double net_loss_grad(Net* n, const void* b, const void* x, int npairs) {
+  LQ_CHECK(npairs >= 1, LQ_EINVAL, "no pairs");
+  const size_t hb = parity_field_bytes(n->ctx->geo.nblk, LQ_F32);
+  net_zero_grad(n);
+  double loss = 0.0;
+  for (int i = 0; i < npairs; ++i)
+    loss += loss_grad_one(n, reinterpret_cast<const char*>(b) + (size_t)i * hb,
+                          reinterpret_cast<const char*>(x) + (size_t)i * hb, 1.0 / npairs);
+  return loss;
+}
+
+void net_adam(Net* n, double lr, double b1, double b2, double eps) {
+  n->step += 1;
+  const int tot = n->L * NET_W;
+  const float c1 = (float)(1.0 - std::pow(b1, (double)n->step));
+  const float c2 = (float)(1.0 - std::pow(b2, (double)n->step));
+  hipLaunchKernelGGL(net_adam_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, n->ctx->cur, n->w,
+                     n->m1, n->m2, n->grad, tot, (float)lr, (float)b1, (float)b2, (float)eps, c1,
+                     c2);
+  LQ_HIP(hipGetLastError());
+  n->adj_ok = false;
+}
+
+// Training: epochs over npairs (b, x) FP32 even fields in shuffled batches
+// (a fixed-seed permutation per epoch), one Adam step per batch; returns the
+// mean loss of each epoch in hist (nullable).
+void net_train(Net* n, const void* b, const void* x, int npairs, int epochs, int batch, double lr,
+               unsigned seed, double* hist) {
+  LQ_CHECK(npairs >= 1 && epochs >= 1 && batch >= 1, LQ_EINVAL, "bad training sizes");
+  lq_ctx* ctx = n->ctx;
+  const size_t hb = parity_field_bytes(ctx->geo.nblk, LQ_F32);
+  std::vector<int> perm(npairs);
+  for (int i = 0; i < npairs; ++i) perm[i] = i;
+  uint64_t st = 0x9e3779b97f4a7c15ull ^ seed;
+  auto rnd = [&st]() {  // splitmix64
+    st += 0x9e3779b97f4a7c15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+  };
+  net_zero_grad(n);
+  for (int e = 0; e < epochs; ++e) {
+    for (int i = npairs - 1; i > 0; --i) std::swap(perm[i], perm[(int)(rnd() % (uint64_t)(i + 1))]);
+    double tot = 0.0;
+    for (int s0 = 0; s0 < npairs; s0 += batch) {
+      const int nb = std::min(batch, npairs - s0);
+      double bl = 0.0;
+      for (int j = 0; j < nb; ++j) {
+        const int q = perm[s0 + j];
+        bl += loss_grad_one(n, reinterpret_cast<const char*>(b) + (size_t)q * hb,
+                            reinterpret_cast<const char*>(x) + (size_t)q * hb, 1.0 / nb);
+      }
+      if (!std::isfinite(bl)) throw Error(LQ_ENAN, "non-finite training loss");
+      net_adam(n, lr, 0.9, 0.999, 1e-8);
+      tot += bl * nb;
+    }
+    if (hist) hist[e] = tot / npairs;
+  }
+}
+
+void caxpy_f32(lq_ctx* ctx, void* y, double cr, double ci, const void* x) {
+  const int64_t n = ctx->geo.nblk * SB * 12;
+  hipLaunchKernelGGL(net_caxpy_kernel<float2>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<float2*>(y), cr, ci, reinterpret_cast<const float2*>(x), n);
+  LQ_HIP(hipGetLastError());
+  ctx->bytes += (double)ctx->geo.vh * 3 * 96;
+}
+
+void caxpy_64_32(lq_ctx* ctx, void* y64, double cr, double ci, const void* x32) {
+  const int64_t n = ctx->geo.nblk * SB * 12;
+  hipLaunchKernelGGL(net_caxpy_kernel<double2>, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<double2*>(y64), cr, ci, reinterpret_cast<const float2*>(x32),
+                     n);
+  LQ_HIP(hipGetLastError());
+  ctx->bytes += (double)ctx->geo.vh * (2 * 192 + 96);
+}
+
+void axpby_f32(lq_ctx* ctx, void* out, double a, const void* x, double b, const void* y) {
+  axpby_f32_impl(ctx, out, a, x, b, y);
+  ctx->bytes += (double)ctx->geo.vh * 3 * 96;
+}
+
+}  // namespace lq

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 
 #include "bicgstab_kernels.h"
@@ -56,6 +57,8 @@ struct Work {
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};
   int graph_iters[3] = {0, 0, 0};
   double graph_k2[3] = {0, 0, 0};
+  // learned-preconditioner solvers: FP32 one-parity fields
+  std::vector<void*> nv, nz, nx;  // Krylov basis, preconditioned basis, work
 };
 
 namespace {
@@ -572,9 +575,209 @@ bool bicgstab(lq_ctx* ctx, Work* w, double target, double delta, int maxiter, in
   }
 }
 
+// ------------------------------------------------------------ learned preconditioner
+// Flexible Krylov solvers with the net N_e: FGMRES(m) on Mhat with N_e as
+// right preconditioner, and flexible CG on Mhat^+ Mhat with N_e N_e^+.  The
+// inner cycles run in FP32 and restart from the FP64 residual of the Schur
+// system (the solution accumulates in FP64); a solve that stagnates, breaks
+// down or runs out of iterations is handed to the plain mixed CG.
+using cplx = std::complex<double>;
+
+void* f32_buf(std::vector<void*>& v, size_t i, size_t bytes) {
+  while (v.size() <= i) v.push_back(dalloc(bytes));
+  return v[i];
+}
+
+cplx cdot32(lq_ctx* ctx, const void* a, const void* b) {
+  double r[2];
+  dot(ctx, r, a, b, LQ_F32);
+  return {r[0], r[1]};
+}
+
+double nrm32(lq_ctx* ctx, const void* a) {
+  double v = 0.0;
+  norm2(ctx, &v, a, LQ_F32);
+  return v;
+}
+
+// Restart bookkeeping shared by both solvers: true residual, stop, stall.
+// Returns 1 = converged, 0 = continue, -1 = give up (fb set for breakdowns).
+int net_restart(lq_ctx* ctx, Work* w, double target, int maxiter, double& best, int& stalls,
+                SolveStats& ss, bool& fb, double& beta) {
+  beta = std::sqrt(schur_residual(ctx, w, ss));
+  if (!std::isfinite(beta)) {
+    fb = true;
+    return -1;
+  }
+  if (beta <= target) return 1;
+  if (ss.iterations >= maxiter) return -1;
+  if (beta < 0.5 * best) {
+    best = beta;
+    stalls = 0;
+  } else if (++stalls >= 3) {
+    fb = true;
+    return -1;
+  }
+  ss.reliable += 1;
+  return 0;
+}
+
+bool fgmres_net(lq_ctx* ctx, Work* w, Net* net, double target, int maxiter, int m,
+                SolveStats& ss, bool& fb) {
+  const size_t f32 = parity_field_bytes(ctx->geo.nblk, LQ_F32);
+  std::vector<void*>& V = w->nv;
+  std::vector<void*>& Z = w->nz;
+  for (int i = 0; i <= m; ++i) f32_buf(V, i, f32);
+  for (int i = 0; i < m; ++i) f32_buf(Z, i, f32);
+  void* wv = f32_buf(w->nx, 0, f32);
+  void* to32 = f32_buf(w->nx, 1, f32);
+  const int L = net_layers(net);
+  double best = INFINITY, beta = 0.0;
+  int stalls = 0;
+  for (;;) {
+    const int st = net_restart(ctx, w, target, maxiter, best, stalls, ss, fb, beta);
+    if (st != 0) return st > 0;
+    axpby<P64, P64, P32>(ctx, V[0], 1.0 / beta, w->r64, 0.0, w->r64);
+    std::vector<cplx> H((size_t)(m + 1) * m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
+    std::vector<double> cs(m, 1.0);
+    g[0] = beta;
+    // an FP32 cycle reduces the residual by at most about 1e-5 reliably
+    const double inner_target = std::max(1e-4 * beta, 0.5 * target);
+    int k = 0;
+    while (k < m && ss.iterations < maxiter) {
+      net_apply_even(net, Z[k], V[k], false);
+      schur(ctx, wv, Z[k], to32, 0, LQ_F32);
+      ss.dslash += 2 + 2 * L;
+      ss.iterations += 1;
+      for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, applied twice
+        std::vector<cplx> c(k + 1);
+        for (int i = 0; i <= k; ++i) c[i] = cdot32(ctx, V[i], wv);
+        for (int i = 0; i <= k; ++i) {
+          caxpy_f32(ctx, wv, -c[i].real(), -c[i].imag(), V[i]);
+          H[(size_t)i * m + k] += c[i];
+        }
+      }
+      const double hn = std::sqrt(nrm32(ctx, wv));
+      if (!std::isfinite(hn)) {
+        fb = true;
+        return false;
+      }
+      H[(size_t)(k + 1) * m + k] = hn;
+      if (hn > 0.0) axpby_f32(ctx, V[k + 1], 1.0 / hn, wv, 0.0, wv);
+      // previous Givens rotations on column k, then the one that clears H[k+1][k]
+      for (int i = 0; i < k; ++i) {
+        const cplx a = H[(size_t)i * m + k], b = H[(size_t)(i + 1) * m + k];
+        H[(size_t)i * m + k] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * m + k] = -std::conj(sn[i]) * a + cs[i] * b;
+      }
+      const cplx a = H[(size_t)k * m + k], b = H[(size_t)(k + 1) * m + k];
+      const double rho = std::sqrt(std::norm(a) + std::norm(b));
+      if (std::abs(a) == 0.0) {
+        cs[k] = 0.0;
+        sn[k] = 1.0;
+      } else {
+        cs[k] = std::abs(a) / rho;
+        sn[k] = (a / std::abs(a)) * std::conj(b) / rho;
+      }
+      H[(size_t)k * m + k] = cs[k] * a + sn[k] * b;
+      H[(size_t)(k + 1) * m + k] = 0.0;
+      g[k + 1] = -std::conj(sn[k]) * g[k];
+      g[k] = cs[k] * g[k];
+      k += 1;
+      if (std::abs(g[k]) <= inner_target || hn == 0.0) break;
+    }
+    // y = R^-1 g, x_e += Z y
+    std::vector<cplx> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      cplx t = g[i];
+      for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * y[j];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    for (int i = 0; i < k; ++i) {
+      if (!std::isfinite(y[i].real()) || !std::isfinite(y[i].imag())) {
+        fb = true;
+        return false;
+      }
+      caxpy_64_32(ctx, w->x, y[i].real(), y[i].imag(), Z[i]);
+    }
+  }
+}
+
+bool fcg_net(lq_ctx* ctx, Work* w, Net* net, double target, int maxiter, SolveStats& ss,
+             bool& fb) {
+  const size_t f32 = parity_field_bytes(ctx->geo.nblk, LQ_F32);
+  for (int i = 0; i < 8; ++i) f32_buf(w->nx, i, f32);
+  void *r = w->nx[0], *z = w->nx[1], *p = w->nx[2], *q = w->nx[3], *t = w->nx[4],
+       *xl = w->nx[5], *to32 = w->nx[6], *u = w->nx[7];
+  const int L = net_layers(net);
+  double best = INFINITY, beta = 0.0;
+  int stalls = 0;
+  auto precond = [&](void* out, const void* in) {  // out = N_e N_e^+ in
+    net_apply_even(net, u, in, true);
+    net_apply_even(net, out, u, false);
+    ss.dslash += 4 * L;
+  };
+  for (;;) {
+    const int st = net_restart(ctx, w, target, maxiter, best, stalls, ss, fb, beta);
+    if (st != 0) return st > 0;
+    schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
+    ss.dslash += 2;
+    axpby<P64, P64, P32>(ctx, r, 1.0, w->rn64, 0.0, w->rn64);
+    const double rn0 = std::sqrt(nrm32(ctx, r));
+    axpby_f32(ctx, xl, 0.0, r, 0.0, r);
+    precond(z, r);
+    axpby_f32(ctx, p, 1.0, z, 0.0, z);
+    for (;;) {
+      schur(ctx, t, p, to32, 0, LQ_F32);
+      schur(ctx, q, t, to32, 1, LQ_F32);
+      ss.dslash += 4;
+      ss.iterations += 1;
+      const cplx pq = cdot32(ctx, p, q), pr = cdot32(ctx, p, r);
+      if (!(pq.real() > 0.0) || !std::isfinite(pq.real())) {
+        fb = true;
+        return false;
+      }
+      const cplx al = pr / pq;
+      caxpy_f32(ctx, xl, al.real(), al.imag(), p);
+      caxpy_f32(ctx, r, -al.real(), -al.imag(), q);
+      const double rn = std::sqrt(nrm32(ctx, r));
+      if (!std::isfinite(rn)) {
+        fb = true;
+        return false;
+      }
+      if (rn <= 1e-3 * rn0 || ss.iterations >= maxiter) break;
+      precond(z, r);
+      // p = z + beta p with beta making p conjugate to the previous direction
+      const cplx bt = -cdot32(ctx, q, z) / pq;
+      caxpy_f32(ctx, z, bt.real(), bt.imag(), p);
+      std::swap(w->nx[1], w->nx[2]);
+      z = w->nx[1];
+      p = w->nx[2];
+    }
+    caxpy_64_32(ctx, w->x, 1.0, 0.0, xl);
+  }
+}
+
 bool run_inner(lq_ctx* ctx, Work* w, int solver, int inner, double target, double delta,
                int maxiter, int check_every, bool use_graph, int fault_inject, SolveStats& ss,
-               bool& fb, Prof* pf) {
+               bool& fb, Prof* pf, Net* net, int restart) {
+  if (solver == LQ_FGMRES_NET || solver == LQ_FCG_NET) {
+    // the plain mixed CG takes over where the flexible solver gave up
+    const bool conv = solver == LQ_FGMRES_NET
+                          ? fgmres_net(ctx, w, net, target, maxiter, restart, ss, fb)
+                          : fcg_net(ctx, w, net, target, maxiter, ss, fb);
+    if (conv) return true;
+    fb = false;
+    ss.fallback = 1;
+    work(ctx, LQ_F32);
+    SolveStats f_ss;
+    const bool c2 = run_cg(ctx, w, LQ_F32, target, 0.1, std::max(1, maxiter - ss.iterations),
+                           check_every, use_graph, 0, f_ss, fb, pf);
+    ss.iterations += f_ss.iterations;
+    ss.reliable += f_ss.reliable;
+    ss.dslash += f_ss.dslash + 4 * f_ss.iterations;
+    return c2;
+  }
   if (solver == LQ_CGNR)
     return run_cg(ctx, w, inner, target, delta, maxiter, check_every, use_graph, fault_inject, ss,
                   fb, pf);
@@ -636,6 +839,8 @@ void free_work(lq_ctx* ctx) {
   if (w->st_host) (void)hipHostFree(w->st_host);
   if (w->bst) (void)hipFree(w->bst);
   if (w->bst_host) (void)hipHostFree(w->bst_host);
+  for (auto* v : {&w->nv, &w->nz, &w->nx})
+    for (void* q : *v) (void)hipFree(q);
   delete w;
   ctx->work = nullptr;
 }
@@ -899,15 +1104,21 @@ void solve_batched(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_
 
 void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const void* dev_b,
            int nrhs, double kappa, double csw, double tol, const lq_solver_params* prm,
-           lq_solve_report* report) {
+           lq_solve_report* report, Net* net) {
   lq_solver_params p{};
   if (prm) p = *prm;
-  const int inner = p.inner_prec;
+  const bool net_solver = p.solver == LQ_FGMRES_NET || p.solver == LQ_FCG_NET;
+  // the flexible solvers run their inner cycles in FP32
+  const int inner = net_solver ? LQ_F32 : p.inner_prec;
   LQ_CHECK(inner == LQ_F64 || inner == LQ_F32 || inner == LQ_F16, LQ_EINVAL,
            "bad inner precision");
-  LQ_CHECK(p.solver == LQ_CGNR || p.solver == LQ_BICGSTAB, LQ_EINVAL,
-           "solver kind not available through lq_solve (learned-preconditioner solvers take a "
-           "net: lq_solve_net)");
+  LQ_CHECK(p.solver == LQ_CGNR || p.solver == LQ_BICGSTAB || net_solver, LQ_EINVAL,
+           "unknown solver kind");
+  LQ_CHECK(!net_solver || net, LQ_EINVAL,
+           "learned-preconditioner solvers take a net (lq_solve_net)");
+  LQ_CHECK(!net || net_ctx(net) == ctx, LQ_EINVAL, "the net belongs to another context");
+  const int restart = p.restart > 0 ? p.restart : 16;
+  LQ_CHECK(restart <= 128, LQ_EINVAL, "restart length above 128");
   const int maxiter = p.maxiter > 0 ? p.maxiter : 20000;
   const double delta = inner == LQ_F64 ? 0.0 : (p.delta > 0.0 ? p.delta : 0.1);
   const int check_every = p.check_every > 0 ? p.check_every : 8;
@@ -989,10 +1200,12 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
         SolveStats inner_ss;
         bool conv = run_inner(ctx, w, p.solver, ss.fallback ? LQ_F64 : inner, frac * tol * bhat_norm,
                            ss.fallback ? 0.0 : delta, left, check_every, use_graph,
-                           p.fault_inject, inner_ss, fb, prof);
+                           p.fault_inject, inner_ss, fb, prof, net, restart);
         ss.iterations += inner_ss.iterations;
         ss.reliable += inner_ss.reliable;
-        ss.dslash += inner_ss.dslash + 4 * inner_ss.iterations;
+        // the flexible solvers count their own operator applications
+        ss.dslash += inner_ss.dslash + (net_solver ? 0 : 4 * inner_ss.iterations);
+        ss.fallback |= inner_ss.fallback;
         if (fb) {
           ss.fallback = 1;
           work(ctx, LQ_F64);

@@ -93,9 +93,22 @@ def lib():
                                ct.POINTER(SolverParams), ct.POINTER(SolveReport)]
         L.lq_solve_device.argtypes = [vp, vp, vp, ip, ct.c_double, ct.c_double, ct.c_double,
                                       ct.POINTER(SolverParams), ct.POINTER(SolveReport)]
+        L.lq_net_create.argtypes = [vp, ip, ct.POINTER(vp)]
+        L.lq_net_destroy.argtypes = [vp]
+        L.lq_net_destroy.restype = None
+        L.lq_net_set_weights.argtypes = [vp, dp]
+        L.lq_net_get_weights.argtypes = [vp, dp]
+        L.lq_net_apply.argtypes = [vp, vp, vp, ip]
+        L.lq_net_loss_grad.argtypes = [vp, vp, vp, ip, dp, dp]
+        L.lq_net_adam_step.argtypes = [vp, ct.c_double, ct.c_double, ct.c_double, ct.c_double]
+        L.lq_net_train.argtypes = [vp, vp, vp, ip, ip, ip, ct.c_double, ct.c_uint, dp]
+        L.lq_solve_net.argtypes = [vp, vp, dp, dp, ip, ct.c_double, ct.c_double, ct.c_double,
+                                   ct.POINTER(SolverParams), ct.POINTER(SolveReport)]
         for name in ("lq_upload_gauge", "lq_set_clover", "lq_spinor_to_device",
                      "lq_spinor_to_host", "lq_dslash", "lq_clover_apply", "lq_schur",
-                     "lq_norm2", "lq_dot", "lq_solve", "lq_solve_device"):
+                     "lq_norm2", "lq_dot", "lq_solve", "lq_solve_device", "lq_net_create",
+                     "lq_net_set_weights", "lq_net_get_weights", "lq_net_apply",
+                     "lq_net_loss_grad", "lq_net_adam_step", "lq_net_train", "lq_solve_net"):
             getattr(L, name).restype = ip
         _lib = L
     return _lib
@@ -260,3 +273,83 @@ class Lattice:
         if rc != 0 and (rc != -4 or raise_on_noconv):
             self._check(rc)
         return reports
+
+
+NET_K = 9  # weight matrices per layer: W0, then (Wp_mu, Wm_mu) for mu = 0..3
+
+
+class Net:
+    """Learned gauge-covariant preconditioner on a Lattice (see lq_net_* in
+    include/lq.h).  Weights: complex array (nlayers, 9, 4, 4); device fields
+    of its calls: FP32 even fields (Lattice.field_bytes(EVEN, F32, n))."""
+
+    def __init__(self, lat, nlayers=4):
+        self.lat = lat
+        self._L = lat._L
+        self.nlayers = int(nlayers)
+        h = ct.c_void_p()
+        lat._check(self._L.lq_net_create(lat._h, self.nlayers, ct.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.lq_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.complex128)
+        assert w.shape == (self.nlayers, NET_K, 4, 4)
+        self.lat._check(self._L.lq_net_set_weights(self._h, _dptr(w.view(np.float64))))
+
+    def get_weights(self):
+        w = np.zeros((self.nlayers, NET_K, 4, 4), dtype=np.complex128)
+        self.lat._check(self._L.lq_net_get_weights(self._h, _dptr(w.view(np.float64))))
+        return w
+
+    def apply(self, out, inp, adjoint=False):
+        self.lat._check(self._L.lq_net_apply(self._h, ct.c_void_p(out.data_ptr()),
+                                             ct.c_void_p(inp.data_ptr()), int(bool(adjoint))))
+
+    def loss_grad(self, dev_b, dev_x, npairs):
+        loss = np.zeros(1)
+        g = np.zeros((self.nlayers, NET_K, 4, 4), dtype=np.complex128)
+        self.lat._check(self._L.lq_net_loss_grad(self._h, ct.c_void_p(dev_b.data_ptr()),
+                                                 ct.c_void_p(dev_x.data_ptr()), int(npairs),
+                                                 _dptr(loss), _dptr(g.view(np.float64))))
+        return float(loss[0]), g
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.lat._check(self._L.lq_net_adam_step(self._h, lr, beta1, beta2, eps))
+
+    def train(self, dev_b, dev_x, npairs, epochs, batch=8, lr=1e-3, seed=0):
+        hist = np.zeros(int(epochs))
+        self.lat._check(self._L.lq_net_train(self._h, ct.c_void_p(dev_b.data_ptr()),
+                                             ct.c_void_p(dev_x.data_ptr()), int(npairs),
+                                             int(epochs), int(batch), float(lr), int(seed),
+                                             _dptr(hist)))
+        return hist
+
+    def solve(self, b, kappa, csw, tol=1e-10, solver=FGMRES_NET, maxiter=0, restart=0,
+              raise_on_noconv=True):
+        """Solve M x = b (full lattice, host arrays) with a flexible solver
+        preconditioned by this net."""
+        b = np.ascontiguousarray(b, dtype=np.complex128)
+        nrhs = b.size // (self.lat.volume * 12)
+        assert nrhs * self.lat.volume * 12 == b.size
+        x = np.zeros_like(b)
+        p = SolverParams(solver, F32, maxiter, 0.0, restart, 0, 0, 0, 0, 0)
+        reps = (SolveReport * nrhs)()
+        rc = self._L.lq_solve_net(self.lat._h, self._h, _dptr(x.view(np.float64)),
+                                  _dptr(b.view(np.float64)), nrhs, float(kappa), float(csw),
+                                  float(tol), ct.byref(p), reps)
+        reports = [Report(**r.as_dict()) for r in reps]
+        if rc != 0 and (rc != -4 or raise_on_noconv):
+            self.lat._check(rc)
+        return x, reports
+
