@@ -21,6 +21,11 @@ Printed (one JSON line):
                 together through the multi-RHS operator (FP16 on the matrix
                 cores), beside one point source solved alone (plain FP64 and
                 mixed FP16) scaled by 12;
+  learned_preconditioner
+                a 4-layer gauge-covariant net trained on the GPU on
+                (source, solution) pairs the solver generated on a 16^3x32
+                field, then used on the benchmark's 32^3x64 field in flexible
+                CG and FGMRES, beside the plain solves of the same system;
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample.
 
 roofline.traffic is the HBM traffic per launch of the roofline kernel from
@@ -158,6 +163,85 @@ def batched_point_sources(lq, lat, torch, dims):
     return out
 
 
+def learned_preconditioner(lq, lat, torch, db_bench, npairs, epochs):
+    """Train the net on pairs from a 16^3x32 field (its own gauge field and
+    sources), then solve the benchmark system (its source on the device,
+    db_bench) with it."""
+    import numpy as np
+    from gen import fields
+    dt = (16, 16, 16, 32)
+    t0 = time.perf_counter()
+    ut = fields.gauge_field(dt, "smooth", fields.SEED_TRAIN_FIELD)
+    tl = lq.Lattice(dt)
+    tl.upload_gauge(ut)
+    tl.set_clover(KAPPA, CSW)
+    vh = tl.volume // 2
+    rng = np.random.default_rng(fields.SEED_TRAIN_SOURCE)
+    fb32 = tl.field_bytes(lq.EVEN, lq.F32)
+    h64 = tl.field_bytes(lq.EVEN, lq.F64)
+    db, dx = tl.new_field(lq.EVEN, lq.F32, npairs), tl.new_field(lq.EVEN, lq.F32, npairs)
+    dB, dX = tl.new_field(lq.FULL, lq.F64), tl.new_field(lq.FULL, lq.F64)  # odd half of dB: 0
+    for i in range(npairs):
+        be = (rng.standard_normal((vh, 4, 3)) + 1j * rng.standard_normal((vh, 4, 3))) / np.sqrt(2)
+        tl.to_device(be, lq.EVEN, lq.F64, out=dB[:h64])  # b = (b_e, 0): x_e = Mhat^-1 b_e
+        tl.solve_device(dX, dB, KAPPA, CSW, TOL, inner_prec=lq.F16)
+        xe = tl.to_host(dX[:h64], lq.EVEN, lq.F64)
+        tl.to_device(be, lq.EVEN, lq.F32, out=db[i * fb32:(i + 1) * fb32])
+        tl.to_device(xe, lq.EVEN, lq.F32, out=dx[i * fb32:(i + 1) * fb32])
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    ntr = max(1, int(0.9 * npairs))
+    nv = npairs - ntr
+    net = lq.Net(tl, 4)
+    net.init_neumann(KAPPA)
+    w0 = net.get_weights()
+    l0, _ = net.loss_grad(db, dx, ntr)
+    v0 = net.loss_grad(db[ntr * fb32:], dx[ntr * fb32:], nv)[0] if nv else None
+    t0 = time.perf_counter()
+    hist = net.train(db, dx, ntr, epochs=epochs, batch=8, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    l1, _ = net.loss_grad(db, dx, ntr)
+    v1 = net.loss_grad(db[ntr * fb32:], dx[ntr * fb32:], nv)[0] if nv else None
+    w = net.get_weights()
+    del db, dx, dB, dX, net, tl
+    bn = lq.Net(lat, 4)
+    out = {"layers": 4, "train_lattice": list(dt), "pairs": npairs, "train_pairs": ntr,
+           "epochs": epochs, "pair_generation_s": round(t_pairs, 2), "training_s": round(t_train, 2),
+           "loss_train": [round(l0, 5), round(l1, 5)],
+           "loss_valid": [round(v0, 5), round(v1, 5)] if nv else None,
+           "loss_history": [round(float(h), 5) for h in hist], "solves": {}}
+    b_host = lat.to_host(db_bench, lq.FULL, lq.F64)
+    for name, wts, kind in (("fcg_trained", w, lq.FCG_NET), ("fcg_initial", w0, lq.FCG_NET),
+                            ("fgmres_trained", w, lq.FGMRES_NET)):
+        bn.set_weights(wts)
+        t0 = time.perf_counter()
+        _, rep = bn.solve(b_host, KAPPA, CSW, TOL, solver=kind)
+        dt_s = time.perf_counter() - t0
+        out["solves"][name] = {"ms": round(dt_s * 1e3, 1), "iterations": rep[0].iterations,
+                               "restarts": rep[0].reliable_updates, "fallback": rep[0].fallback,
+                               "dslash_equivalents": rep[0].dslash_calls,
+                               "true_residual": rep[0].true_residual}
+    # the net application alone, in the solvers' FP16 form, on the even half of b
+    dn = lat.to_device(lat.to_host(db_bench[:lat.field_bytes(lq.EVEN, lq.F64)], lq.EVEN, lq.F64),
+                       lq.EVEN, lq.F32)
+    dy = lat.new_field(lq.EVEN, lq.F32)
+    bn.set_weights(w)
+    for _ in range(3):
+        bn.apply(dy, dn, fp16=True)
+    a = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(10):
+        bn.apply(dy, dn, fp16=True)
+    e.record()
+    torch.cuda.synchronize()
+    out["net_apply_fp16_ms"] = round(a.elapsed_time(e) / 10, 3)
+    del dn, dy, bn
+    return out
+
+
 def recorded_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     or None when the sources changed since it was taken."""
@@ -207,6 +291,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-net", action="store_true")
+    ap.add_argument("--net-pairs", type=int, default=400)
+    ap.add_argument("--net-epochs", type=int, default=8)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): this build has no "
@@ -334,6 +421,10 @@ def main():
     if not a.no_batched:
         log("12 point sources: batched solve, and one source alone")
         result["batched_12rhs"] = batched_point_sources(lq, lat, torch, dims)
+    if not a.no_net:
+        log(f"learned preconditioner: {a.net_pairs} training pairs, {a.net_epochs} epochs")
+        result["learned_preconditioner"] = learned_preconditioner(lq, lat, torch, db, a.net_pairs,
+                                                                  a.net_epochs)
 
     if not a.no_cpu_baseline:
         log("CPU baseline (oracle)")

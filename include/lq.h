@@ -227,8 +227,18 @@ void lq_net_destroy(lq_net* net);
 lq_status lq_net_set_weights(lq_net* net, const double* host_w);
 lq_status lq_net_get_weights(lq_net* net, double* host_w);
 
-/* dev_out = N_e dev_in, or N_e^+ dev_in when adjoint != 0 (distinct buffers). */
-lq_status lq_net_apply(lq_net* net, void* dev_out, const void* dev_in, int adjoint);
+/* The Neumann start of training: W0 = 1, Wp_mu = -(kappa / w_l)(1 - gamma_mu),
+ * Wm_mu = -(kappa / w_l)(1 + gamma_mu) with w_l = exp(2 pi i (l+1) / (nlayers+1)),
+ * which makes the net the truncated series sum_{n <= nlayers} (kappa H)^n of
+ * the hopping term H (gamma matrices of the chiral basis of lq_dslash). */
+lq_status lq_net_init_neumann(lq_net* net, double kappa);
+
+/* dev_out = N_e dev_in (distinct buffers); mode is a sum of flags:
+ * LQ_NET_ADJOINT applies N_e^+; LQ_NET_FP16 computes with FP16 links and
+ * FP16 activations (per-site FP32 scales) and FP32 accumulation, the form the
+ * solvers use (otherwise FP32 links and activations). */
+enum { LQ_NET_ADJOINT = 1, LQ_NET_FP16 = 2 };
+lq_status lq_net_apply(lq_net* net, void* dev_out, const void* dev_in, int mode);
 
 /* Training loss over npairs (source b_i, target x_i) pairs, each a set of
  * npairs consecutive even fields:  loss = mean_i ||N_e b_i - x_i||^2 / ||x_i||^2.

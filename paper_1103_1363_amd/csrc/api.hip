@@ -1,5 +1,6 @@
 // C ABI entry points (include/lq.h): argument checks, error capture, context
 // lifetime.  No C++ exception crosses this boundary.
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -371,6 +372,14 @@ lq_status lq_net_set_weights(lq_net* net, const double* host_w) {
   });
 }
 
+lq_status lq_net_init_neumann(lq_net* net, double kappa) {
+  if (!net) return LQ_EINVAL;
+  return guarded(net->ctx, [&] {
+    LQ_CHECK(std::isfinite(kappa), LQ_EINVAL, "bad kappa");
+    lq::net_init_neumann(net->impl, kappa);
+  });
+}
+
 lq_status lq_net_get_weights(lq_net* net, double* host_w) {
   if (!net) return LQ_EINVAL;
   return guarded(net->ctx, [&] {
@@ -379,12 +388,16 @@ lq_status lq_net_get_weights(lq_net* net, double* host_w) {
   });
 }
 
-lq_status lq_net_apply(lq_net* net, void* dev_out, const void* dev_in, int adjoint) {
+lq_status lq_net_apply(lq_net* net, void* dev_out, const void* dev_in, int mode) {
   if (!net) return LQ_EINVAL;
   return guarded(net->ctx, [&] {
     LQ_CHECK(dev_out && dev_in && dev_out != dev_in, LQ_EINVAL,
              "null or identical device pointers");
-    lq::net_apply_even(net->impl, dev_out, dev_in, adjoint != 0);
+    LQ_CHECK(mode >= 0 && mode <= 3, LQ_EINVAL, "bad mode");
+    if (mode & LQ_NET_FP16)
+      lq::net_apply_even_fast(net->impl, dev_out, dev_in, (mode & LQ_NET_ADJOINT) != 0);
+    else
+      lq::net_apply_even(net->impl, dev_out, dev_in, (mode & LQ_NET_ADJOINT) != 0);
     LQ_HIP(hipStreamSynchronize(net->ctx->cur));
   });
 }

@@ -355,9 +355,11 @@ int net_layers(const Net* n);
 lq_ctx* net_ctx(const Net* n);
 void net_set_weights(Net* n, const double* host);  // [L][9][4][4] complex
 void net_get_weights(Net* n, double* host);
+void net_init_neumann(Net* n, double kappa);
 void net_get_grad(Net* n, double* host);            // dL/dconj(W) of the last loss
 void net_zero_grad(Net* n);
 void net_apply_even(Net* n, void* y_e, const void* x_e, bool adjoint);
+void net_apply_even_fast(Net* n, void* y_e, const void* x_e, bool adjoint);  // FP16 inside
 double net_loss_grad(Net* n, const void* b, const void* x, int npairs);
 void net_adam(Net* n, double lr, double b1, double b2, double eps);
 void net_train(Net* n, const void* b, const void* x, int npairs, int epochs, int batch, double lr,
@@ -366,6 +368,13 @@ void net_train(Net* n, const void* b, const void* x, int npairs, int epochs, int
 void caxpy_f32(lq_ctx* ctx, void* y, double cr, double ci, const void* x);        // y += c x
 void caxpy_64_32(lq_ctx* ctx, void* y64, double cr, double ci, const void* x32);  // y += c x
 void axpby_f32(lq_ctx* ctx, void* out, double a, const void* x, double b, const void* y);
+constexpr int MDOT_BLOCKS_MAX = 256;  // partial rows per vector of multidot_f32
+// res_host[2i], res_host[2i+1] = <V_i, w> for the nv fields whose device
+// pointers are at vdev; part: nv * 256 * 2 doubles, res_dev: 2 nv doubles
+void multidot_f32(lq_ctx* ctx, const void* vdev, int nv, const void* w, double* part,
+                  double* res_dev, double* res_host);
+// w -= sum_i c_i V_i, c_dev: nv complex (double2) on the device
+void multiaxpy_f32(lq_ctx* ctx, const void* vdev, int nv, const double* c_dev, void* w);
 void mrhs_iterate(lq_ctx* ctx, MRWork* w, int check_every, bool use_graph);
 void mrhs_state_upload(lq_ctx* ctx, MRWork* w);
 void mrhs_state_download(lq_ctx* ctx, MRWork* w);

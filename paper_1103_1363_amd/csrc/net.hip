@@ -23,6 +23,7 @@
 // Wp_mu^+ (backward hop).
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <vector>
 
@@ -48,6 +49,7 @@ struct Net {
   int nblk_grad = 0;
   void* act = nullptr;      // (L + 1) full FP32 fields
   void* gbuf[2] = {nullptr, nullptr};
+  void* fbuf[2] = {nullptr, nullptr};  // FP16 full fields of the fast path (lazy)
   int64_t step = 0;
   bool adj_ok = false;
 };
@@ -74,11 +76,11 @@ __device__ __forceinline__ void spin_mix_add(const C<float>* __restrict__ W, con
 
 // T psi at site s of parity p for hop (MU, BACK): the neighbour spinor of
 // the other parity carried by the link (all four spins), times the time
-// boundary phase.
-template <int MU, bool BACK>
-__device__ __forceinline__ void transport(const Geo& g, const Field<P32>& other,
-                                          const float2* __restrict__ gauge, int p, int64_t s,
-                                          const int l[4], const int tc[4], int x3,
+// boundary phase.  PI: precision of the input field, PL: of the links.
+template <int MU, bool BACK, class PI = P32, class PL = P32>
+__device__ __forceinline__ void transport(const Geo& g, const Field<PI>& other,
+                                          const typename PL::S* __restrict__ gauge, int p,
+                                          int64_t s, const int l[4], const int tc[4], int x3,
                                           C<float> w[12]) {
   float sign = 1.f;
   if constexpr (MU == 3) {
@@ -91,12 +93,12 @@ __device__ __forceinline__ void transport(const Geo& g, const Field<P32>& other,
     y[MU] = (y[MU] == 0) ? g.L[MU] - 1 : y[MU] - 1;
   const int64_t sy = cb_index(g, y);
   C<float> v[12];
-  load_raw<P32>(other, sy, v);
+  sign *= (float)load_raw<PI>(other, sy, v);
   C<float> u[9];
   if constexpr (!BACK)
-    load_link<P32>(gauge, g.nblk, p, MU, s, u);
+    load_link<PL>(gauge, g.nblk, p, MU, s, u);
   else
-    load_link<P32>(gauge, g.nblk, 1 - p, MU, sy, u);
+    load_link<PL>(gauge, g.nblk, 1 - p, MU, sy, u);
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -109,21 +111,27 @@ __device__ __forceinline__ void transport(const Geo& g, const Field<P32>& other,
     }
 }
 
-template <int MU, bool BACK>
-__device__ __forceinline__ void layer_hop(const Geo& g, const Field<P32>& other,
-                                          const float2* __restrict__ gauge, int p, int64_t s,
-                                          const int l[4], const int tc[4], int x3,
+template <int MU, bool BACK, class PI, class PL>
+__device__ __forceinline__ void layer_hop(const Geo& g, const Field<PI>& other,
+                                          const typename PL::S* __restrict__ gauge, int p,
+                                          int64_t s, const int l[4], const int tc[4], int x3,
                                           const C<float>* __restrict__ W, C<float> acc[12]) {
   C<float> w[12];
-  transport<MU, BACK>(g, other, gauge, p, s, l, tc, x3, w);
+  transport<MU, BACK, PI, PL>(g, other, gauge, p, s, l, tc, x3, w);
   spin_mix_add(W + 16 * (BACK ? 2 + 2 * MU : 1 + 2 * MU), w, 1.f, acc);
 }
 
+enum { NET_FULL = 0, NET_SELF = 1, NET_HOPS = 2 };
+
 // out (parity p) = layer(in) restricted to parity p; same = in at parity p,
 // other = in at parity 1 - p, W = the layer's 9 x 16 complex weights.
-__global__ __launch_bounds__(NET_BLK) void net_layer_kernel(Geo g, int p, Field<P32> out,
-                                                            Field<P32> same, Field<P32> other,
-                                                            const float2* __restrict__ gauge,
+// MODE: NET_FULL, NET_SELF (the other parity of the input is zero) or
+// NET_HOPS (this parity of the input is zero).  PS, PO, POUT: precisions of
+// the two input parities and the output; PL: of the links.
+template <class PS, class PO, class POUT, class PL, int MODE>
+__global__ __launch_bounds__(NET_BLK) void net_layer_kernel(Geo g, int p, Field<POUT> out,
+                                                            Field<PS> same, Field<PO> other,
+                                                            const typename PL::S* __restrict__ gauge,
                                                             const float2* __restrict__ W) {
   __shared__ C<float> ws[NET_W];
   for (int i = threadIdx.x; i < NET_W; i += blockDim.x) ws[i] = C<float>{W[i].x, W[i].y};
@@ -133,23 +141,25 @@ __global__ __launch_bounds__(NET_BLK) void net_layer_kernel(Geo g, int p, Field<
   C<float> acc[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = C<float>{0.f, 0.f};
-  {
+  if constexpr (MODE != NET_HOPS) {
     C<float> v[12];
-    load_raw<P32>(same, s, v);
-    spin_mix_add(ws, v, 1.f, acc);
+    const float sc = (float)load_raw<PS>(same, s, v);
+    spin_mix_add(ws, v, sc, acc);
   }
-  int l[4], tc[4];
-  site_local(g, p, s, l, tc);
-  const int x3 = tc[3] * g.T[3] + l[3];
-  layer_hop<0, false>(g, other, gauge, p, s, l, tc, x3, ws, acc);
-  layer_hop<0, true>(g, other, gauge, p, s, l, tc, x3, ws, acc);
-  layer_hop<1, false>(g, other, gauge, p, s, l, tc, x3, ws, acc);
-  layer_hop<1, true>(g, other, gauge, p, s, l, tc, x3, ws, acc);
-  layer_hop<2, false>(g, other, gauge, p, s, l, tc, x3, ws, acc);
-  layer_hop<2, true>(g, other, gauge, p, s, l, tc, x3, ws, acc);
-  layer_hop<3, false>(g, other, gauge, p, s, l, tc, x3, ws, acc);
-  layer_hop<3, true>(g, other, gauge, p, s, l, tc, x3, ws, acc);
-  store_spinor<P32>(out, s, acc);
+  if constexpr (MODE != NET_SELF) {
+    int l[4], tc[4];
+    site_local(g, p, s, l, tc);
+    const int x3 = tc[3] * g.T[3] + l[3];
+    layer_hop<0, false, PO, PL>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+    layer_hop<0, true, PO, PL>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+    layer_hop<1, false, PO, PL>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+    layer_hop<1, true, PO, PL>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+    layer_hop<2, false, PO, PL>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+    layer_hop<2, true, PO, PL>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+    layer_hop<3, false, PO, PL>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+    layer_hop<3, true, PO, PL>(g, other, gauge, p, s, l, tc, x3, ws, acc);
+  }
+  store_spinor<POUT>(out, s, acc);
 }
 
 // Per-workgroup partial of sum_{x in parity p, colour} g(x) (T_k psi)(x)^+
@@ -311,13 +321,31 @@ void layer(lq_ctx* ctx, const float2* W, void* out, void* in) {
   const Geo& g = ctx->geo;
   const auto* gauge = reinterpret_cast<const float2*>(ctx->gauge[LQ_F32]);
   for (int p = 0; p < 2; ++p)
-    hipLaunchKernelGGL(net_layer_kernel, dim3(grid_for(g.vh, NET_BLK)), dim3(NET_BLK), 0,
-                       ctx->cur, g, p, field_at<P32>(half32(out, ctx, p), g.nblk),
+    hipLaunchKernelGGL((net_layer_kernel<P32, P32, P32, P32, NET_FULL>),
+                       dim3(grid_for(g.vh, NET_BLK)), dim3(NET_BLK), 0, ctx->cur, g, p,
+                       field_at<P32>(half32(out, ctx, p), g.nblk),
                        field_at<P32>(half32(in, ctx, p), g.nblk),
                        field_at<P32>(half32(in, ctx, 1 - p), g.nblk), gauge, W);
   LQ_HIP(hipGetLastError());
-  // bytes: 8 neighbours and the site read (with reuse: twice per site), 8 FP32 links, write
+  // bytes: the input at this site and (reused) at the neighbours, 8 FP32 links, the output
   ctx->bytes += (double)ctx->V * (2.0 * 96 + 8 * 48 + 96);
+}
+
+// one parity of a layer in the fast precision set (FP16 links)
+template <class PS, class PO, class POUT, int MODE>
+void layer_part(lq_ctx* ctx, const float2* W, int p, void* out, const void* same,
+                const void* other) {
+  const Geo& g = ctx->geo;
+  const auto* gauge = reinterpret_cast<const __half2*>(ctx->gauge[LQ_F16]);
+  hipLaunchKernelGGL((net_layer_kernel<PS, PO, POUT, P16, MODE>), dim3(grid_for(g.vh, NET_BLK)),
+                     dim3(NET_BLK), 0, ctx->cur, g, p, field_at<POUT>(out, g.nblk),
+                     field_at<PS>(const_cast<void*>(same), g.nblk),
+                     field_at<PO>(const_cast<void*>(other), g.nblk), gauge, W);
+  LQ_HIP(hipGetLastError());
+  double b = spinor_site_bytes(POUT::id);
+  if (MODE != NET_HOPS) b += spinor_site_bytes(PS::id);
+  if (MODE != NET_SELF) b += spinor_site_bytes(PO::id) + 8 * link_site_bytes(LQ_F16);
+  ctx->bytes += (double)g.vh * b;
 }
 
 void ensure_adjoint(Net* n) {
@@ -373,7 +401,7 @@ Net* net_create(lq_ctx* ctx, int L) {
 void net_destroy(Net* n) {
   if (!n) return;
   for (void* p : {(void*)n->w, (void*)n->wadj, (void*)n->m1, (void*)n->m2, (void*)n->grad,
-                  (void*)n->part, n->act, n->gbuf[0], n->gbuf[1]})
+                  (void*)n->part, n->act, n->gbuf[0], n->gbuf[1], n->fbuf[0], n->fbuf[1]})
     if (p) (void)hipFree(p);
   delete n;
 }
@@ -394,6 +422,46 @@ void net_set_weights(Net* n, const double* host) {
   LQ_HIP(hipMemset(n->grad, 0, h.size() * sizeof(double2)));
   n->step = 0;
   n->adj_ok = false;
+}
+
+// Neumann start: W0 = 1, Wp_mu = -(kappa / w_l)(1 - gamma_mu),
+// Wm_mu = -(kappa / w_l)(1 + gamma_mu), w_l = exp(2 pi i (l + 1) / (L + 1)),
+// so that layer l is 1 - (kappa / w_l) H and the net the truncated series
+// sum_{n <= L} (kappa H)^n (prod_l (1 - z / w_l) = 1 + z + ... + z^L).
+// Gamma matrices of the chiral basis used by the hopping term:
+// gamma_mu = [[0, -i sigma], [i sigma, 0]] for mu = 0, 1, 2, [[0, 1], [1, 0]] for mu = 3.
+void net_init_neumann(Net* n, double kappa) {
+  using cd = std::complex<double>;
+  const cd I(0.0, 1.0);
+  cd gam[4][4][4] = {};
+  const cd sig[3][2][2] = {{{0.0, 1.0}, {1.0, 0.0}}, {{0.0, -I}, {I, 0.0}}, {{1.0, 0.0}, {0.0, -1.0}}};
+  for (int mu = 0; mu < 4; ++mu)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const cd blk = mu < 3 ? sig[mu][a][b] : cd(a == b ? 1.0 : 0.0);
+        gam[mu][a][2 + b] = mu < 3 ? -I * blk : blk;
+        gam[mu][2 + a][b] = mu < 3 ? I * blk : blk;
+      }
+  std::vector<double> h((size_t)n->L * NET_W * 2, 0.0);
+  for (int l = 0; l < n->L; ++l) {
+    const cd om = std::polar(1.0, 2.0 * M_PI * (l + 1) / (n->L + 1));
+    const cd c = -kappa / om;
+    for (int s = 0; s < 4; ++s)
+      for (int t = 0; t < 4; ++t) {
+        const double one = s == t ? 1.0 : 0.0;
+        auto put = [&](int k, cd v) {
+          const size_t q = (((size_t)l * NET_K + k) * 16 + s * 4 + t) * 2;
+          h[q] = v.real();
+          h[q + 1] = v.imag();
+        };
+        put(0, one);
+        for (int mu = 0; mu < 4; ++mu) {
+          put(1 + 2 * mu, c * (one - gam[mu][s][t]));
+          put(2 + 2 * mu, c * (one + gam[mu][s][t]));
+        }
+      }
+  }
+  net_set_weights(n, h.data());
 }
 
 void net_get_weights(Net* n, double* host) {
@@ -481,6 +549,38 @@ double loss_grad_one(Net* n, const void* b, const void* x, double weight) {
   return weight * dn / xn;
 }
 
+// y_e = N_e x_e (adjoint: N_e^+ x_e) in the fast precision set used inside
+// the solvers: FP16 links, FP16 activations with per-site scales, FP32
+// input and output.  The first layer sees an even-only input (its even
+// output is W0 x_e alone, its odd output the hops of x_e alone) and only the
+// even output of the last layer is formed.
+void net_apply_even_fast(Net* n, void* y_e, const void* x_e, bool adjoint) {
+  lq_ctx* ctx = n->ctx;
+  const size_t h16 = parity_field_bytes(ctx->geo.nblk, LQ_F16);
+  if (!n->fbuf[0]) {
+    LQ_HIP(hipMalloc(&n->fbuf[0], 2 * h16));
+    LQ_HIP(hipMalloc(&n->fbuf[1], 2 * h16));
+  }
+  if (adjoint) ensure_adjoint(n);
+  const float2* W = adjoint ? n->wadj : n->w;
+  auto wl = [&](int i) { return W + (adjoint ? n->L - 1 - i : i) * NET_W; };
+  char* f[2][2] = {{reinterpret_cast<char*>(n->fbuf[0]), reinterpret_cast<char*>(n->fbuf[0]) + h16},
+                   {reinterpret_cast<char*>(n->fbuf[1]), reinterpret_cast<char*>(n->fbuf[1]) + h16}};
+  if (n->L == 1) {
+    layer_part<P32, P32, P32, NET_SELF>(ctx, wl(0), LQ_EVEN, y_e, x_e, x_e);
+    return;
+  }
+  layer_part<P32, P32, P16, NET_SELF>(ctx, wl(0), LQ_EVEN, f[0][0], x_e, x_e);
+  layer_part<P32, P32, P16, NET_HOPS>(ctx, wl(0), LQ_ODD, f[0][1], x_e, x_e);
+  int cur = 0;
+  for (int i = 1; i < n->L - 1; ++i) {
+    for (int p = 0; p < 2; ++p)
+      layer_part<P16, P16, P16, NET_FULL>(ctx, wl(i), p, f[1 - cur][p], f[cur][p], f[cur][1 - p]);
+    cur = 1 - cur;
+  }
+  layer_part<P16, P16, P32, NET_FULL>(ctx, wl(n->L - 1), LQ_EVEN, y_e, f[cur][0], f[cur][1]);
+}
+
 // Loss mean_i |N_e b_i - x_i|^2 / |x_i|^2 over npairs pairs of FP32 even
 // fields (npairs consecutive fields each); the gradient of this loss
 // replaces the accumulated one.
@@ -565,6 +665,86 @@ void caxpy_64_32(lq_ctx* ctx, void* y64, double cr, double ci, const void* x32) 
 void axpby_f32(lq_ctx* ctx, void* out, double a, const void* x, double b, const void* y) {
   axpby_f32_impl(ctx, out, a, x, b, y);
   ctx->bytes += (double)ctx->geo.vh * 3 * 96;
+}
+
+// ---------------------------------------------------------------- Gram-Schmidt
+// c_i = <V_i, w> = sum conj(V_i) w for the nv FP32 one-parity fields whose
+// device pointers are in V; per-workgroup FP64 partials part[i][block][2].
+constexpr int MDOT_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void multidot_kernel(const float2* const* __restrict__ V,
+                                                       const float2* __restrict__ w, int64_t n,
+                                                       double* __restrict__ part) {
+  __shared__ double sh[2][16];
+  const float2* __restrict__ v = V[blockIdx.y];
+  double t[2] = {0.0, 0.0};
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const float2 a = v[j], b = w[j];
+    t[0] += (double)a.x * b.x + (double)a.y * b.y;
+    t[1] += (double)a.x * b.y - (double)a.y * b.x;
+  }
+  block_sum<2>(t, sh);
+  if (threadIdx.x == 0) {
+    part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 2] = t[0];
+    part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 2 + 1] = t[1];
+  }
+}
+
+__global__ __launch_bounds__(256) void multidot_finalize(const double* __restrict__ part,
+                                                         int nblocks, double* __restrict__ out) {
+  __shared__ double sh[2][16];
+  double t[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    t[0] += part[((int64_t)blockIdx.x * nblocks + b) * 2];
+    t[1] += part[((int64_t)blockIdx.x * nblocks + b) * 2 + 1];
+  }
+  block_sum<2>(t, sh);
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = t[0];
+    out[2 * blockIdx.x + 1] = t[1];
+  }
+}
+
+// w -= sum_i c_i V_i (c: nv complex on the device)
+__global__ __launch_bounds__(256) void multiaxpy_kernel(const float2* const* __restrict__ V,
+                                                        const double2* __restrict__ c, int nv,
+                                                        float2* __restrict__ w, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  float2 acc = w[j];
+  for (int i = 0; i < nv; ++i) {
+    const float2 v = V[i][j];
+    const float cr = (float)c[i].x, ci = (float)c[i].y;
+    acc.x -= cr * v.x - ci * v.y;
+    acc.y -= cr * v.y + ci * v.x;
+  }
+  w[j] = acc;
+}
+
+void multidot_f32(lq_ctx* ctx, const void* vdev, int nv, const void* w, double* part,
+                  double* res_dev, double* res_host) {
+  const int64_t n = ctx->geo.nblk * SB * 12;
+  hipLaunchKernelGGL(multidot_kernel, dim3(MDOT_BLOCKS, nv), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<const float2* const*>(vdev),
+                     reinterpret_cast<const float2*>(w), n, part);
+  hipLaunchKernelGGL(multidot_finalize, dim3(nv), dim3(256), 0, ctx->cur, part, MDOT_BLOCKS,
+                     res_dev);
+  LQ_HIP(hipGetLastError());
+  LQ_HIP(hipMemcpyAsync(res_host, res_dev, sizeof(double) * 2 * nv, hipMemcpyDeviceToHost,
+                        ctx->cur));
+  LQ_HIP(hipStreamSynchronize(ctx->cur));
+  ctx->bytes += (double)ctx->geo.vh * 96.0 * (nv + 1);
+}
+
+void multiaxpy_f32(lq_ctx* ctx, const void* vdev, int nv, const double* c_dev, void* w) {
+  const int64_t n = ctx->geo.nblk * SB * 12;
+  hipLaunchKernelGGL(multiaxpy_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<const float2* const*>(vdev),
+                     reinterpret_cast<const double2*>(c_dev), nv, reinterpret_cast<float2*>(w),
+                     n);
+  LQ_HIP(hipGetLastError());
+  ctx->bytes += (double)ctx->geo.vh * 96.0 * (nv + 2);
 }
 
 }  // namespace lq

@@ -59,6 +59,11 @@ struct Work {
   double graph_k2[3] = {0, 0, 0};
   // learned-preconditioner solvers: FP32 one-parity fields
   std::vector<void*> nv, nz, nx;  // Krylov basis, preconditioned basis, work
+  void* vptr = nullptr;           // device copy of the basis pointers
+  int vptr_n = 0;
+  double* mpart = nullptr;        // Gram-Schmidt partials, results, coefficients
+  double* mres = nullptr;
+  double* mcoef = nullptr;
 };
 
 namespace {
@@ -631,6 +636,17 @@ bool fgmres_net(lq_ctx* ctx, Work* w, Net* net, double target, int maxiter, int 
   for (int i = 0; i < m; ++i) f32_buf(Z, i, f32);
   void* wv = f32_buf(w->nx, 0, f32);
   void* to32 = f32_buf(w->nx, 1, f32);
+  if (w->vptr_n < m + 1) {  // device array of the basis pointers, Gram-Schmidt buffers
+    for (void* q : {w->vptr, (void*)w->mpart, (void*)w->mres, (void*)w->mcoef})
+      if (q) (void)hipFree(q);
+    w->vptr = dalloc(sizeof(void*) * (m + 1));
+    w->mpart = reinterpret_cast<double*>(dalloc(sizeof(double) * 2 * MDOT_BLOCKS_MAX * (m + 1)));
+    w->mres = reinterpret_cast<double*>(dalloc(sizeof(double) * 2 * (m + 1)));
+    w->mcoef = reinterpret_cast<double*>(dalloc(sizeof(double) * 2 * (m + 1)));
+    w->vptr_n = m + 1;
+  }
+  LQ_HIP(hipMemcpyAsync(w->vptr, V.data(), sizeof(void*) * (m + 1), hipMemcpyHostToDevice,
+                        ctx->cur));
   const int L = net_layers(net);
   double best = INFINITY, beta = 0.0;
   int stalls = 0;
@@ -645,17 +661,22 @@ bool fgmres_net(lq_ctx* ctx, Work* w, Net* net, double target, int maxiter, int 
     const double inner_target = std::max(1e-4 * beta, 0.5 * target);
     int k = 0;
     while (k < m && ss.iterations < maxiter) {
-      net_apply_even(net, Z[k], V[k], false);
+      net_apply_even_fast(net, Z[k], V[k], false);
       schur(ctx, wv, Z[k], to32, 0, LQ_F32);
       ss.dslash += 2 + 2 * L;
       ss.iterations += 1;
       for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, applied twice
-        std::vector<cplx> c(k + 1);
-        for (int i = 0; i <= k; ++i) c[i] = cdot32(ctx, V[i], wv);
+        std::vector<double> c(2 * (k + 1));
+        multidot_f32(ctx, w->vptr, k + 1, wv, w->mpart, w->mres, c.data());
+        std::vector<double> nc(2 * (k + 1));
         for (int i = 0; i <= k; ++i) {
-          caxpy_f32(ctx, wv, -c[i].real(), -c[i].imag(), V[i]);
-          H[(size_t)i * m + k] += c[i];
+          H[(size_t)i * m + k] += cplx(c[2 * i], c[2 * i + 1]);
+          nc[2 * i] = c[2 * i];
+          nc[2 * i + 1] = c[2 * i + 1];
         }
+        LQ_HIP(hipMemcpyAsync(w->mcoef, nc.data(), sizeof(double) * nc.size(),
+                              hipMemcpyHostToDevice, ctx->cur));
+        multiaxpy_f32(ctx, w->vptr, k + 1, w->mcoef, wv);
       }
       const double hn = std::sqrt(nrm32(ctx, wv));
       if (!std::isfinite(hn)) {
@@ -713,8 +734,8 @@ bool fcg_net(lq_ctx* ctx, Work* w, Net* net, double target, int maxiter, SolveSt
   double best = INFINITY, beta = 0.0;
   int stalls = 0;
   auto precond = [&](void* out, const void* in) {  // out = N_e N_e^+ in
-    net_apply_even(net, u, in, true);
-    net_apply_even(net, out, u, false);
+    net_apply_even_fast(net, u, in, true);
+    net_apply_even_fast(net, out, u, false);
     ss.dslash += 4 * L;
   };
   for (;;) {
@@ -841,6 +862,8 @@ void free_work(lq_ctx* ctx) {
   if (w->bst_host) (void)hipHostFree(w->bst_host);
   for (auto* v : {&w->nv, &w->nz, &w->nx})
     for (void* q : *v) (void)hipFree(q);
+  for (void* q : {w->vptr, (void*)w->mpart, (void*)w->mres, (void*)w->mcoef})
+    if (q) (void)hipFree(q);
   delete w;
   ctx->work = nullptr;
 }
@@ -1117,7 +1140,7 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
   LQ_CHECK(!net_solver || net, LQ_EINVAL,
            "learned-preconditioner solvers take a net (lq_solve_net)");
   LQ_CHECK(!net || net_ctx(net) == ctx, LQ_EINVAL, "the net belongs to another context");
-  const int restart = p.restart > 0 ? p.restart : 16;
+  const int restart = p.restart > 0 ? p.restart : 32;
   LQ_CHECK(restart <= 128, LQ_EINVAL, "restart length above 128");
   const int maxiter = p.maxiter > 0 ? p.maxiter : 20000;
   const double delta = inner == LQ_F64 ? 0.0 : (p.delta > 0.0 ? p.delta : 0.1);

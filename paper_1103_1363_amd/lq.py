@@ -98,6 +98,7 @@ def lib():
         L.lq_net_destroy.restype = None
         L.lq_net_set_weights.argtypes = [vp, dp]
         L.lq_net_get_weights.argtypes = [vp, dp]
+        L.lq_net_init_neumann.argtypes = [vp, ct.c_double]
         L.lq_net_apply.argtypes = [vp, vp, vp, ip]
         L.lq_net_loss_grad.argtypes = [vp, vp, vp, ip, dp, dp]
         L.lq_net_adam_step.argtypes = [vp, ct.c_double, ct.c_double, ct.c_double, ct.c_double]
@@ -107,7 +108,7 @@ def lib():
         for name in ("lq_upload_gauge", "lq_set_clover", "lq_spinor_to_device",
                      "lq_spinor_to_host", "lq_dslash", "lq_clover_apply", "lq_schur",
                      "lq_norm2", "lq_dot", "lq_solve", "lq_solve_device", "lq_net_create",
-                     "lq_net_set_weights", "lq_net_get_weights", "lq_net_apply",
+                     "lq_net_set_weights", "lq_net_get_weights", "lq_net_init_neumann", "lq_net_apply",
                      "lq_net_loss_grad", "lq_net_adam_step", "lq_net_train", "lq_solve_net"):
             getattr(L, name).restype = ip
         _lib = L
@@ -307,14 +308,18 @@ class Net:
         assert w.shape == (self.nlayers, NET_K, 4, 4)
         self.lat._check(self._L.lq_net_set_weights(self._h, _dptr(w.view(np.float64))))
 
+    def init_neumann(self, kappa):
+        self.lat._check(self._L.lq_net_init_neumann(self._h, float(kappa)))
+
     def get_weights(self):
         w = np.zeros((self.nlayers, NET_K, 4, 4), dtype=np.complex128)
         self.lat._check(self._L.lq_net_get_weights(self._h, _dptr(w.view(np.float64))))
         return w
 
-    def apply(self, out, inp, adjoint=False):
+    def apply(self, out, inp, adjoint=False, fp16=False):
+        mode = (1 if adjoint else 0) | (2 if fp16 else 0)
         self.lat._check(self._L.lq_net_apply(self._h, ct.c_void_p(out.data_ptr()),
-                                             ct.c_void_p(inp.data_ptr()), int(bool(adjoint))))
+                                             ct.c_void_p(inp.data_ptr()), mode))
 
     def loss_grad(self, dev_b, dev_x, npairs):
         loss = np.zeros(1)
