@@ -163,6 +163,66 @@ def batched_point_sources(lq, lat, torch, dims):
     return out
 
 
+def uneven_batch(lq, torch):
+    """Eight independent solves on lattices from 8^4 to 24^3x48 (kappa in
+    [0.130, 0.136], csw = 1, smooth links, Gaussian sources) as one uneven
+    batch, against the same eight solved one after another."""
+    from gen import fields
+    spec = fields.uneven_batch()
+    t0 = time.perf_counter()
+    lats, db, dx = [], [], []
+    for dims, kappa, gs, ss in spec:
+        lat = lq.Lattice(dims)
+        lat.upload_gauge(fields.gauge_field(dims, "smooth", gs))
+        lat.set_clover(kappa, CSW)
+        lats.append(lat)
+        db.append(lat.to_device(fields.gaussian_spinor(dims, ss), lq.FULL, lq.F64))
+        dx.append(lat.new_field(lq.FULL, lq.F64))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    kap = [k for _, k, _, _ in spec]
+    csw = [CSW] * len(spec)
+    ens = lq.Ensemble(lats)
+    out = {"members": ["x".join(map(str, d)) for d, *_ in spec],
+           "kappa": [round(k, 5) for k in kap], "even_sites": sum(l.volume // 2 for l in lats),
+           "inputs_s": round(t_gen, 1)}
+    for name, prec in (("batch_mixed_f16", lq.F16), ("batch_plain_f64", lq.F64)):
+        tune = ens.tune(prec)
+        ens.solve_device(dx, db, kap, csw, TOL, inner_prec=prec)  # warm-up: graphs, clover
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps, er = ens.solve_device(dx, db, kap, csw, TOL, inner_prec=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out[name] = {"ms": round(ms, 2), "tile_sites": tune["tile_sites"],
+                     "tune_ms_per_iteration": [round(t, 4) for t in tune["tune_ms"]],
+                     "graph_captures": er["graph_captures"], "replays": er["replays"],
+                     "iterations": [r.iterations for r in reps],
+                     "reliable_updates": [r.reliable_updates for r in reps],
+                     "fallbacks": sum(r.fallback for r in reps),
+                     "max_true_residual": max(r.true_residual for r in reps),
+                     "GB/s": round(er["bytes"] / (ms * 1e-3) / 1e9, 1)}
+    for name, prec in (("sequential_plain_f64", lq.F64), ("sequential_mixed_f16", lq.F16)):
+        for j, lat in enumerate(lats):  # warm-up: work fields and graphs of every lattice
+            lat.solve_device(dx[j], db[j], kap[j], CSW, TOL, inner_prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = [lat.solve_device(dx[j], db[j], kap[j], CSW, TOL, inner_prec=prec)[0]
+                for j, lat in enumerate(lats)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out[name] = {"ms": round(ms, 2), "iterations": [r.iterations for r in reps],
+                     "max_true_residual": max(r.true_residual for r in reps)}
+    b16 = out["batch_mixed_f16"]["ms"]
+    out["speedup_vs_sequential_plain_f64"] = round(out["sequential_plain_f64"]["ms"] / b16, 3)
+    out["speedup_vs_sequential_mixed_f16"] = round(out["sequential_mixed_f16"]["ms"] / b16, 3)
+    out["batch_plain_vs_sequential_plain"] = round(
+        out["sequential_plain_f64"]["ms"] / out["batch_plain_f64"]["ms"], 3)
+    ens.close()
+    del db, dx
+    return out
+
+
 def learned_preconditioner(lq, lat, torch, db_bench, npairs, epochs):
     """Train the net on pairs from a 16^3x32 field (its own gauge field and
     sources), then solve the benchmark system (its source on the device,
@@ -292,6 +352,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-net", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--net-pairs", type=int, default=400)
     ap.add_argument("--net-epochs", type=int, default=8)
     a = ap.parse_args()
@@ -421,6 +482,9 @@ def main():
     if not a.no_batched:
         log("12 point sources: batched solve, and one source alone")
         result["batched_12rhs"] = batched_point_sources(lq, lat, torch, dims)
+    if not a.no_uneven:
+        log("uneven batch of eight lattices: one batch, and one after another")
+        result["uneven_batch"] = uneven_batch(lq, torch)
     if not a.no_net:
         log(f"learned preconditioner: {a.net_pairs} training pairs, {a.net_epochs} epochs")
         result["learned_preconditioner"] = learned_preconditioner(lq, lat, torch, db, a.net_pairs,

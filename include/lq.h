@@ -268,6 +268,65 @@ lq_status lq_solve_net(lq_ctx* ctx, lq_net* net, double* host_x, const double* h
                        double kappa, double csw, double tol, const lq_solver_params* params,
                        lq_solve_report* report);
 
+/* ------------------------------------------------------------------------
+ * Uneven batch.  Independent solves of M x = b (the even-odd CG of lq_solve
+ * with reliable updates, section 5) on lattices of different extents and
+ * hopping parameters, one right-hand side each, advanced together: every
+ * stage of an iteration is one kernel launch over the site tiles of all
+ * members still iterating, the members' scalars stay on the device, the
+ * FP64 reliable updates are batched launches inside the iteration, and
+ * check_every iterations are replayed from a captured graph between host
+ * polls.  Finished members drop out of the tile list.  Members that break
+ * down or stagnate are finished by the FP64 CG of their own context
+ * (report fallback = 1).
+ *
+ * Members are distinct contexts of one device with a gauge field; they must
+ * outlive the batch and not be used by other calls while it solves.  The
+ * batch launches on a stream of its own after synchronising each member's
+ * stream; the call returns when every member is finished.
+ * ------------------------------------------------------------------------ */
+typedef struct lq_ensemble lq_ensemble;
+
+typedef struct {
+  int tile_sites;       /* sites per workgroup of the iteration kernels (64, 128, 256) */
+  int tile_from_cache;  /* 1: the tile was read from the cache file */
+  double tune_ms[3];    /* measured time of one iteration's operator and vector kernels
+                           for 64, 128 and 256 sites per workgroup (0: not measured) */
+  int graph_captures;   /* graphs captured during the solve */
+  int replays;          /* graph replays, each followed by one host poll */
+  int iterations;       /* inner iterations of the longest member */
+  double seconds;       /* wall time of the whole solve */
+  double bytes;         /* algorithmic bytes of all members' kernels */
+} lq_ensemble_report;
+
+/* A batch of n (1..64) member contexts.  On failure *out is NULL and
+ * lq_ensemble_last_error(NULL) holds the message. */
+lq_status lq_ensemble_create(lq_ctx* const* members, int n, lq_ensemble** out);
+void lq_ensemble_destroy(lq_ensemble* e);
+const char* lq_ensemble_last_error(const lq_ensemble* e);
+
+/* Choose the tile shape for inner precision inner_prec (LQ_F64, LQ_F32 or
+ * LQ_F16): from the batch's memory, else from the JSON file cache_path (may
+ * be NULL), else by timing every candidate on the members (which need their
+ * clover term, lq_set_clover); a measured choice is written to cache_path.
+ * The cache key is the GPU architecture, the precision, nrhs = 1 and the
+ * members' extents in order.  rep (may be NULL) receives the tile fields. */
+lq_status lq_ensemble_tune(lq_ensemble* e, int inner_prec, const char* cache_path,
+                           lq_ensemble_report* rep);
+
+/* Solve member j's system with (kappa[j], csw[j]) on full-lattice FP64
+ * device fields dev_b[j] -> dev_x[j] (as lq_solve_device; caller-owned,
+ * distinct), to the FP64 true residual tol for every member.  params: solver
+ * LQ_CGNR, inner_prec, maxiter, delta, check_every, use_graph as for
+ * lq_solve (batched, profile, fault_inject must be 0).  Tunes on first use
+ * of a precision (lq_ensemble_tune without a file).  reports: n entries (may
+ * be NULL; seconds = whole batch); rep may be NULL.  Returns LQ_ENOCONV when
+ * a member did not converge, with the reports filled. */
+lq_status lq_ensemble_solve(lq_ensemble* e, void* const* dev_x, const void* const* dev_b,
+                            const double* kappa, const double* csw, double tol,
+                            const lq_solver_params* params, lq_solve_report* reports,
+                            lq_ensemble_report* rep);
+
 #ifdef __cplusplus
 }
 #endif

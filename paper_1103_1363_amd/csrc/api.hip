@@ -96,6 +96,11 @@ void ensure_red(lq_ctx* ctx) {
 }  // namespace lq
 
 // the public net handle: the library net and the context it belongs to
+struct lq_ensemble {
+  lq::Ensemble* impl;
+  std::string err;
+};
+
 struct lq_net {
   lq_ctx* ctx;
   lq::Net* impl;
@@ -446,6 +451,78 @@ lq_status lq_solve_net(lq_ctx* ctx, lq_net* net, double* host_x, const double* h
     LQ_CHECK(tol > 0.0 && tol < 1.0, LQ_EINVAL, "tol must lie in (0, 1)");
     lq::solve(ctx, host_x, host_b, nullptr, nullptr, nrhs, kappa, csw, tol, params, report,
               net->impl);
+  });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ uneven batch
+namespace {
+thread_local std::string g_ens_create_error;
+
+template <class F>
+lq_status guarded_e(lq_ensemble* e, F&& f) {
+  if (!e) return LQ_EINVAL;
+  try {
+    f();
+    return LQ_OK;
+  } catch (const lq::Error& x) {
+    e->err = x.what();
+    return x.code;
+  } catch (const std::bad_alloc&) {
+    e->err = "host allocation failed";
+    return LQ_ENOMEM;
+  } catch (const std::exception& x) {
+    e->err = x.what();
+    return LQ_EINVAL;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+lq_status lq_ensemble_create(lq_ctx* const* members, int n, lq_ensemble** out) {
+  if (!out) {
+    g_ens_create_error = "null pointer";
+    return LQ_EINVAL;
+  }
+  *out = nullptr;
+  try {
+    lq::Ensemble* impl = lq::ensemble_create(members, n);
+    *out = new lq_ensemble{impl, std::string()};
+    return LQ_OK;
+  } catch (const lq::Error& x) {
+    g_ens_create_error = x.what();
+    return x.code;
+  } catch (const std::exception& x) {
+    g_ens_create_error = x.what();
+    return LQ_ENOMEM;
+  }
+}
+
+void lq_ensemble_destroy(lq_ensemble* e) {
+  if (!e) return;
+  lq::ensemble_destroy(e->impl);
+  delete e;
+}
+
+const char* lq_ensemble_last_error(const lq_ensemble* e) {
+  return e ? e->err.c_str() : g_ens_create_error.c_str();
+}
+
+lq_status lq_ensemble_tune(lq_ensemble* e, int inner_prec, const char* cache_path,
+                           lq_ensemble_report* rep) {
+  return guarded_e(e, [&] { lq::ensemble_tune(e->impl, inner_prec, cache_path, rep); });
+}
+
+lq_status lq_ensemble_solve(lq_ensemble* e, void* const* dev_x, const void* const* dev_b,
+                            const double* kappa, const double* csw, double tol,
+                            const lq_solver_params* params, lq_solve_report* reports,
+                            lq_ensemble_report* rep) {
+  return guarded_e(e, [&] {
+    LQ_CHECK(dev_x && dev_b && kappa && csw, LQ_EINVAL, "null pointer");
+    LQ_CHECK(tol > 0.0 && tol < 1.0, LQ_EINVAL, "tol must lie in (0, 1)");
+    lq::ensemble_solve(e->impl, dev_x, dev_b, kappa, csw, tol, params, reports, rep);
   });
 }
 

@@ -204,7 +204,7 @@ inline size_t parity_field_bytes(int64_t nblk, int prec) {
 }
 
 template <class P>
-inline Field<P> field_at(void* base, int64_t nblk) {
+__host__ __device__ inline Field<P> field_at(void* base, int64_t nblk) {
   Field<P> f;
   f.d = reinterpret_cast<typename P::S*>(base);
   f.norm = P::has_norm ? reinterpret_cast<float*>(reinterpret_cast<char*>(base) +
@@ -269,6 +269,7 @@ struct Clover {
 struct Work;    // solver work space (solver.hip)
 struct MRWork;  // batched multi-RHS solver work space (mrhs.hip)
 struct Net;     // learned preconditioner (net.hip)
+struct Ensemble;  // uneven batch of independent solves (ensemble.hip)
 
 }  // namespace lq
 
@@ -333,6 +334,25 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
            int nrhs, double kappa, double csw, double tol, const lq_solver_params* params,
            lq_solve_report* report, Net* net = nullptr);
 void free_work(lq_ctx* ctx);
+// Pieces of one solve, for the uneven batch (ensemble.hip): the work fields
+// of inner precision `inner` (allocated on first use); right-hand side setup
+// from a full-lattice FP64 device field (bhat, x = 0; returns |b|^2);
+// a single-lattice continuation from the current x to the Schur target
+// (mixed CG with the FP64 fallback); odd-site reconstruction with the full
+// residual |b - M x|^2 and the Schur residual.
+struct SolveFields {
+  void *x, *bhat, *r64, *rn64, *to;  // FP64: x (full lattice, even half first), even, odd
+  void *p, *q, *t, *xl, *r, *rt;     // inner iteration (t odd, the rest even)
+};
+struct SolveTally {
+  int iterations = 0, reliable = 0, fallback = 0, dslash = 0;
+};
+SolveFields solve_fields(lq_ctx* ctx, int inner);
+double solve_begin(lq_ctx* ctx, void* dev_x, const void* dev_b, double* bhat_norm);
+bool solve_more(lq_ctx* ctx, int inner, double target, int maxiter, int check_every,
+                bool use_graph, SolveTally& t);
+double solve_end(lq_ctx* ctx, double* schur2, SolveTally& t);
+void iteration_bytes(int inner, double out[LQ_NK]);  // per site, per kernel of one iteration
 
 // mrhs.hip: multi-RHS interleaved FP16 fields (lq_prec LQ_F16X) and the
 // matrix-core hopping term; batched CG helpers
@@ -383,6 +403,14 @@ void mrhs_slot_from_single(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void*
                            int r, double a, double b);
 void mrhs_single_from_slot(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single64,
                            int r, double a, double b);
+
+// ensemble.hip: uneven batch (member contexts must outlive the batch)
+Ensemble* ensemble_create(lq_ctx* const* members, int n);
+void ensemble_destroy(Ensemble* e);
+void ensemble_tune(Ensemble* e, int inner, const char* cache_path, lq_ensemble_report* rep);
+void ensemble_solve(Ensemble* e, void* const* dev_x, const void* const* dev_b, const double* kappa,
+                    const double* csw, double tol, const lq_solver_params* params,
+                    lq_solve_report* reports, lq_ensemble_report* rep);
 
 inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
 

@@ -70,6 +70,16 @@ __device__ __forceinline__ void block_partial(double v[N], double* part) {
     for (int k = 0; k < N; ++k) part[(int64_t)blockIdx.x * N + k] = v[k];
 }
 
+// As block_partial, at partial row idx instead of the workgroup index.
+template <int N>
+__device__ __forceinline__ void block_partial_at(double v[N], double* part, int64_t idx) {
+  __shared__ double sh[N][16];
+  block_sum<N>(v, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) part[idx * N + k] = v[k];
+}
+
 // One workgroup: totals of nparts partials, then fin(totals) in thread 0.
 template <int N, class Fin>
 __global__ __launch_bounds__(256) void finalize_kernel(RedBuf rb, int nparts, Fin fin) {

@@ -814,6 +814,20 @@ bool run_inner(lq_ctx* ctx, Work* w, int solver, int inner, double target, doubl
   }
 }
 
+// |b|^2 of the full right-hand side w->b; bhat = b_e + kappa H_eo A_oo^-1 b_o
+// (its norm in bhat_norm); x = 0.
+double prepare_rhs(lq_ctx* ctx, Work* w, double& bhat_norm) {
+  const int64_t nb = ctx->geo.nblk;
+  const double b2 = nrm2(ctx, w->b) + nrm2(ctx, odd_half(w->b, nb));
+  clover_apply(ctx, w->to, odd_half(w->b, nb), LQ_ODD, 1, LQ_F64);
+  dslash(ctx, w->te, w->to, LQ_EVEN, 0, LQ_F64);
+  axpby64(ctx, w->bhat, 1.0, w->b, ctx->clov.kappa, w->te);
+  bhat_norm = std::sqrt(nrm2(ctx, w->bhat));
+  zero<P64>(ctx, w->x);
+  zero<P64>(ctx, odd_half(w->x, nb));
+  return b2;
+}
+
 // x_o = A_oo^-1 (b_o + kappa H_oe x_e); returns |b - M x|^2 over both parities.
 double reconstruct_and_residual(lq_ctx* ctx, Work* w, SolveStats& ss) {
   const int64_t nb = ctx->geo.nblk;
@@ -1201,15 +1215,9 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
       w->b = const_cast<char*>(reinterpret_cast<const char*>(dev_b)) + rhs * fb;
       w->x = reinterpret_cast<char*>(dev_x) + rhs * fb;
     }
-    const double b2 = nrm2(ctx, w->b) + nrm2(ctx, odd_half(w->b, nb));
-    // bhat = b_e + kappa H_eo A_oo^-1 b_o
-    clover_apply(ctx, w->to, odd_half(w->b, nb), LQ_ODD, 1, LQ_F64);
-    dslash(ctx, w->te, w->to, LQ_EVEN, 0, LQ_F64);
-    axpby64(ctx, w->bhat, 1.0, w->b, kappa, w->te);
+    double bhat_norm = 0.0;
+    const double b2 = prepare_rhs(ctx, w, bhat_norm);
     ss.dslash += 1;
-    const double bhat_norm = std::sqrt(nrm2(ctx, w->bhat));
-    zero<P64>(ctx, w->x);
-    zero<P64>(ctx, odd_half(w->x, nb));
     double res2 = 0.0;
     bool ok = false;
     double frac = 0.5;
@@ -1279,6 +1287,75 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
     }
   }
   if (worst != LQ_OK) throw Error(worst, msg);
+}
+
+
+// ------------------------------------------------------------ pieces of one solve
+// Used by the uneven batch (ensemble.hip), which runs the inner iterations of
+// several lattices together and these steps per lattice.
+SolveFields solve_fields(lq_ctx* ctx, int inner) {
+  Work* w = work(ctx, inner);
+  work(ctx, LQ_F64);
+  SolveFields f;
+  f.x = w->x;
+  f.bhat = w->bhat;
+  f.r64 = w->r64;
+  f.rn64 = w->rn64;
+  f.to = w->to;
+  f.p = w->p[inner];
+  f.q = w->q[inner];
+  f.t = w->t[inner];
+  f.xl = w->xl[inner];
+  f.r = w->r[inner];
+  f.rt = w->rt[inner];
+  return f;
+}
+
+double solve_begin(lq_ctx* ctx, void* dev_x, const void* dev_b, double* bhat_norm) {
+  Work* w = work(ctx, LQ_F64);
+  w->b = const_cast<void*>(dev_b);
+  w->x = dev_x;
+  double bn = 0.0;
+  const double b2 = prepare_rhs(ctx, w, bn);
+  *bhat_norm = bn;
+  return b2;
+}
+
+bool solve_more(lq_ctx* ctx, int inner, double target, int maxiter, int check_every,
+                bool use_graph, SolveTally& t) {
+  Work* w = work(ctx, inner);
+  SolveStats ss;
+  bool fb = false;
+  const double delta = inner == LQ_F64 ? 0.0 : 0.1;
+  bool conv = run_cg(ctx, w, inner, target, delta, std::max(1, maxiter), check_every, use_graph,
+                     0, ss, fb, nullptr);
+  t.iterations += ss.iterations;
+  t.reliable += ss.reliable;
+  t.dslash += ss.dslash + 4 * ss.iterations;
+  if (fb) {
+    t.fallback = 1;
+    work(ctx, LQ_F64);
+    SolveStats f;
+    conv = run_cg(ctx, w, LQ_F64, target, 0.0, std::max(1, maxiter - ss.iterations), check_every,
+                  use_graph, 0, f, fb, nullptr);
+    t.iterations += f.iterations;
+    t.reliable += f.reliable;
+    t.dslash += f.dslash + 4 * f.iterations;
+  }
+  return conv;
+}
+
+double solve_end(lq_ctx* ctx, double* schur2, SolveTally& t) {
+  Work* w = ctx->work;
+  SolveStats ss;
+  const double res2 = reconstruct_and_residual(ctx, w, ss);
+  *schur2 = schur_residual(ctx, w, ss);
+  t.dslash += ss.dslash;
+  return res2;
+}
+
+void iteration_bytes(int inner, double out[LQ_NK]) {
+  iteration_site_bytes(inner, vec_prec(inner), out);
 }
 
 }  // namespace lq

@@ -60,6 +60,84 @@ __device__ __forceinline__ double site_norm2(const C<R> v[12]) {
   return a;
 }
 
+// ---------------------------------------------------------------- site bodies
+// The per-site work of each stage, shared by the single-lattice kernels below
+// and by the uneven-batch kernels (ensemble.hip), which only differ in how a
+// workgroup finds its lattice and its sites.
+
+// t = A_oo^-1 H_oe in (DAG: A_oo^-1 H^+_oe in) at odd site s.
+template <class PO, bool DAG>
+__device__ __forceinline__ void k1_site(const Geo& g, int64_t s, const Field<PO>& t,
+                                        const Field<PO>& in,
+                                        const typename PO::S* __restrict__ gauge,
+                                        const typename PO::S* __restrict__ ainv) {
+  C<typename PO::R> acc[12], y[12];
+  hop_site<DAG>(g, in, gauge, 1, s, acc);
+  clover_mul<PO>(ainv, s, acc, y);
+  store_spinor<PO>(t, s, y);
+}
+
+// y = A_ee in - k2 H_eo t (DAG: H^+_eo) at even site s: the Schur operator
+// (or its adjoint) once t holds the K1 result; inv receives in(s).
+template <class PO, bool DAG>
+__device__ __forceinline__ void schur_site(const Geo& g, int64_t s, const Field<PO>& in,
+                                           const Field<PO>& t,
+                                           const typename PO::S* __restrict__ gauge,
+                                           const typename PO::S* __restrict__ aee,
+                                           typename PO::R k2, C<typename PO::R> inv[12],
+                                           C<typename PO::R> y[12]) {
+  C<typename PO::R> acc[12];
+  hop_site<DAG>(g, t, gauge, 0, s, acc);
+  load_scaled<PO>(in, s, inv);
+  clover_mul<PO>(aee, s, inv, y);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) y[c] = y[c] - k2 * acc[c];
+}
+
+// x += alpha p, r -= alpha y, rt -= alpha qv at even site s;
+// v = (|r_new|^2, |rt_new|^2) of the site.
+template <class PO, class PV>
+__device__ __forceinline__ void k4_update_site(int64_t s, typename PO::R alpha,
+                                               const Field<PO>& p, const Field<PV>& x,
+                                               const Field<PV>& r, const Field<PV>& rt,
+                                               const C<typename PO::R> y[12],
+                                               const C<typename PO::R> qv[12], double v[2]) {
+  using R = typename PO::R;
+  static_assert(sizeof(R) == sizeof(typename PV::R), "operator and vector arithmetic differ");
+  C<R> a[12], b[12];
+  load_scaled<PV>(x, s, a);
+  load_scaled<PO>(p, s, b);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) a[c] = a[c] + alpha * b[c];
+  store_spinor<PV>(x, s, a);
+  load_scaled<PV>(r, s, a);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) a[c] = a[c] - alpha * y[c];
+  store_spinor<PV>(r, s, a);
+  v[0] = site_norm2(a);
+  load_scaled<PV>(rt, s, a);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) a[c] = a[c] - alpha * qv[c];
+  store_spinor<PV>(rt, s, a);
+  v[1] = site_norm2(a);
+}
+
+// p = r + beta p at site s (beta == 0: p = r without reading p).
+template <class PO, class PV>
+__device__ __forceinline__ void k5_site(int64_t s, typename PO::R beta, const Field<PO>& p,
+                                        const Field<PV>& r) {
+  using R = typename PO::R;
+  C<R> a[12], b[12];
+  load_scaled<PV>(r, s, a);
+  if (beta != (R)0) {
+    load_scaled<PO>(p, s, b);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) a[c] = a[c] + beta * b[c];
+  }
+  store_spinor<PO>(p, s, a);
+}
+
+// ---------------------------------------------------------------- kernels
 template <class PO, bool DAG>
 LQ_HOP_KERNEL(PO) void cg_k1(Geo g, const int* __restrict__ active, Field<PO> t,
                                               Field<PO> in, const typename PO::S* __restrict__ gauge,
@@ -67,10 +145,7 @@ LQ_HOP_KERNEL(PO) void cg_k1(Geo g, const int* __restrict__ active, Field<PO> t,
   if (!*active) return;
   const int64_t s = xcd_block(blockIdx.x, gridDim.x) * SBLK + threadIdx.x;
   if (s >= g.vh) return;
-  C<typename PO::R> acc[12], y[12];
-  hop_site<DAG>(g, in, gauge, 1, s, acc);
-  clover_mul<PO>(ainv, s, acc, y);
-  store_spinor<PO>(t, s, y);
+  k1_site<PO, DAG>(g, s, t, in, gauge, ainv);
 }
 
 struct FinAlpha {
@@ -98,12 +173,8 @@ LQ_HOP_KERNEL(PO) void cg_k2(Geo g, CGState* st, Field<PO> q, Field<PO> t,
   const int64_t s = xcd_block(blockIdx.x, gridDim.x) * SBLK + threadIdx.x;
   double v[1] = {0.0};
   if (s < g.vh) {
-    C<R> acc[12], pv[12], y[12];
-    hop_site<false>(g, t, gauge, 0, s, acc);
-    load_scaled<PO>(p, s, pv);
-    clover_mul<PO>(aee, s, pv, y);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) y[c] = y[c] - k2 * acc[c];
+    C<R> pv[12], y[12];
+    schur_site<PO, false>(g, s, p, t, gauge, aee, k2, pv, y);
     store_spinor<PO>(q, s, y);
     v[0] = site_norm2(y);
   }
@@ -145,37 +216,13 @@ LQ_HOP_KERNEL(PO) void cg_k4(Geo g, CGState* st, Field<PO> t, Field<PO> q,
                                               const typename PO::S* __restrict__ aee,
                                               typename PO::R k2, RedBuf rb) {
   using R = typename PO::R;
-  static_assert(sizeof(R) == sizeof(typename PV::R), "operator and vector arithmetic differ");
   if (!st->active) return;
   const int64_t s = xcd_block(blockIdx.x, gridDim.x) * SBLK + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (s < g.vh) {
-    const R alpha = (R)st->alpha;
-    C<R> acc[12], qv[12], y[12];
-    hop_site<true>(g, t, gauge, 0, s, acc);
-    load_scaled<PO>(q, s, qv);
-    clover_mul<PO>(aee, s, qv, y);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) y[c] = y[c] - k2 * acc[c];  // y = Mhat^+ q
-    C<R> a[12], b[12];
-    // x += alpha p
-    load_scaled<PV>(x, s, a);
-    load_scaled<PO>(p, s, b);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) a[c] = a[c] + alpha * b[c];
-    store_spinor<PV>(x, s, a);
-    // r -= alpha y
-    load_scaled<PV>(r, s, a);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) a[c] = a[c] - alpha * y[c];
-    store_spinor<PV>(r, s, a);
-    v[0] = site_norm2(a);
-    // rt -= alpha q
-    load_scaled<PV>(rt, s, a);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) a[c] = a[c] - alpha * qv[c];
-    store_spinor<PV>(rt, s, a);
-    v[1] = site_norm2(a);
+    C<R> qv[12], y[12];
+    schur_site<PO, true>(g, s, q, t, gauge, aee, k2, qv, y);  // y = Mhat^+ q
+    k4_update_site<PO, PV>(s, (R)st->alpha, p, x, r, rt, y, qv, v);
   }
   block_partial<2>(v, rb.part);
 }
@@ -183,17 +230,10 @@ LQ_HOP_KERNEL(PO) void cg_k4(Geo g, CGState* st, Field<PO> t, Field<PO> q,
 template <class PO, class PV>
 __global__ __launch_bounds__(SBLK) void cg_k5(Geo g, const CGState* __restrict__ st, Field<PO> p,
                                               Field<PV> r) {
-  using R = typename PO::R;
   if (!st->active) return;
   const int64_t s = (int64_t)blockIdx.x * SBLK + threadIdx.x;
   if (s >= g.vh) return;
-  const R beta = (R)st->beta;
-  C<R> a[12], b[12];
-  load_scaled<PV>(r, s, a);
-  load_scaled<PO>(p, s, b);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) b[c] = a[c] + beta * b[c];
-  store_spinor<PO>(p, s, b);
+  k5_site<PO, PV>(s, (typename PO::R)st->beta, p, r);
 }
 
 // out = a * x + b * y (real coefficients), any precisions; out may alias x or y.

@@ -55,6 +55,20 @@ class SolveReport(ct.Structure):
         return d
 
 
+class EnsembleReport(ct.Structure):
+    _fields_ = [("tile_sites", ct.c_int), ("tile_from_cache", ct.c_int),
+                ("tune_ms", ct.c_double * 3), ("graph_captures", ct.c_int),
+                ("replays", ct.c_int), ("iterations", ct.c_int), ("seconds", ct.c_double),
+                ("bytes", ct.c_double)]
+
+    def as_dict(self):
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if hasattr(v, "__len__") else v
+        return d
+
+
 _lib = None
 
 
@@ -105,6 +119,17 @@ def lib():
         L.lq_net_train.argtypes = [vp, vp, vp, ip, ip, ip, ct.c_double, ct.c_uint, dp]
         L.lq_solve_net.argtypes = [vp, vp, dp, dp, ip, ct.c_double, ct.c_double, ct.c_double,
                                    ct.POINTER(SolverParams), ct.POINTER(SolveReport)]
+        L.lq_ensemble_create.argtypes = [ct.POINTER(vp), ip, ct.POINTER(vp)]
+        L.lq_ensemble_destroy.argtypes = [vp]
+        L.lq_ensemble_destroy.restype = None
+        L.lq_ensemble_last_error.argtypes = [vp]
+        L.lq_ensemble_last_error.restype = ct.c_char_p
+        L.lq_ensemble_tune.argtypes = [vp, ip, ct.c_char_p, ct.POINTER(EnsembleReport)]
+        L.lq_ensemble_solve.argtypes = [vp, ct.POINTER(vp), ct.POINTER(vp), dp, dp, ct.c_double,
+                                        ct.POINTER(SolverParams), ct.POINTER(SolveReport),
+                                        ct.POINTER(EnsembleReport)]
+        for name in ("lq_ensemble_create", "lq_ensemble_tune", "lq_ensemble_solve"):
+            getattr(L, name).restype = ip
         for name in ("lq_upload_gauge", "lq_set_clover", "lq_spinor_to_device",
                      "lq_spinor_to_host", "lq_dslash", "lq_clover_apply", "lq_schur",
                      "lq_norm2", "lq_dot", "lq_solve", "lq_solve_device", "lq_net_create",
@@ -358,3 +383,58 @@ class Net:
             self.lat._check(rc)
         return x, reports
 
+
+class Ensemble:
+    """Uneven batch of independent solves on several Lattice objects (see
+    lq_ensemble_* in include/lq.h).  The lattices must outlive the batch."""
+
+    def __init__(self, lattices):
+        self.lats = list(lattices)
+        self._L = lib()
+        arr = (ct.c_void_p * len(self.lats))(*[l._h.value for l in self.lats])
+        h = ct.c_void_p()
+        rc = self._L.lq_ensemble_create(arr, len(self.lats), ct.byref(h))
+        if rc != 0:
+            raise LQError(rc, self._L.lq_ensemble_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.lq_ensemble_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise LQError(rc, self._L.lq_ensemble_last_error(self._h).decode())
+
+    def tune(self, inner_prec=F16, cache_path=None):
+        rep = EnsembleReport()
+        path = cache_path.encode() if cache_path else None
+        self._check(self._L.lq_ensemble_tune(self._h, inner_prec, path, ct.byref(rep)))
+        return rep.as_dict()
+
+    def solve_device(self, dev_x, dev_b, kappas, csws, tol=1e-10, inner_prec=F16, maxiter=0,
+                     delta=0.0, check_every=0, use_graph=0, raise_on_noconv=True):
+        """dev_x[j], dev_b[j]: full-lattice FP64 device fields of lattice j.
+        Returns (member reports, batch report dict)."""
+        n = len(self.lats)
+        assert len(dev_x) == n and len(dev_b) == n and len(kappas) == n and len(csws) == n
+        xs = (ct.c_void_p * n)(*[t.data_ptr() for t in dev_x])
+        bs = (ct.c_void_p * n)(*[t.data_ptr() for t in dev_b])
+        ka = np.ascontiguousarray(kappas, dtype=np.float64)
+        cs = np.ascontiguousarray(csws, dtype=np.float64)
+        p = SolverParams(CGNR, inner_prec, maxiter, delta, 0, check_every, use_graph, 0, 0, 0)
+        reps = (SolveReport * n)()
+        er = EnsembleReport()
+        rc = self._L.lq_ensemble_solve(self._h, xs, bs, _dptr(ka), _dptr(cs), float(tol),
+                                       ct.byref(p), reps, ct.byref(er))
+        reports = [Report(**r.as_dict()) for r in reps]
+        if rc != 0 and (rc != -4 or raise_on_noconv):
+            self._check(rc)
+        return reports, er.as_dict()

@@ -28,3 +28,23 @@ def case(dims, kind="smooth", seed=0):
 
 def say(msg):
     print(msg, flush=True)
+
+
+def residual_at(u, kappa, csw, x, b, site, antiperiodic_t=True):
+    """(b - M x)(site) from the oracle, at one site of a lattice too large for
+    the oracle's whole-lattice operator.  The clover term at a site depends
+    only on links within one step of it, so it is taken from the oracle's
+    clover matrix of the periodic 4^4 window of links starting one step below
+    the site (every leaf at window index 1 stays inside the window); the
+    hopping term is the oracle's single-site hop_at."""
+    from oracle import clover as oclover
+    from oracle import dirac
+    lt, lz, ly, lx = u.shape[:4]
+    ext = (lx, ly, lz, lt)
+    idx = [[(site[d] - 1 + k) % ext[d] for k in range(4)] for d in range(4)]
+    win = u[np.ix_(idx[3], idx[2], idx[1], idx[0])]
+    a = oclover.clover_matrix(win, kappa, csw)[1, 1, 1, 1]
+    xs = x[site[3], site[2], site[1], site[0]]
+    mx = oclover.apply_site_matrix(a, xs) - kappa * dirac.hop_at(u, x, site,
+                                                                  antiperiodic_t=antiperiodic_t)
+    return b[site[3], site[2], site[1], site[0]] - mx
