@@ -178,14 +178,22 @@ __device__ __forceinline__ void member_total(const double* __restrict__ part, in
   block_sum<N>(t, sh);
 }
 
+// Members due an update stage, one bit per table slot: cleared by
+// ens_fin_alpha, set by ens_fin_beta when a member's iteration stops, and
+// cleared again by ens_fin_res for members that finished.  The update-stage
+// kernels read this one word instead of every member's state.
+using Mask = unsigned long long;
+
 // One workgroup per member: alpha = |r|^2 / |Mhat p|^2.  Also ends the
-// update stage of the previous iteration (clears ru).
+// update stage of the previous iteration (clears ru and the mask).
 __global__ __launch_bounds__(256) void ens_fin_alpha(const EMember* __restrict__ m,
-                                                     const double* __restrict__ part) {
+                                                     const double* __restrict__ part,
+                                                     Mask* __restrict__ due) {
   const EMember& M = m[blockIdx.x];
   double t[1];
   member_total<1>(part, M.t0, M.nt, t);
   if (threadIdx.x != 0) return;
+  if (blockIdx.x == 0) *due = 0;
   EState* st = M.st;
   st->ru = 0;
   const int was = st->cg.active;
@@ -197,7 +205,8 @@ __global__ __launch_bounds__(256) void ens_fin_alpha(const EMember* __restrict__
 // breakdown schedules the update stage, as does the iteration-level
 // stagnation test of the mixed-precision iteration.
 __global__ __launch_bounds__(256) void ens_fin_beta(const EMember* __restrict__ m,
-                                                    const double* __restrict__ part) {
+                                                    const double* __restrict__ part,
+                                                    Mask* __restrict__ due) {
   const EMember& M = m[blockIdx.x];
   double t[2];
   member_total<2>(part, M.t0, M.nt, t);
@@ -215,46 +224,41 @@ __global__ __launch_bounds__(256) void ens_fin_beta(const EMember* __restrict__ 
       c.reason = R_RELIABLE;
       st->stalled = 1;
       st->ru = 1;
+      atomicOr(due, Mask(1) << blockIdx.x);
     }
   } else if (c.reason == R_NAN) {
     st->done = E_FALLBACK;
   } else {
     st->ru = 1;
+    atomicOr(due, Mask(1) << blockIdx.x);
   }
 }
 
-// Walks the update-stage tiles of the members that pass `pred`; the tiles
-// of other members are skipped in one step per member.
-template <class Pred, class Body>
-__device__ __forceinline__ void update_tiles(const EMember* __restrict__ m, int nm, Pred pred,
-                                             Body body) {
+// Walks the update-stage tiles of the members whose bit is set in `due`, as
+// one list of their tiles dealt round-robin to the workgroups; `body` gets
+// the member, the site and the member's partial-sum row.  A launch with no
+// member due returns after one load.
+template <class Body>
+__device__ __forceinline__ void update_tiles(const EMember* __restrict__ m, int nm,
+                                             const Mask* __restrict__ due, Body body) {
+  const Mask mk = *due;
+  if (!mk) return;
   const int64_t G = gridDim.x;
-  const int64_t total = m[nm - 1].r0 + m[nm - 1].nr;
-  int j = 0;
-  for (int64_t b = blockIdx.x; b < total;) {
-    while (b >= m[j].r0 + m[j].nr) ++j;
+  int64_t v0 = 0;  // list index of the current member's first tile
+  for (int j = 0; j < nm; ++j) {
+    if (!((mk >> j) & 1)) continue;
     const EMember& M = m[j];
-    if (!pred(*M.st)) {
-      const int64_t end = M.r0 + M.nr;
-      b += (end - b + G - 1) / G * G;
-      continue;
-    }
-    body(M, (b - M.r0) * UTB + threadIdx.x, b);
-    b += G;
+    int64_t v = v0 + (((int64_t)blockIdx.x - v0) % G + G) % G;
+    for (; v < v0 + M.nr; v += G) body(M, (v - v0) * UTB + threadIdx.x, M.r0 + (v - v0));
+    v0 += M.nr;
   }
 }
-
-struct DueAll {  // update stage scheduled
-  __device__ bool operator()(const EState& s) const { return s.ru == 1; }
-};
-struct DueGo {  // ... and the member goes on iterating
-  __device__ bool operator()(const EState& s) const { return s.ru == 1 && s.done == E_RUN; }
-};
 
 // x += xl (FP64), xl = 0
 template <class PV>
-__global__ __launch_bounds__(UTB) void ens_fold(const EMember* __restrict__ m, int nm) {
-  update_tiles(m, nm, DueAll{}, [](const EMember& M, int64_t s, int64_t) {
+__global__ __launch_bounds__(UTB) void ens_fold(const EMember* __restrict__ m, int nm,
+                                                const Mask* __restrict__ due) {
+  update_tiles(m, nm, due, [](const EMember& M, int64_t s, int64_t) {
     if (s >= M.g.vh) return;
     using RV = typename PV::R;
     const Field<P64> x = field_at<P64>(M.x, M.g.nblk);
@@ -276,17 +280,13 @@ __global__ __launch_bounds__(UTB) void ens_fold(const EMember* __restrict__ m, i
 // FP64 odd-site step: to = A_oo^-1 H_oe x (DAG: A_oo^-1 H^+_oe r64)
 template <bool DAG>
 __global__ __launch_bounds__(UTB) __attribute__((amdgpu_waves_per_eu(P64::waves)))
-void ens_res_odd(const EMember* __restrict__ m, int nm) {
-  auto body = [](const EMember& M, int64_t s, int64_t) {
+void ens_res_odd(const EMember* __restrict__ m, int nm, const Mask* __restrict__ due) {
+  update_tiles(m, nm, due, [](const EMember& M, int64_t s, int64_t) {
     if (s >= M.g.vh) return;
     const int64_t nb = M.g.nblk;
     k1_site<P64, DAG>(M.g, s, field_at<P64>(M.to, nb), field_at<P64>(DAG ? M.r64 : M.x, nb),
                       (const double2*)M.gauge64, (const double2*)M.ainv64);
-  };
-  if constexpr (DAG)
-    update_tiles(m, nm, DueGo{}, body);
-  else
-    update_tiles(m, nm, DueAll{}, body);
+  });
 }
 
 // FP64 even-site step with partial sums:
@@ -294,8 +294,9 @@ void ens_res_odd(const EMember* __restrict__ m, int nm) {
 //    DAG: rn64 = Mhat^+ r64,     partial |rn64|^2
 template <bool DAG>
 __global__ __launch_bounds__(UTB) __attribute__((amdgpu_waves_per_eu(P64::waves)))
-void ens_res_even(const EMember* __restrict__ m, int nm, double* __restrict__ part) {
-  auto body = [part](const EMember& M, int64_t s, int64_t b) {
+void ens_res_even(const EMember* __restrict__ m, int nm, const Mask* __restrict__ due,
+                  double* __restrict__ part) {
+  update_tiles(m, nm, due, [part](const EMember& M, int64_t s, int64_t b) {
     double v[1] = {0.0};
     if (s < M.g.vh) {
       const int64_t nb = M.g.nblk;
@@ -314,18 +315,15 @@ void ens_res_even(const EMember* __restrict__ m, int nm, double* __restrict__ pa
       v[0] = site_norm2(y);
     }
     block_partial_at<1>(v, part, b);
-  };
-  if constexpr (DAG)
-    update_tiles(m, nm, DueGo{}, body);
-  else
-    update_tiles(m, nm, DueAll{}, body);
+  });
 }
 
 // After the FP64 Schur residual: converged, out of iterations, stagnated
 // (five updates without a factor-4 drop of |r|^2 after the oldest of six),
 // or go on.
 __global__ __launch_bounds__(256) void ens_fin_res(const EMember* __restrict__ m,
-                                                   const double* __restrict__ part) {
+                                                   const double* __restrict__ part,
+                                                   Mask* __restrict__ due) {
   const EMember& M = m[blockIdx.x];
   double t[1];
   member_total<1>(part, M.r0, M.nr, t);
@@ -360,6 +358,7 @@ __global__ __launch_bounds__(256) void ens_fin_res(const EMember* __restrict__ m
     }
   }
   st->done = done;
+  if (done != E_RUN) atomicAnd(due, ~(Mask(1) << blockIdx.x));
 }
 
 // After the FP64 normal residual: restart the inner iteration.  The stopping
@@ -387,8 +386,9 @@ __global__ __launch_bounds__(256) void ens_fin_rn(const EMember* __restrict__ m,
 
 // r = rn64, rt = r64 (inner precision), p = r + beta p
 template <class PO, class PV>
-__global__ __launch_bounds__(UTB) void ens_load(const EMember* __restrict__ m, int nm) {
-  update_tiles(m, nm, DueGo{}, [](const EMember& M, int64_t s, int64_t) {
+__global__ __launch_bounds__(UTB) void ens_load(const EMember* __restrict__ m, int nm,
+                                                const Mask* __restrict__ due) {
+  update_tiles(m, nm, due, [](const EMember& M, int64_t s, int64_t) {
     if (s >= M.g.vh) return;
     using R = typename PO::R;
     const int64_t nb = M.g.nblk;
@@ -422,6 +422,8 @@ struct Ensemble {
   EState* st_host = nullptr;      // pinned
   double* part = nullptr;         // partial sums, one row per tile
   int64_t part_rows = 0;
+  Mask* due = nullptr;            // device: members due an update stage
+  Mask* due_host = nullptr;       // pinned
   hipGraphExec_t graph = nullptr;
   std::string graph_key;
   std::map<std::string, TuneEntry> tuned;
@@ -585,10 +587,10 @@ void launch_core(Ensemble* E, int nm, int64_t ntiles, bool finalise) {
   hipStream_t s = E->stream;
   hipLaunchKernelGGL((ens_k1<PO, false, TB>), g, b, 0, s, E->table, nm);
   hipLaunchKernelGGL((ens_k2<PO, TB>), g, b, 0, s, E->table, nm, E->part);
-  if (finalise) hipLaunchKernelGGL(ens_fin_alpha, f, fb, 0, s, E->table, E->part);
+  if (finalise) hipLaunchKernelGGL(ens_fin_alpha, f, fb, 0, s, E->table, E->part, E->due);
   hipLaunchKernelGGL((ens_k1<PO, true, TB>), g, b, 0, s, E->table, nm);
   hipLaunchKernelGGL((ens_k4<PO, PV, TB>), g, b, 0, s, E->table, nm, E->part);
-  if (finalise) hipLaunchKernelGGL(ens_fin_beta, f, fb, 0, s, E->table, E->part);
+  if (finalise) hipLaunchKernelGGL(ens_fin_beta, f, fb, 0, s, E->table, E->part, E->due);
   hipLaunchKernelGGL((ens_k5<PO, PV, TB>), g, b, 0, s, E->table, nm);
   LQ_HIP(hipGetLastError());
 }
@@ -597,14 +599,14 @@ template <class PO, class PV>
 void launch_update(Ensemble* E, int nm, int64_t nutiles) {
   const dim3 g((unsigned)std::min<int64_t>(nutiles, UGRID)), b(UTB), f((unsigned)nm), fb(256);
   hipStream_t s = E->stream;
-  hipLaunchKernelGGL((ens_fold<PV>), g, b, 0, s, E->table, nm);
-  hipLaunchKernelGGL((ens_res_odd<false>), g, b, 0, s, E->table, nm);
-  hipLaunchKernelGGL((ens_res_even<false>), g, b, 0, s, E->table, nm, E->part);
-  hipLaunchKernelGGL(ens_fin_res, f, fb, 0, s, E->table, E->part);
-  hipLaunchKernelGGL((ens_res_odd<true>), g, b, 0, s, E->table, nm);
-  hipLaunchKernelGGL((ens_res_even<true>), g, b, 0, s, E->table, nm, E->part);
+  hipLaunchKernelGGL((ens_fold<PV>), g, b, 0, s, E->table, nm, E->due);
+  hipLaunchKernelGGL((ens_res_odd<false>), g, b, 0, s, E->table, nm, E->due);
+  hipLaunchKernelGGL((ens_res_even<false>), g, b, 0, s, E->table, nm, E->due, E->part);
+  hipLaunchKernelGGL(ens_fin_res, f, fb, 0, s, E->table, E->part, E->due);
+  hipLaunchKernelGGL((ens_res_odd<true>), g, b, 0, s, E->table, nm, E->due);
+  hipLaunchKernelGGL((ens_res_even<true>), g, b, 0, s, E->table, nm, E->due, E->part);
   hipLaunchKernelGGL(ens_fin_rn, f, fb, 0, s, E->table, E->part);
-  hipLaunchKernelGGL((ens_load<PO, PV>), g, b, 0, s, E->table, nm);
+  hipLaunchKernelGGL((ens_load<PO, PV>), g, b, 0, s, E->table, nm, E->due);
   LQ_HIP(hipGetLastError());
 }
 
@@ -687,6 +689,9 @@ Ensemble* ensemble_create(lq_ctx* const* members, int n) {
     for (lq_ctx* c : E->mem) rows += ceil_div(c->geo.vh, TILE_CHOICES[0]);
     E->part_rows = rows;
     LQ_HIP(hipMalloc(reinterpret_cast<void**>(&E->part), sizeof(double) * 2 * rows));
+    LQ_HIP(hipMalloc(reinterpret_cast<void**>(&E->due), sizeof(Mask)));
+    LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&E->due_host), sizeof(Mask),
+                         hipHostMallocDefault));
   } catch (...) {
     ensemble_destroy(E);
     throw;
@@ -703,6 +708,8 @@ void ensemble_destroy(Ensemble* E) {
   if (E->st) (void)hipFree(E->st);
   if (E->st_host) (void)hipHostFree(E->st_host);
   if (E->part) (void)hipFree(E->part);
+  if (E->due) (void)hipFree(E->due);
+  if (E->due_host) (void)hipHostFree(E->due_host);
   if (E->stream) (void)hipStreamDestroy(E->stream);
   delete E;
 }
@@ -861,6 +868,8 @@ void ensemble_solve(Ensemble* E, void* const* dev_x, const void* const* dev_b,
     build_table(E, inner, tb, live, nt, nu);
     int tbl_n = (int)live.size();
     int64_t tbl_tiles = nt;
+    *E->due_host = tbl_n == 64 ? ~Mask(0) : (Mask(1) << tbl_n) - 1;  // every member
+    LQ_HIP(hipMemcpyAsync(E->due, E->due_host, sizeof(Mask), hipMemcpyHostToDevice, E->stream));
     update(E, inner, tbl_n, nu);  // initial residuals; starts the iteration
     const int max_chunks = maxiter / check_every + 4;
     for (int chunk = 0; chunk < max_chunks; ++chunk) {

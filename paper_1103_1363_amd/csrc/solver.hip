@@ -745,6 +745,10 @@ bool fcg_net(lq_ctx* ctx, Work* w, Net* net, double target, int maxiter, SolveSt
     ss.dslash += 2;
     axpby<P64, P64, P32>(ctx, r, 1.0, w->rn64, 0.0, w->rn64);
     const double rn0 = std::sqrt(nrm32(ctx, r));
+    // an FP32 cycle reduces the normal residual by about 1e-3 reliably; the
+    // last cycle stops at the reduction the Schur residual still needs
+    // (with a margin of 2), instead of overshooting the tolerance
+    const double cycle = std::max(1e-3, 0.5 * target / beta);
     axpby_f32(ctx, xl, 0.0, r, 0.0, r);
     precond(z, r);
     axpby_f32(ctx, p, 1.0, z, 0.0, z);
@@ -766,7 +770,7 @@ bool fcg_net(lq_ctx* ctx, Work* w, Net* net, double target, int maxiter, SolveSt
         fb = true;
         return false;
       }
-      if (rn <= 1e-3 * rn0 || ss.iterations >= maxiter) break;
+      if (rn <= cycle * rn0 || ss.iterations >= maxiter) break;
       precond(z, r);
       // p = z + beta p with beta making p conjugate to the previous direction
       const cplx bt = -cdot32(ctx, q, z) / pq;

@@ -1,7 +1,7 @@
 """Summarise a rocprofv3 kernel trace (SQLite .db or kernel_trace.csv), or
 turn two counter runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per launch.
 
-Usage: python -m paper_1103_1363_amd.prof_summary TRACE [--top N]
+Usage: python -m paper_1103_1363_amd.prof_summary TRACE [--top N] [--match REGEX]
        python -m paper_1103_1363_amd.prof_summary --pmc FETCH_CSV WRITE_CSV [--kernel SUBSTR]
 
 For every kernel: launches, total and average duration, and the average over
@@ -41,10 +41,12 @@ def short(name):
     return re.sub(r"\(.*", "", name)
 
 
-def summary(path, top=20):
+def summary(path, top=20, match=None):
     durs = load(path)
     rows = []
     for name, ds in durs.items():
+        if match and not re.search(match, short(name)):
+            continue
         med = statistics.median(ds)
         work = [d for d in ds if d >= 0.25 * med]
         rows.append((sum(ds), short(name), len(ds), sum(ds) / len(ds), len(work),
@@ -59,16 +61,24 @@ def summary(path, top=20):
     return "\n".join(out)
 
 
+# Sources that define the single-lattice CG iteration kernels (cg_k1 ... cg_k5):
+# their device code, the precision traits and loads they use, and the
+# reduction helpers; with the compile flags, they fix the kernels' code.
+KERNEL_SOURCES = ("solver_kernels.h", "dslash_core.h", "reduce.h", "lq_internal.h",
+                  "site_index.h")
+
+
 def source_digest():
-    """sha256 of every source file of the library (any change invalidates
-    counter figures taken on an older build)."""
+    """sha256 of the CG iteration kernels' sources and the compile flags
+    (any change invalidates counter figures taken on an older build)."""
     import hashlib
+    from paper_1103_1363_amd import build
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(here)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(here, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    h.update(" ".join(f for f in build.FLAGS if not f.startswith("-I")).encode())
     return h.hexdigest()[:16]
 
 
@@ -117,6 +127,7 @@ def main():
     ap.add_argument("--top", type=int, default=20)
     ap.add_argument("--pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--kernel")
+    ap.add_argument("--match", help="regular expression on the short kernel name")
     a = ap.parse_args()
     if a.pmc:
         cf, cw, rows = pmc_traffic(a.pmc[0], a.pmc[1], a.kernel)
@@ -128,7 +139,7 @@ def main():
             print(f"{name[:58]:58s} {n:10d} {f:14.4g} {w:14.4g}")
         return
     print(f"# source: {os.path.basename(a.trace)} (durations in ns in the trace)")
-    print(summary(a.trace, a.top))
+    print(summary(a.trace, a.top, a.match))
 
 
 if __name__ == "__main__":
