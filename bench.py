@@ -446,6 +446,20 @@ def main():
                                 "GB/s": round(rp.bytes / tp / 1e9, 1)}
         result["speedup_vs_plain_fp64"] = round(tp / (wall / a.steps), 3)
         result["mixed_vs_plain_rel_error"] = err
+        log("BiCGStab on the Schur operator, same inner precision and plain FP64")
+        bi = {}
+        for name, prec in ((a.inner, inner), ("f64", lq.F64)):
+            lat.solve_device(dx2, db, KAPPA, CSW, TOL, solver=lq.BICGSTAB, inner_prec=prec)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            rb = lat.solve_device(dx2, db, KAPPA, CSW, TOL, solver=lq.BICGSTAB,
+                                  inner_prec=prec)[0]
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - tb
+            bi[name] = {"ms": round(tb * 1e3, 2), "iterations": rb.iterations,
+                        "reliable_updates": rb.reliable_updates, "fallback": rb.fallback,
+                        "true_residual": rb.true_residual, "GB/s": round(rb.bytes / tb / 1e9, 1)}
+        result["bicgstab"] = bi
         del dx2
 
     log("profiled solve (per-kernel HIP events)")
