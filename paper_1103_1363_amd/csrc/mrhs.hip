@@ -311,6 +311,9 @@ __device__ __forceinline__ void mr_h2f(const mr_u4 w, float f[8]) {
 }
 
 // x_r += alpha_r p_r;  r_r -= alpha_r s_r;  per-block partial |r_r|^2.
+// Every operand of a (site, RHS) is loaded before the first store: the
+// fields are distinct, but the compiler cannot know it, and interleaved
+// loads and stores would leave one load pair in flight per thread.
 __global__ __launch_bounds__(256) void mr_cg_update(Geo g, const MRState* __restrict__ mst,
                                                     MField<P32> x, MField<P32> rv, MField<P16> p,
                                                     MField<P16> sv, double* __restrict__ part) {
@@ -327,28 +330,43 @@ __global__ __launch_bounds__(256) void mr_cg_update(Geo g, const MRState* __rest
       float4* rp = reinterpret_cast<float4*>(rv.d + i0);
       const mr_u4* pp = reinterpret_cast<const mr_u4*>(p.d + i0);
       const mr_u4* sp = reinterpret_cast<const mr_u4*>(sv.d + i0);
+      float4 xv[6], rr[6];
+      mr_u4 pw[3], sw[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        pw[k] = pp[k];
+        sw[k] = sp[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        xv[k] = xp[k];
+        rr[k] = rp[k];
+      }
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         float pf[8], sf[8];
-        const mr_u4 pw = pp[k], sw = sp[k];
-        mr_h2f(pw, pf);
-        mr_h2f(sw, sf);
+        mr_h2f(pw[k], pf);
+        mr_h2f(sw[k], sf);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          float4 xv = xp[2 * k + h], rr = rp[2 * k + h];
-          xv.x += ap * pf[4 * h];
-          xv.y += ap * pf[4 * h + 1];
-          xv.z += ap * pf[4 * h + 2];
-          xv.w += ap * pf[4 * h + 3];
-          rr.x -= as * sf[4 * h];
-          rr.y -= as * sf[4 * h + 1];
-          rr.z -= as * sf[4 * h + 2];
-          rr.w -= as * sf[4 * h + 3];
-          xp[2 * k + h] = xv;
-          rp[2 * k + h] = rr;
-          acc += (double)rr.x * rr.x + (double)rr.y * rr.y + (double)rr.z * rr.z +
-                 (double)rr.w * rr.w;
+          float4& xo = xv[2 * k + h];
+          float4& ro = rr[2 * k + h];
+          xo.x += ap * pf[4 * h];
+          xo.y += ap * pf[4 * h + 1];
+          xo.z += ap * pf[4 * h + 2];
+          xo.w += ap * pf[4 * h + 3];
+          ro.x -= as * sf[4 * h];
+          ro.y -= as * sf[4 * h + 1];
+          ro.z -= as * sf[4 * h + 2];
+          ro.w -= as * sf[4 * h + 3];
+          acc += (double)ro.x * ro.x + (double)ro.y * ro.y + (double)ro.z * ro.z +
+                 (double)ro.w * ro.w;
         }
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        xp[k] = xv[k];
+        rp[k] = rr[k];
       }
     }
   }

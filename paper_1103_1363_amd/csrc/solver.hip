@@ -552,11 +552,8 @@ bool bicgstab(lq_ctx* ctx, Work* w, double target, double delta, int maxiter, in
     rt2 = schur_residual(ctx, w, ss);
     ss.reliable += 1;
     if (!std::isfinite(rt2)) {
-      if (PO::id != LQ_F64) {
-        want_fallback = true;
-        return false;
-      }
-      throw Error(LQ_ENAN, "NaN in the FP64 residual");
+      want_fallback = true;
+      return false;
     }
     if (rt2 <= target2) return true;
     if (h.reason == R_MAXITER || h.iter >= maxiter) return false;
@@ -570,12 +567,12 @@ bool bicgstab(lq_ctx* ctx, Work* w, double target, double delta, int maxiter, in
     const bool no_progress = nhist == 6 && std::fmin(std::fmin(hist[1], hist[2]),
                                                      std::fmin(std::fmin(hist[3], hist[4]),
                                                                hist[5])) > 0.25 * hist[0];
+    // BiCGStab stagnates on indefinite systems (a spectrum on both sides of
+    // the imaginary axis), in any precision; the plain FP64 CG on the normal
+    // equations takes over
     if (no_progress || restarts > 20) {
-      if (PO::id != LQ_F64) {
-        want_fallback = true;
-        return false;
-      }
-      if (restarts > 20) throw Error(LQ_ENAN, "BiCGStab broke down repeatedly");
+      want_fallback = true;
+      return false;
     }
   }
 }
@@ -1233,13 +1230,18 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
         bool fb = false;
         int left = maxiter - ss.iterations;
         SolveStats inner_ss;
-        bool conv = run_inner(ctx, w, p.solver, ss.fallback ? LQ_F64 : inner, frac * tol * bhat_norm,
-                           ss.fallback ? 0.0 : delta, left, check_every, use_graph,
-                           p.fault_inject, inner_ss, fb, prof, net, restart);
+        // once the plain FP64 CG has taken over, the tightening rounds stay with it
+        const bool plain = ss.fallback;
+        bool conv = plain
+                        ? run_cg(ctx, w, LQ_F64, frac * tol * bhat_norm, 0.0, left, check_every,
+                                 use_graph, 0, inner_ss, fb, prof)
+                        : run_inner(ctx, w, p.solver, inner, frac * tol * bhat_norm, delta, left,
+                                    check_every, use_graph, p.fault_inject, inner_ss, fb, prof,
+                                    net, restart);
         ss.iterations += inner_ss.iterations;
         ss.reliable += inner_ss.reliable;
         // the flexible solvers count their own operator applications
-        ss.dslash += inner_ss.dslash + (net_solver ? 0 : 4 * inner_ss.iterations);
+        ss.dslash += inner_ss.dslash + (net_solver && !plain ? 0 : 4 * inner_ss.iterations);
         ss.fallback |= inner_ss.fallback;
         if (fb) {
           ss.fallback = 1;
