@@ -449,7 +449,7 @@ def main():
         log("BiCGStab on the Schur operator, same inner precision and plain FP64")
         bi = {}
         for name, prec in ((a.inner, inner), ("f64", lq.F64)):
-            lat.solve_device(dx2, db, KAPPA, CSW, TOL, solver=lq.BICGSTAB, inner_prec=prec)
+            # no warm-up: on this indefinite system BiCGStab runs for seconds
             torch.cuda.synchronize()
             tb = time.perf_counter()
             rb = lat.solve_device(dx2, db, KAPPA, CSW, TOL, solver=lq.BICGSTAB,
