@@ -318,7 +318,9 @@ lq_status lq_ensemble_tune(lq_ensemble* e, int inner_prec, const char* cache_pat
  * device fields dev_b[j] -> dev_x[j] (as lq_solve_device; caller-owned,
  * distinct), to the FP64 true residual tol for every member.  params: solver
  * LQ_CGNR, inner_prec, maxiter, delta, check_every, use_graph as for
- * lq_solve (batched, profile, fault_inject must be 0).  Tunes on first use
+ * lq_solve (batched and profile must be 0; fault_inject = 1, for tests, makes the
+ * members of even index withhold their inner corrections so that they stagnate
+ * and fall back).  Tunes on first use
  * of a precision (lq_ensemble_tune without a file).  reports: n entries (may
  * be NULL; seconds = whole batch); rep may be NULL.  Returns LQ_ENOCONV when
  * a member did not converge, with the reports filled. */

@@ -71,7 +71,7 @@ struct EState {
                     // giving up; 0 = no such test (FP64 inner iteration)
   int ref_iter;
   int nhist;
-  int pad_;
+  int withhold;     // tests only: the fold drops the inner correction
   double ref_rt2;
   double hist[6];   // FP64 Schur residuals of the last reliable updates
 };
@@ -267,9 +267,10 @@ __global__ __launch_bounds__(UTB) void ens_fold(const EMember* __restrict__ m, i
     C<RV> d[12];
     load_scaled<P64>(x, s, a);
     load_scaled<PV>(xl, s, d);
+    const double keep = M.st->withhold ? 0.0 : 1.0;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      a[c] = a[c] + C<double>{(double)d[c].re, (double)d[c].im};
+      a[c] = a[c] + keep * C<double>{(double)d[c].re, (double)d[c].im};
       d[c] = C<RV>{(RV)0, (RV)0};
     }
     store_spinor<P64>(x, s, a);
@@ -796,8 +797,10 @@ void ensemble_solve(Ensemble* E, void* const* dev_x, const void* const* dev_b,
   lq_solver_params p{};
   if (prm) p = *prm;
   LQ_CHECK(p.solver == LQ_CGNR, LQ_EINVAL, "the uneven batch runs CG on the normal equations");
-  LQ_CHECK(!p.batched && !p.profile && !p.fault_inject, LQ_EINVAL,
-           "batched, profile and fault_inject do not apply to the uneven batch");
+  LQ_CHECK(!p.batched && !p.profile, LQ_EINVAL,
+           "batched and profile do not apply to the uneven batch");
+  LQ_CHECK(!p.fault_inject || p.inner_prec != LQ_F64, LQ_EINVAL,
+           "fault_inject needs a mixed-precision inner iteration");
   const int inner = p.inner_prec;
   const int nm = (int)E->mem.size();
   for (int j = 0; j < nm; ++j) {
@@ -846,6 +849,10 @@ void ensemble_solve(Ensemble* E, void* const* dev_x, const void* const* dev_b,
     s.ru = s.done == E_RUN ? 1 : 0;
     s.updates = -1;  // the first pass of the update stage forms the initial residuals
     s.stall_iters = inner == LQ_F64 ? 0 : STALL_ITERS;
+    // tests: with fault_inject the members whose index is even withhold
+    // every inner correction from the FP64 solution (the initial residual
+    // is formed normally), so they must stagnate and fall back
+    s.withhold = (p.fault_inject && j % 2 == 0) ? 1 : 0;
     s.ref_rt2 = INFINITY;
     const double target = 0.5 * tol * bhat_norm[j];
     s.cg.target2 = target * target;

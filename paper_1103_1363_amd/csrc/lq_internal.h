@@ -399,8 +399,8 @@ void mrhs_iterate(lq_ctx* ctx, MRWork* w, int check_every, bool use_graph);
 void mrhs_state_upload(lq_ctx* ctx, MRWork* w);
 void mrhs_state_download(lq_ctx* ctx, MRWork* w);
 double mrhs_iteration_site_bytes(int nrhs);
-void mrhs_slot_from_single(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single64,
-                           int r, double a, double b);
+void mrhs_slot_from_single(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single,
+                           int r, double a, double b, int single_prec = LQ_F64);
 void mrhs_single_from_slot(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single64,
                            int r, double a, double b);
 

@@ -698,12 +698,21 @@ double mrhs_iteration_site_bytes(int nrhs) {
          + nrhs * (S32 + 2 * S);                  // p = r + beta p
 }
 
-void mrhs_slot_from_single(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single64,
-                           int r, double a, double b) {
-  if (prec == LQ_F16)
-    slot_axpby<P64, P16>(ctx, mfield, w->nrhs, single64, r, a, b, 1);
-  else
-    slot_axpby<P64, P32>(ctx, mfield, w->nrhs, single64, r, a, b, 1);
+void mrhs_slot_from_single(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single,
+                           int r, double a, double b, int single_prec) {
+  LQ_CHECK(single_prec == LQ_F64 || single_prec == LQ_F32, LQ_EINVAL,
+           "slot sources are FP64 or FP32 fields");
+  if (single_prec == LQ_F64) {
+    if (prec == LQ_F16)
+      slot_axpby<P64, P16>(ctx, mfield, w->nrhs, single, r, a, b, 1);
+    else
+      slot_axpby<P64, P32>(ctx, mfield, w->nrhs, single, r, a, b, 1);
+  } else {
+    if (prec == LQ_F16)
+      slot_axpby<P32, P16>(ctx, mfield, w->nrhs, single, r, a, b, 1);
+    else
+      slot_axpby<P32, P32>(ctx, mfield, w->nrhs, single, r, a, b, 1);
+  }
 }
 void mrhs_single_from_slot(lq_ctx* ctx, MRWork* w, void* mfield, int prec, void* single64,
                            int r, double a, double b) {

@@ -260,16 +260,35 @@ double schur_residual(lq_ctx* ctx, Work* w, SolveStats& ss) {
   return nrm2(ctx, w->r64);
 }
 
+// Normal residual of the restart: r = Mhat^+ r64 in the vector precision and
+// rt = r64 rounded to it; returns |r|^2.  A mixed-precision iteration forms r
+// with the FP32 operator from the rounded r64: r only restarts the inner
+// vector, which holds FP32 accuracy anyway, for half the bytes of the FP64
+// sweep.  (The FP64 residual r64 itself always comes from the FP64 operator.)
 template <class PO, class PV>
-void load_inner_state(lq_ctx* ctx, Work* w, int ip, double rn2_64, bool restart_p, double beta) {
-  // r = rn64, rt = r64 (cast to inner precision); p = r (+ beta p)
-  axpby<P64, P64, PV>(ctx, w->r[ip], 1.0, w->rn64, 0.0, w->rn64);
-  axpby<P64, P64, PV>(ctx, w->rt[ip], 1.0, w->r64, 0.0, w->r64);
+double restart_residuals(lq_ctx* ctx, Work* w, int ip, SolveStats& ss) {
+  ss.dslash += 2;
+  if constexpr (PV::id == LQ_F64) {
+    schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
+    axpby<P64, P64, PV>(ctx, w->r[ip], 1.0, w->rn64, 0.0, w->rn64);
+    axpby<P64, P64, PV>(ctx, w->rt[ip], 1.0, w->r64, 0.0, w->r64);
+    return nrm2(ctx, w->rn64);
+  } else {
+    axpby<P64, P64, PV>(ctx, w->rt[ip], 1.0, w->r64, 0.0, w->r64);
+    schur(ctx, w->r[ip], w->rt[ip], w->to, 1, LQ_F32);  // w->to: FP64 odd, holds an FP32 one
+    double v = 0.0;
+    norm2(ctx, &v, w->r[ip], LQ_F32);
+    return v;
+  }
+}
+
+template <class PO, class PV>
+void load_inner_state(lq_ctx* ctx, Work* w, int ip, bool restart_p, double beta) {
+  // p = r (+ beta p), r and rt already restarted
   if (restart_p)
     axpby<PV, PV, PO>(ctx, w->p[ip], 1.0, w->r[ip], 0.0, w->r[ip]);
   else
     axpby<PV, PO, PO>(ctx, w->p[ip], 1.0, w->r[ip], beta, w->p[ip]);
-  (void)rn2_64;
 }
 
 // Returns true when the Schur residual reached target; x (even half) updated.
@@ -287,11 +306,9 @@ bool cg_normal(lq_ctx* ctx, Work* w, double target, double delta, int maxiter, i
   want_fallback = false;
   double rt2 = schur_residual(ctx, w, ss);
   if (rt2 <= target2) return true;
-  schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
-  ss.dslash += 2;
-  double rr = nrm2(ctx, w->rn64);
+  double rr = restart_residuals<PO, PV>(ctx, w, ip, ss);
   zero<PV>(ctx, w->xl[ip]);
-  load_inner_state<PO, PV>(ctx, w, ip, rr, true, 0.0);
+  load_inner_state<PO, PV>(ctx, w, ip, true, 0.0);
   CGState& h = *w->st_host;
   std::memset(&h, 0, sizeof(CGState));
   h.rr = rr;
@@ -368,14 +385,12 @@ bool cg_normal(lq_ctx* ctx, Work* w, double target, double delta, int maxiter, i
         return false;
       }
     }
-    schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
-    ss.dslash += 2;
-    const double rr_new = nrm2(ctx, w->rn64);
+    const double rr_new = restart_residuals<PO, PV>(ctx, w, ip, ss);
     // The iteration that triggered the update computed x, r and
     // beta = |r_k+1|^2 / |r_k|^2 but not p_k+1.  p continues as
     // r_new + (|r_new|^2 / |r_k|^2) p_k, with |r_k|^2 = h.rr / h.beta.
     const double beta = (h.rr > 0.0 && h.beta > 0.0) ? h.beta * rr_new / h.rr : 0.0;
-    load_inner_state<PO, PV>(ctx, w, ip, rr_new, false, beta);
+    load_inner_state<PO, PV>(ctx, w, ip, false, beta);
     h.rr = rr_new;
     h.rt2 = rt2;
     h.rt2_max = rt2;
@@ -889,6 +904,20 @@ void free_work(lq_ctx* ctx) {
 // single-RHS FP64 kernels on each RHS's own FP64 fields.
 namespace {
 
+// Normal residual Mhat^+ r64 of a restart in FP32 (the inner vectors hold
+// FP32 accuracy; the FP32 sweep moves half the bytes of the FP64 one), into
+// the FP32 field w->r[LQ_F16]; returns its squared norm.
+double normal_residual32(lq_ctx* ctx, Work* w, SolveStats& ss) {
+  void* r32 = w->rt[LQ_F16];
+  void* rn32 = w->r[LQ_F16];
+  axpby<P64, P64, P32>(ctx, r32, 1.0, w->r64, 0.0, w->r64);
+  schur(ctx, rn32, r32, w->to, 1, LQ_F32);  // w->to: FP64 odd, holds an FP32 one
+  ss.dslash += 2;
+  double v = 0.0;
+  norm2(ctx, &v, rn32, LQ_F32);
+  return v;
+}
+
 void solve_batched(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x,
                    const void* dev_b, int nrhs, double tol, const lq_solver_params& p,
                    lq_solve_report* report) {
@@ -896,7 +925,8 @@ void solve_batched(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_
   LQ_CHECK(p.solver == LQ_CGNR, LQ_EINVAL, "batched solves use CG on the normal equations");
   auto t0 = std::chrono::steady_clock::now();
   const double bytes0 = ctx->bytes;
-  Work* w = work(ctx, LQ_F64);
+  Work* w = work(ctx, LQ_F16);  // FP32 single fields of the restarts
+  work(ctx, LQ_F64);
   MRWork* mw = mrhs_work(ctx, nrhs);
   mrhs_tables(ctx, true);  // before any graph capture
   const int64_t nb = ctx->geo.nblk;
@@ -964,11 +994,9 @@ void solve_batched(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_
         mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->r64, r, 0.0, 0.0);
         continue;
       }
-      schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
-      ss.dslash += 2;
-      const double rr = nrm2(ctx, w->rn64);
-      mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->rn64, r, 1.0, 0.0);
-      mrhs_slot_from_single(ctx, mw, mw->p, LQ_F16, w->rn64, r, 1.0, 0.0);
+      const double rr = normal_residual32(ctx, w, ss);
+      mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->r[LQ_F16], r, 1.0, 0.0, LQ_F32);
+      mrhs_slot_from_single(ctx, mw, mw->p, LQ_F16, w->r[LQ_F16], r, 1.0, 0.0, LQ_F32);
       h.on[r] = 1;
       h.rr[r] = rr;
       h.rr_max[r] = rr;
@@ -1047,12 +1075,10 @@ void solve_batched(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_
             fell_back = true;
             break;
           }
-          schur(ctx, w->rn64, w->r64, w->to, 1, LQ_F64);
-          ss.dslash += 2;
-          const double rr_new = nrm2(ctx, w->rn64);
+          const double rr_new = normal_residual32(ctx, w, ss);
           const double beta = (h.rr[r] > 0.0 && h.beta[r] > 0.0) ? h.beta[r] * rr_new / h.rr[r] : 0.0;
-          mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->rn64, r, 1.0, 0.0);
-          mrhs_slot_from_single(ctx, mw, mw->p, LQ_F16, w->rn64, r, 1.0, beta);
+          mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->r[LQ_F16], r, 1.0, 0.0, LQ_F32);
+          mrhs_slot_from_single(ctx, mw, mw->p, LQ_F16, w->r[LQ_F16], r, 1.0, beta, LQ_F32);
           h.rr[r] = rr_new;
           h.rr_max[r] = rr_new;
           h.target2[r] = target * target * rr_new / t2 * 0.25;

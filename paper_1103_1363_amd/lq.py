@@ -420,7 +420,8 @@ class Ensemble:
         return rep.as_dict()
 
     def solve_device(self, dev_x, dev_b, kappas, csws, tol=1e-10, inner_prec=F16, maxiter=0,
-                     delta=0.0, check_every=0, use_graph=0, raise_on_noconv=True):
+                     delta=0.0, check_every=0, use_graph=0, fault_inject=0,
+                     raise_on_noconv=True):
         """dev_x[j], dev_b[j]: full-lattice FP64 device fields of lattice j.
         Returns (member reports, batch report dict)."""
         n = len(self.lats)
@@ -429,7 +430,8 @@ class Ensemble:
         bs = (ct.c_void_p * n)(*[t.data_ptr() for t in dev_b])
         ka = np.ascontiguousarray(kappas, dtype=np.float64)
         cs = np.ascontiguousarray(csws, dtype=np.float64)
-        p = SolverParams(CGNR, inner_prec, maxiter, delta, 0, check_every, use_graph, 0, 0, 0)
+        p = SolverParams(CGNR, inner_prec, maxiter, delta, 0, check_every, use_graph,
+                         fault_inject, 0, 0)
         reps = (SolveReport * n)()
         er = EnsembleReport()
         rc = self._L.lq_ensemble_solve(self._h, xs, bs, _dptr(ka), _dptr(cs), float(tol),

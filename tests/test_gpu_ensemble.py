@@ -131,6 +131,26 @@ def test_without_graph_same_result(lq):
     ens.close()
 
 
+def test_fault_injection_falls_back(lq):
+    """Members of even index withhold their inner corrections: their FP64
+    residual cannot fall, the stagnation test stops them, and the FP64 CG of
+    their own context finishes them; the other members finish in the batch."""
+    tol, csw = 1e-10, 1.0
+    say("uneven batch fault injection")
+    lats, us, bs, db, dx = make_members(lq, SMALL, csw)
+    ens = lq.Ensemble(lats)
+    kap = [k for _, k, _, _ in SMALL]
+    reps, er = ens.solve_device(dx, db, kap, [csw] * 4, tol, inner_prec=lq.F16, fault_inject=1)
+    say(f"  {er} fallback={[r.fallback for r in reps]}")
+    assert [r.fallback for r in reps] == [1, 0, 1, 0]
+    for j in range(4):
+        x = lats[j].to_host(dx[j], lq.FULL, lq.F64).reshape(bs[j].shape)
+        assert oracle_residual(us[j], kap[j], csw, x, bs[j]) <= tol
+    with pytest.raises(lq.LQError):
+        ens.solve_device(dx, db, kap, [csw] * 4, tol, inner_prec=lq.F64, fault_inject=1)
+    ens.close()
+
+
 def test_maxiter_reports_noconv(lq):
     say("uneven batch maxiter")
     lats, us, bs, db, dx = make_members(lq, SMALL[:2], 1.0)
