@@ -265,9 +265,6 @@ constexpr int MR_BLK = 256;
 #define LQ_MR_SITES_PER_BLOCK 32
 #endif
 constexpr int MR_SITES_PER_BLOCK = LQ_MR_SITES_PER_BLOCK;  // 4 waves, each every 4th site
-#ifndef LQ_MR_MASKED_LOADS
-#define LQ_MR_MASKED_LOADS 0
-#endif
 
 // out = H in (EPI_NONE), A^-1 H in (EPI_CLOVINV) or A x - k2 H in
 // (EPI_SCHUR2, with per-workgroup partial |out|^2 per RHS in part[block][r]),
@@ -314,50 +311,81 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
 #pragma unroll
       for (int h = 0; h < 8; ++h) nt[h] = nbase[(s + 4) * 8 + h];
     }
-    // gather every operand of the site first (one memory round trip):
-    // neighbour scales, neighbour spinor blocks, link entries
-    const unsigned* lf = links + ((int64_t)p * nsite + s) * 36;
-    const unsigned* lb = links + (int64_t)(1 - p) * nsite * 36;
-    float nb[8];
-    mr_u4 bv[8];
-    unsigned lv[8];
-#if LQ_MR_MASKED_LOADS
-    // only lanes whose data is used issue the loads
-    const bool arow = q.c0 || q.c1;
+    // gather every operand of the site first (one memory round trip).  The
+    // neighbour spinor blocks are one 16-byte load per hop; the small
+    // operands (8 x nrhs neighbour scales, the 72 link entries, the 42
+    // clover words) are fetched with lane-dense loads, one word per lane,
+    // and each lane then picks its entries with a cross-lane permute: a
+    // wavefront load costs texture-address cycles for all 64 lanes however
+    // few distinct words it touches.
+    // (the small loads are issued first: loads complete in issue order, so
+    // the permutes below wait for them and not for the spinor blocks)
+    // scales: lane l holds RHS (l & 7) [+ 8] of neighbour l >> 3
+    const int dh = lane >> 3, dr = lane & 7;
+    int sd = sy[0];
 #pragma unroll
-    for (int h = 0; h < 8; ++h) {
-      nb[h] = 0.f;
-      bv[h] = mr_u4{0u, 0u, 0u, 0u};
-      lv[h] = 0u;
-      if (li < nrhs) nb[h] = mr_ld<float>(in.norm + (int64_t)sy[h] * nrhs, 4u * (unsigned)lic);
-      if (bl) bv[h] = mr_ld<mr_u4>(ind + (int64_t)sy[h] * sblk, bofs);
-      const unsigned* lk = (h & 1) ? lb + (int64_t)sy[h] * 36 + 9 * (h >> 1) : lf + 9 * (h >> 1);
-      if (arow) lv[h] = mr_ld<unsigned>(lk, (h & 1) ? q.eb : q.ef);
+    for (int h = 1; h < 8; ++h) sd = dh == h ? sy[h] : sd;
+    const float* nrow = in.norm + (int64_t)sd * nrhs;
+    const float na = nrow[dr < nrhs ? dr : nrhs - 1];
+    const float nbb = nrow[dr + 8 < nrhs ? dr + 8 : nrhs - 1];
+    // links: forward links of the site (36 contiguous words), then the
+    // backward links of mu = 0..3 at the neighbours (9 words each): words
+    // 0..63 in the first load, the last 8 in the second
+    const int64_t lbase = (int64_t)(1 - p) * nsite * 36;
+    int64_t lw0;
+    {
+      const int j = lane - 36, mu = j / 9;
+      int sb = sy[1];
+      sb = mu == 1 ? sy[3] : sb;
+      sb = mu == 2 ? sy[5] : sb;
+      sb = mu == 3 ? sy[7] : sb;
+      lw0 = lane < 36 ? ((int64_t)p * nsite + s) * 36 + lane : lbase + (int64_t)sb * 36 + j;
     }
-#else
-#pragma unroll
-    for (int h = 0; h < 8; ++h) {
-      nb[h] = mr_ld<float>(in.norm + (int64_t)sy[h] * nrhs, 4u * (unsigned)lic);
-      bv[h] = mr_ld<mr_u4>(ind + (int64_t)sy[h] * sblk, bofs);
-      const unsigned* lk = (h & 1) ? lb + (int64_t)sy[h] * 36 + 9 * (h >> 1) : lf + 9 * (h >> 1);
-      lv[h] = mr_ld<unsigned>(lk, (h & 1) ? q.eb : q.ef);
-    }
-#endif
-    // clover entries of the lane (two per block) and the x block
-    unsigned ce[2][2] = {{0u, 0u}, {0u, 0u}};
+    const unsigned lda = links[lw0];
+    const unsigned ldb = links[lbase + (int64_t)sy[7] * 36 + 28 + (lane < 8 ? lane : 7)];
+    // clover words of the site (two blocks of 21)
+    unsigned cw = 0u;
+    if constexpr (EPI != MR_EPI_NONE) cw = clov[s * MR_CLOV_SITE + (lane < 42 ? lane : 41)];
+    // the x block
     mr_u4 xv = {0u, 0u, 0u, 0u};
     float xn = 0.f;
-    if constexpr (EPI != MR_EPI_NONE) {
-      const unsigned* cl = clov + s * MR_CLOV_SITE;
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-          ce[cb][k] = mr_ld<unsigned>(cl + MR_CLOV_BLOCK * cb, q.cslot[k]);
-    }
     if constexpr (EPI == MR_EPI_SCHUR2) {
       xv = mr_ld<mr_u4>(reinterpret_cast<const unsigned*>(x.d) + s * sblk, bofs);
       xn = mr_ld<float>(x.norm + s * nrhs, 4u * (unsigned)lic);
+    }
+    mr_u4 bv[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) bv[h] = mr_ld<mr_u4>(ind + (int64_t)sy[h] * sblk, bofs);
+    // distribute: the lane's scale of each neighbour, its link entries, its
+    // clover entries
+    float nb[8];
+    unsigned lv[8];
+    unsigned ce[2][2] = {{0u, 0u}, {0u, 0u}};
+    {
+      const int ln = lic & 7;
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const float a = __shfl(na, h * 8 + ln, 64), b = __shfl(nbb, h * 8 + ln, 64);
+        nb[h] = lic < 8 ? a : b;
+      }
+      const int ef = (int)(q.ef >> 2), eb = (int)(q.eb >> 2);
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        lv[2 * mu] = __shfl(lda, 9 * mu + ef, 64);
+        if (mu < 3) {
+          lv[2 * mu + 1] = __shfl(lda, 36 + 9 * mu + eb, 64);
+        } else {
+          const unsigned a = __shfl(lda, 63, 64), b = __shfl(ldb, eb > 0 ? eb - 1 : 0, 64);
+          lv[7] = eb == 0 ? a : b;
+        }
+      }
+      if constexpr (EPI != MR_EPI_NONE) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int k = 0; k < 2; ++k)
+            ce[cb][k] = __shfl(cw, MR_CLOV_BLOCK * cb + (int)(q.cslot[k] >> 2), 64);
+      }
     }
     // keep the gather ahead of the arithmetic (the scheduler would otherwise
     // sink loads towards their uses and serialise the memory latency)
