@@ -67,6 +67,17 @@ int64_t tile_target() {
   return 65536;
 }
 
+// Largest number of sites of one parity per tile of the multi-RHS fields;
+// LQ_MR_TILE_SITES overrides the default (tuning experiments).
+int64_t mr_tile_target() {
+  const char* e = std::getenv("LQ_MR_TILE_SITES");
+  if (e) {
+    const long long v = std::atoll(e);
+    if (v >= 64) return v;
+  }
+  return 2048;
+}
+
 size_t field_bytes(const lq_ctx* ctx, int parity, int prec, int nrhs) {
   size_t one = parity_field_bytes(ctx->geo.nblk, prec);
   return one * (parity == LQ_FULL ? 2 : 1) * (size_t)(nrhs > 0 ? nrhs : 1);
@@ -133,6 +144,9 @@ lq_status lq_create(const int dims[4], int t_antiperiodic, void* hip_stream, lq_
   lq::choose_tiles(ctx->geo.L, lq::tile_target(), ctx->geo.T);
   lq::geo_finish(ctx->geo);
   ctx->geo.apt = t_antiperiodic ? 1 : 0;
+  ctx->mr_geo = ctx->geo;
+  lq::choose_tiles(ctx->geo.L, lq::mr_tile_target(), ctx->mr_geo.T);
+  lq::geo_finish(ctx->mr_geo);
   ctx->V = V;
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   ctx->cur = ctx->stream;

@@ -28,6 +28,10 @@ struct Ensemble;  // uneven batch of independent solves (ensemble.hip)
 
 struct lq_ctx {
   lq::Geo geo;
+  // Site numbering of the multi-RHS fields and tables: the same lattice in
+  // smaller tiles.  A site's nrhs spinors sit together (hundreds of bytes),
+  // so the neighbours across a tile must stay within the reach of L2.
+  lq::Geo mr_geo;
   int dims[4];
   int64_t V;
   hipStream_t stream = nullptr;   // caller's stream (public per-operation calls)

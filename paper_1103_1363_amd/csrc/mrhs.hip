@@ -105,16 +105,24 @@ __global__ void mr_nbr_kernel(Geo g, int* __restrict__ out) {
 
 // FP16 site-major copy of the links: all nine entries of U_mu(s), row 2
 // rebuilt from the FP64 compressed field.
-__global__ void mr_links_kernel(Geo g, const double2* __restrict__ g64, unsigned* __restrict__ out) {
-  const int64_t nsite = g.nblk * 64;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (p, s, mu)
+__global__ void mr_links_kernel(Geo gm, Geo gs, const double2* __restrict__ g64,
+                                unsigned* __restrict__ out) {
+  const int64_t nsite = gm.nblk * 64;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (p, m, mu)
   if (t >= 2 * nsite * 4) return;
   const int mu = (int)(t & 3);
   const int64_t ps = t >> 2;
   const int p = ps >= nsite ? 1 : 0;
-  const int64_t s = ps - p * nsite;
+  const int64_t m = ps - p * nsite;
+  if (m >= gm.vh) {  // padding sites
+#pragma unroll
+    for (int e = 0; e < 9; ++e) out[t * 9 + e] = 0u;
+    return;
+  }
+  int x[4];
+  site_coords(gm, p, m, x);
   C<double> u[9];
-  load_link<P64>(g64, g.nblk, p, mu, s, u);
+  load_link<P64>(g64, gs.nblk, p, mu, cb_index(gs, x), u);
 #pragma unroll
   for (int e = 0; e < 9; ++e)
     out[t * 9 + e] =
@@ -124,12 +132,21 @@ __global__ void mr_links_kernel(Geo g, const double2* __restrict__ g64, unsigned
 // FP16 site-major copy of a clover table (36 complex per site: per block
 // three packed diagonal pairs then the upper triangle) with the diagonal
 // unpacked to (d_k, 0).
-__global__ void mr_clov_kernel(Geo g, const double2* __restrict__ c64, unsigned* __restrict__ out) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.nblk * 64) return;
+__global__ void mr_clov_kernel(Geo gm, Geo gs, int p, const double2* __restrict__ c64,
+                               unsigned* __restrict__ out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= gm.nblk * 64) return;
+  if (m >= gm.vh) {  // padding sites
+#pragma unroll
+    for (int k = 0; k < MR_CLOV_SITE; ++k) out[m * MR_CLOV_SITE + k] = 0u;
+    return;
+  }
+  int x[4];
+  site_coords(gm, p, m, x);
+  const int64_t s = cb_index(gs, x);
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb) {
-    unsigned* o = out + s * MR_CLOV_SITE + cb * MR_CLOV_BLOCK;
+    unsigned* o = out + m * MR_CLOV_SITE + cb * MR_CLOV_BLOCK;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const double2 v = c64[clov_idx(s, 18 * cb + (k >> 1))];
@@ -147,16 +164,21 @@ __global__ void mr_clov_kernel(Geo g, const double2* __restrict__ c64, unsigned*
 // dst_slot = a * src + b * dst_slot (to_slot) or single = a * slot + b * single.
 // A zero coefficient drops its operand unread, so a = b = 0 clears the
 // destination whatever the other memory holds.
+// The single field and the slot hold the even sites, each in its own
+// numbering (g, gm).
 template <class PS, class PM>
-__global__ void mr_axpby_slot_kernel(Geo g, MField<PM> m, Field<PS> f, int r, double a, double b,
-                                     int to_slot) {
+__global__ void mr_axpby_slot_kernel(Geo g, Geo gm, MField<PM> m, Field<PS> f, int r, double a,
+                                     double b, int to_slot) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.vh) return;
+  int x[4];
+  site_coords(g, LQ_EVEN, s, x);
+  const int64_t ms = cb_index(gm, x);
   const double cf = to_slot ? a : b, cm = to_slot ? b : a;  // coefficients of single, slot
   C<typename PS::R> fv[12];  // spin * 3 + colour
   double fn = 0.0;
   if (cf != 0.0) fn = (double)load_raw<PS>(f, s, fv);
-  const double mn = (cm != 0.0 && PM::has_norm) ? (double)m.norm[s * m.nrhs + r] : 1.0;
+  const double mn = (cm != 0.0 && PM::has_norm) ? (double)m.norm[ms * m.nrhs + r] : 1.0;
   double re[12], im[12];
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
@@ -170,7 +192,7 @@ __global__ void mr_axpby_slot_kernel(Geo g, MField<PM> m, Field<PS> f, int r, do
         im[k] += cf * fn * (double)fv[k].im;
       }
       if (cm != 0.0) {
-        const C<typename PM::R> w = ld<PM>(m.d, mr_idx(s, m.nrhs, r, c * 4 + sp));
+        const C<typename PM::R> w = ld<PM>(m.d, mr_idx(ms, m.nrhs, r, c * 4 + sp));
         re[k] += cm * mn * (double)w.re;
         im[k] += cm * mn * (double)w.im;
       }
@@ -180,7 +202,7 @@ __global__ void mr_axpby_slot_kernel(Geo g, MField<PM> m, Field<PS> f, int r, do
     if constexpr (PM::has_norm) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) mx = fmax(mx, fmax(fabs(re[k]), fabs(im[k])));
-      m.norm[s * m.nrhs + r] = (float)mx;
+      m.norm[ms * m.nrhs + r] = (float)mx;
     }
     const double inv = PM::has_norm ? (mx > 0.0 ? 1.0 / mx : 0.0) : 1.0;
 #pragma unroll
@@ -188,7 +210,7 @@ __global__ void mr_axpby_slot_kernel(Geo g, MField<PM> m, Field<PS> f, int r, do
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int k = sp * 3 + c;
-        st<PM>(m.d, mr_idx(s, m.nrhs, r, c * 4 + sp),
+        st<PM>(m.d, mr_idx(ms, m.nrhs, r, c * 4 + sp),
                C<typename PM::R>{(typename PM::R)(inv * re[k]), (typename PM::R)(inv * im[k])});
       }
   } else {
@@ -434,7 +456,7 @@ int mr_hop_grid(const Geo& g) { return grid_for(g.vh, MR_SITES_PER_BLOCK); }
 
 void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, const void* in,
             const void* x, int nrhs, double* part) {
-  const Geo& g = ctx->geo;
+  const Geo& g = ctx->mr_geo;
   LQ_CHECK(ctx->mr_links_ok && ctx->mr_nbr && (epi == MR_EPI_NONE || ctx->mr_clov_ok),
            LQ_ESTATE, "multi-RHS operator tables not built");
   MField<P16> fo = mfield_at<P16>(out, g.nblk, nrhs);
@@ -471,7 +493,7 @@ void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, 
 
 void mrhs_pack(lq_ctx* ctx, void* dev, const double2* src_dev, int parity, int prec, int nrhs,
                int r) {
-  const Geo& g = ctx->geo;
+  const Geo& g = ctx->mr_geo;  // multi-RHS site numbering
   ctx->bytes += (double)g.vh * (192.0 + spinor_site_bytes(prec));
   if (prec == LQ_F16)
     hipLaunchKernelGGL(mr_pack_kernel<P16>, dim3(grid_for(g.vh, 256)), dim3(256), 0, ctx->cur, g,
@@ -484,7 +506,7 @@ void mrhs_pack(lq_ctx* ctx, void* dev, const double2* src_dev, int parity, int p
 
 void mrhs_unpack(lq_ctx* ctx, double2* dst_dev, const void* dev, int parity, int prec, int nrhs,
                  int r) {
-  const Geo& g = ctx->geo;
+  const Geo& g = ctx->mr_geo;  // multi-RHS site numbering
   ctx->bytes += (double)g.vh * (192.0 + spinor_site_bytes(prec));
   void* d = const_cast<void*>(dev);
   if (prec == LQ_F16)
@@ -497,7 +519,7 @@ void mrhs_unpack(lq_ctx* ctx, double2* dst_dev, const void* dev, int parity, int
 }
 
 void mrhs_tables(lq_ctx* ctx, bool clover) {
-  const Geo& g = ctx->geo;
+  const Geo& g = ctx->mr_geo;
   const int64_t nsite = g.nblk * 64;
   LQ_CHECK(g.vh < ((int64_t)1 << 31), LQ_EINVAL, "lattice too large for the multi-RHS kernels");
   if (!ctx->mr_nbr) {  // depends on the geometry only
@@ -511,7 +533,7 @@ void mrhs_tables(lq_ctx* ctx, bool clover) {
     if (!ctx->mr_links) LQ_HIP(hipMalloc(&ctx->mr_links, (size_t)nsite * 2 * 4 * 9 * 4));
     const int64_t n = nsite * 2 * 4;
     hipLaunchKernelGGL(mr_links_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur, g,
-                       (const double2*)ctx->gauge[LQ_F64], (unsigned*)ctx->mr_links);
+                       ctx->geo, (const double2*)ctx->gauge[LQ_F64], (unsigned*)ctx->mr_links);
     LQ_HIP(hipGetLastError());
     ctx->mr_links_ok = true;
   }
@@ -521,7 +543,7 @@ void mrhs_tables(lq_ctx* ctx, bool clover) {
     for (int p = 0; p < 2; ++p) {
       if (!ctx->mr_clov[p]) LQ_HIP(hipMalloc(&ctx->mr_clov[p], (size_t)nsite * MR_CLOV_SITE * 4));
       hipLaunchKernelGGL(mr_clov_kernel, dim3(grid_for(nsite, 256)), dim3(256), 0, ctx->cur, g,
-                         (const double2*)src[p], (unsigned*)ctx->mr_clov[p]);
+                         ctx->geo, p, (const double2*)src[p], (unsigned*)ctx->mr_clov[p]);
       LQ_HIP(hipGetLastError());
     }
     ctx->mr_clov_ok = true;
@@ -560,7 +582,7 @@ void slot_axpby(lq_ctx* ctx, void* mfield, int nrhs, void* single, int r, double
   ctx->bytes += (double)g.vh * (spinor_site_bytes(PS::id) * (to_slot ? 1 : 2) +
                                 spinor_site_bytes(PM::id) * (to_slot ? 2 : 1));
   hipLaunchKernelGGL((mr_axpby_slot_kernel<PS, PM>), dim3(grid_for(g.vh, 256)), dim3(256), 0,
-                     ctx->cur, g, mfield_at<PM>(mfield, g.nblk, nrhs),
+                     ctx->cur, g, ctx->mr_geo, mfield_at<PM>(mfield, g.nblk, nrhs),
                      field_at<PS>(single, g.nblk), r, a, b, to_slot);
   LQ_HIP(hipGetLastError());
 }
@@ -575,7 +597,7 @@ void mr_reduce(lq_ctx* ctx, MRWork* w, int nrows, Fin fin) {
 }
 
 void mr_launch_iteration(lq_ctx* ctx, MRWork* w) {
-  const Geo& g = ctx->geo;
+  const Geo& g = ctx->mr_geo;  // multi-RHS site numbering
   const int n = w->nrhs;
   const int* act = &w->st->active;
   mr_hop(ctx, LQ_ODD, 0, MR_EPI_CLOVINV, act, w->t, w->p, nullptr, n, nullptr);
