@@ -41,3 +41,46 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(lq, "_lib", None)
     with pytest.raises(ImportError):
         lq.lib()
+
+
+def _lib():
+    from paper_1103_1363_amd import lq
+    if not os.path.exists(lq.LIB_PATH):
+        pytest.fail("liblq.so is not built (run python -m paper_1103_1363_amd.build)")
+    lib = ctypes.CDLL(lq.LIB_PATH)
+    lib.lq_create.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_void_p,
+                              ctypes.POINTER(ctypes.c_void_p)]
+    lib.lq_create.restype = ctypes.c_int
+    lib.lq_last_error.argtypes = [ctypes.c_void_p]
+    lib.lq_last_error.restype = ctypes.c_char_p
+    lib.lq_ensemble_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+    lib.lq_ensemble_create.restype = ctypes.c_int
+    lib.lq_ensemble_last_error.argtypes = [ctypes.c_void_p]
+    lib.lq_ensemble_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+@pytest.mark.parametrize("dims,msg", [((3, 4, 4, 4), b"even"), ((4, 4, 4, 0), b"even"),
+                                      ((4, 1, 4, 4), b"even"),
+                                      ((64, 64, 64, 256), b"too large")])
+def test_create_rejects_bad_lattices_before_any_device_call(dims, msg):
+    """Odd or vanishing extents and lattices beyond the reduction scratch
+    (more than 65536 x 256 sites of one parity) are refused on the host."""
+    lib = _lib()
+    out = ctypes.c_void_p(123)
+    rc = lib.lq_create((ctypes.c_int * 4)(*dims), 1, None, ctypes.byref(out))
+    assert rc == -1  # LQ_EINVAL
+    assert msg in lib.lq_last_error(None)
+
+
+def test_ensemble_create_rejects_bad_arguments_on_the_host():
+    lib = _lib()
+    out = ctypes.c_void_p(123)
+    assert lib.lq_ensemble_create(None, 0, ctypes.byref(out)) == -1
+    assert out.value is None
+    assert b"member" in lib.lq_ensemble_last_error(None)
+    members = (ctypes.c_void_p * 2)(None, None)
+    assert lib.lq_ensemble_create(members, 2, ctypes.byref(out)) == -1
+    assert lib.lq_ensemble_create(members, 65, ctypes.byref(out)) == -1
+    assert lib.lq_ensemble_create(members, 2, None) == -1
