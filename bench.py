@@ -357,9 +357,8 @@ def main():
     ap.add_argument("--net-epochs", type=int, default=8)
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): this build has no "
-              "multi-GPU path; how the solve would shard is described in DESIGN.md",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if world != 1:
