@@ -9,7 +9,7 @@ import scipy.sparse.linalg as spla
 from gen import fields
 from oracle import dirac, evenodd
 from tests import bruteforce
-from tests.gpu_common import say
+from tests.gpu_common import case, residual_at, say
 
 pytestmark = pytest.mark.gpu
 
@@ -178,3 +178,72 @@ def test_bicgstab_fault_injection_falls_back(lq):
                        raise_on_noconv=False)
     assert rep[0].fallback == 1
     assert oracle_residual(u, kappa, csw, x, b) <= 1e-10
+
+
+def sampled_residuals(u, kappa, csw, x, b, extra_sites, n_random, seed):
+    """Norms of the oracle's single-site residual (b - M x)(site) at the given
+    sites, the lattice corners and n_random random sites."""
+    lt, lz, ly, lx = u.shape[:4]
+    rng = fields.rng(seed)
+    sites = [(0, 0, 0, 0), (lx - 1, ly - 1, lz - 1, lt - 1), (0, 0, 0, lt - 1)] + list(extra_sites)
+    sites += [(int(rng.integers(lx)), int(rng.integers(ly)), int(rng.integers(lz)),
+               int(rng.integers(lt))) for _ in range(n_random)]
+    return [float(np.linalg.norm(residual_at(u, kappa, csw, x, b, s))) for s in sites]
+
+
+def test_full_size_mixed_solve(lq):
+    """The benchmark's step at its full size: 32^3x64, kappa 0.135, csw 1,
+    smooth links, Gaussian source, FP16 inner iteration with FP64 reliable
+    updates.  No site may carry more than the whole residual allows
+    (|r(x)| <= tol |b|), by the oracle's own operator at sampled sites; the
+    solution agrees with the plain FP64 solve within the conditioning bound."""
+    dims, kappa, csw, tol = (32, 32, 32, 64), 0.135, 1.0, 1e-10
+    say("full-size mixed solve 32^3x64")
+    u, b, _, _ = case(dims, "smooth", 2)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    db = lat.to_device(b, lq.FULL, lq.F64)
+    dx = lat.new_field(lq.FULL, lq.F64)
+    rep = lat.solve_device(dx, db, kappa, csw, tol, inner_prec=lq.F16)[0]
+    say(f"  {rep.iterations} iterations, {rep.reliable_updates} updates, "
+        f"residual {rep.true_residual:.2e}")
+    assert rep.true_residual <= tol and rep.fallback == 0
+    x = lat.to_host(dx, lq.FULL, lq.F64).reshape(b.shape)
+    bound = tol * dirac.norm(b)
+    rs = sampled_residuals(u, kappa, csw, x, b, [], 24, 301)
+    say(f"  largest sampled site residual {max(rs):.2e} (bound {bound:.2e})")
+    assert max(rs) <= 1.01 * bound
+    dx64 = lat.new_field(lq.FULL, lq.F64)
+    lat.solve_device(dx64, db, kappa, csw, 1e-12, inner_prec=lq.F64)
+    x64 = lat.to_host(dx64, lq.FULL, lq.F64).reshape(b.shape)
+    err = dirac.norm(x - x64) / dirac.norm(x64)
+    say(f"  relative difference to the plain FP64 solution {err:.2e}")
+    assert err <= 1e3 * tol
+
+
+def test_full_size_batched_point_sources(lq):
+    """The 12 spin-colour point sources at 32^3x64 through the 12-RHS
+    operator: every RHS reaches the tolerance, and at the origin, its eight
+    neighbours and random sites the oracle's residual of each RHS stays
+    within the bound the whole residual sets (|b_r| = 1)."""
+    dims, kappa, csw, tol = (32, 32, 32, 64), 0.135, 1.0, 1e-10
+    say("full-size batched point sources 32^3x64")
+    u, _, _, _ = case(dims, "smooth", 2)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    b = fields.point_sources_12(dims)
+    x, reps = lat.solve(b, kappa, csw, tol, inner_prec=lq.F16, batched=1)
+    say(f"  {reps[0].iterations} iterations, max residual "
+        f"{max(r.true_residual for r in reps):.2e}")
+    assert max(r.true_residual for r in reps) <= tol
+    assert all(r.fallback == 0 for r in reps)
+    lx, ly, lz, lt = dims
+    near = [(1, 0, 0, 0), (lx - 1, 0, 0, 0), (0, 1, 0, 0), (0, ly - 1, 0, 0), (0, 0, 1, 0),
+            (0, 0, lz - 1, 0), (0, 0, 0, 1)]
+    worst = 0.0
+    for r in range(12):
+        rs = sampled_residuals(u, kappa, csw, x[r].reshape(b[r].shape), b[r], near, 4, 400 + r)
+        worst = max(worst, max(rs))
+    say(f"  largest sampled site residual {worst:.2e} (bound {tol:.2e})")
+    assert worst <= 1.01 * tol
+
