@@ -111,6 +111,37 @@ def test_dropout_zero_source_and_reuse(lq):
     ens.close()
 
 
+def test_mixed_boundaries_and_extent_two(lq):
+    """Members differ in their time boundary (one periodic) and include an
+    extent-2 direction (both hops of that direction land on one site and
+    add); each is checked against the oracle with its own boundary."""
+    tol, csw = 1e-10, 1.0
+    say("uneven batch: periodic member and extent-2 member")
+    spec = [((4, 4, 4, 4), 0.12, False), ((6, 2, 2, 2), 0.11, True), ((8, 4, 4, 8), 0.125, True)]
+    lats, us, bs, db, dx = [], [], [], [], []
+    for j, (dims, kappa, apt) in enumerate(spec):
+        u = fields.gauge_field(dims, "haar" if j == 1 else "smooth", fields.SEED_GAUGE + 50 + j)
+        lat = lq.Lattice(dims, antiperiodic_t=apt)
+        lat.upload_gauge(u)
+        lat.set_clover(kappa, csw)
+        b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 50 + j)
+        lats.append(lat)
+        us.append(u)
+        bs.append(b)
+        db.append(lat.to_device(b, lq.FULL, lq.F64))
+        dx.append(lat.new_field(lq.FULL, lq.F64))
+    ens = lq.Ensemble(lats)
+    kap = [k for _, k, _ in spec]
+    reps, er = ens.solve_device(dx, db, kap, [csw] * 3, tol, inner_prec=lq.F16)
+    say(f"  {er} iters={[r.iterations for r in reps]}")
+    for j, (dims, kappa, apt) in enumerate(spec):
+        x = lats[j].to_host(dx[j], lq.FULL, lq.F64).reshape(bs[j].shape)
+        wc = evenodd.WilsonClover(us[j], kappa, csw, antiperiodic_t=apt)
+        res = dirac.norm(bs[j] - wc.M(x)) / dirac.norm(bs[j])
+        assert res <= tol, (j, res)
+    ens.close()
+
+
 def test_without_graph_same_result(lq):
     """use_graph = -1 launches the same kernels one by one: the same
     iteration counts and residuals within the tolerance."""
