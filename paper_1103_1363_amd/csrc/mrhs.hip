@@ -318,89 +318,9 @@ __global__ __launch_bounds__(256) void mr_finalize_kernel(const double* __restri
   if (threadIdx.x == 0) fin(tot);
 }
 
-// The batched vector kernels: threadIdx.x = RHS (16 lanes), threadIdx.y =
+// The batched vector kernel: threadIdx.x = RHS (16 lanes), threadIdx.y =
 // site (16 per step), grid-stride over sites.  Per (site, RHS) the 12
 // complex of an FP32 field are six 16-byte words, of an FP16 field three.
-// (the word is taken by value and split with shifts: element access through
-// a reference to a vector in global memory read only its first element here)
-__device__ __forceinline__ void mr_h2f(const mr_u4 w, float f[8]) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const unsigned u = w[k];
-    f[2 * k] = (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xffffu));
-    f[2 * k + 1] = (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
-  }
-}
-
-// x_r += alpha_r p_r;  r_r -= alpha_r s_r;  per-block partial |r_r|^2.
-// Every operand of a (site, RHS) is loaded before the first store: the
-// fields are distinct, but the compiler cannot know it, and interleaved
-// loads and stores would leave one load pair in flight per thread.
-__global__ __launch_bounds__(256) void mr_cg_update(Geo g, const MRState* __restrict__ mst,
-                                                    MField<P32> x, MField<P32> rv, MField<P16> p,
-                                                    MField<P16> sv, double* __restrict__ part) {
-  __shared__ double red[4][MR_MAX];
-  const int r = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int nrhs = x.nrhs;
-  double acc = 0.0;
-  if (mst->active && r < nrhs) {
-    const float al = (float)mst->alpha[r];
-    for (int64_t s = (int64_t)blockIdx.x * 16 + ty; s < g.vh; s += (int64_t)gridDim.x * 16) {
-      const int64_t i0 = mr_idx(s, nrhs, r, 0);
-      const float ap = al * p.norm[s * nrhs + r], as = al * sv.norm[s * nrhs + r];
-      float4* xp = reinterpret_cast<float4*>(x.d + i0);
-      float4* rp = reinterpret_cast<float4*>(rv.d + i0);
-      const mr_u4* pp = reinterpret_cast<const mr_u4*>(p.d + i0);
-      const mr_u4* sp = reinterpret_cast<const mr_u4*>(sv.d + i0);
-      float4 xv[6], rr[6];
-      mr_u4 pw[3], sw[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        pw[k] = pp[k];
-        sw[k] = sp[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        xv[k] = xp[k];
-        rr[k] = rp[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        float pf[8], sf[8];
-        mr_h2f(pw[k], pf);
-        mr_h2f(sw[k], sf);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          float4& xo = xv[2 * k + h];
-          float4& ro = rr[2 * k + h];
-          xo.x += ap * pf[4 * h];
-          xo.y += ap * pf[4 * h + 1];
-          xo.z += ap * pf[4 * h + 2];
-          xo.w += ap * pf[4 * h + 3];
-          ro.x -= as * sf[4 * h];
-          ro.y -= as * sf[4 * h + 1];
-          ro.z -= as * sf[4 * h + 2];
-          ro.w -= as * sf[4 * h + 3];
-          acc += (double)ro.x * ro.x + (double)ro.y * ro.y + (double)ro.z * ro.z +
-                 (double)ro.w * ro.w;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        xp[k] = xv[k];
-        rp[k] = rr[k];
-      }
-    }
-  }
-  // column r of this workgroup: lanes of equal r are 16 apart in the block
-  acc += __shfl_xor(acc, 16, 64);
-  acc += __shfl_xor(acc, 32, 64);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) < 16) red[w][r] = acc;
-  __syncthreads();
-  if (threadIdx.x < 16) part[blockIdx.x * MR_MAX + r] = red[0][r] + red[1][r] + red[2][r] + red[3][r];
-}
-
 // p_r = r_r + beta_r p_r, stored in FP16 with a new per-(site, RHS) scale.
 __global__ __launch_bounds__(256) void mr_p_update(Geo g, const MRState* __restrict__ mst,
                                                    MField<P16> p, MField<P32> rv) {
@@ -455,7 +375,7 @@ namespace {
 int mr_hop_grid(const Geo& g) { return grid_for(g.vh, MR_SITES_PER_BLOCK); }
 
 void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, const void* in,
-            const void* x, int nrhs, double* part) {
+            const void* x, int nrhs, double* part, MRUpd upd = MRUpd{}) {
   const Geo& g = ctx->mr_geo;
   LQ_CHECK(ctx->mr_links_ok && ctx->mr_nbr && (epi == MR_EPI_NONE || ctx->mr_clov_ok),
            LQ_ESTATE, "multi-RHS operator tables not built");
@@ -471,12 +391,18 @@ void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, 
   // algorithmic bytes: 8 links (12 reals), in and out per RHS, clover table, x per RHS
   double sb = 8 * link_site_bytes(LQ_F16) + 2.0 * nrhs * spinor_site_bytes(LQ_F16);
   if (epi != MR_EPI_NONE) sb += clover_site_bytes(LQ_F16);
-  if (epi == MR_EPI_SCHUR2) sb += nrhs * spinor_site_bytes(LQ_F16);
+  if (epi == MR_EPI_SCHUR2 || epi == MR_EPI_UPDATE) sb += nrhs * spinor_site_bytes(LQ_F16);
+  if (epi == MR_EPI_UPDATE)  // no output; x, r read and written, p read
+    sb += nrhs * (4 * spinor_site_bytes(LQ_F32) - spinor_site_bytes(LQ_F16)) +
+          nrhs * spinor_site_bytes(LQ_F16);
   ctx->bytes += sb * (double)g.vh;
 #define LQ_MR_LAUNCH(D, E)                                                                    \
   hipLaunchKernelGGL((mrhs_hop_kernel<D, E>), grid, blk, 0, ctx->cur, g, p, active, fo, fi, fx, \
-                     lk, cl, nb, k2, part)
-  if (dag) {
+                     lk, cl, nb, k2, part, upd)
+  if (epi == MR_EPI_UPDATE) {
+    LQ_CHECK(dag && upd.st, LQ_EINVAL, "the fused update follows the adjoint Schur sweep");
+    LQ_MR_LAUNCH(true, MR_EPI_UPDATE);
+  } else if (dag) {
     if (epi == MR_EPI_NONE) LQ_MR_LAUNCH(true, MR_EPI_NONE);
     else if (epi == MR_EPI_CLOVINV) LQ_MR_LAUNCH(true, MR_EPI_CLOVINV);
     else LQ_MR_LAUNCH(true, MR_EPI_SCHUR2);
@@ -604,11 +530,11 @@ void mr_launch_iteration(lq_ctx* ctx, MRWork* w) {
   mr_hop(ctx, LQ_EVEN, 0, MR_EPI_SCHUR2, act, w->q, w->t, w->p, n, w->part);
   mr_reduce(ctx, w, mr_hop_grid(g), MRFinAlpha{w->st});
   mr_hop(ctx, LQ_ODD, 1, MR_EPI_CLOVINV, act, w->t, w->q, nullptr, n, nullptr);
-  mr_hop(ctx, LQ_EVEN, 1, MR_EPI_SCHUR2, act, w->s, w->t, w->q, n, nullptr);
-  hipLaunchKernelGGL(mr_cg_update, dim3(MR_UPD_BLOCKS), dim3(256), 0, ctx->cur, g, w->st,
-                     mfield_at<P32>(w->x, g.nblk, n), mfield_at<P32>(w->r, g.nblk, n),
-                     mfield_at<P16>(w->p, g.nblk, n), mfield_at<P16>(w->s, g.nblk, n), w->part);
-  mr_reduce(ctx, w, MR_UPD_BLOCKS, MRFinBeta{w->st});
+  // s = Mhat^+ q, used at once: x += alpha p, r -= alpha s, partial |r|^2
+  const MRUpd upd{mfield_at<P32>(w->x, g.nblk, n), mfield_at<P32>(w->r, g.nblk, n),
+                  mfield_at<P16>(w->p, g.nblk, n), w->st};
+  mr_hop(ctx, LQ_EVEN, 1, MR_EPI_UPDATE, act, w->q, w->t, w->q, n, w->part, upd);
+  mr_reduce(ctx, w, mr_hop_grid(g), MRFinBeta{w->st});
   hipLaunchKernelGGL(mr_p_update, dim3(MR_UPD_BLOCKS), dim3(256), 0, ctx->cur, g, w->st,
                      mfield_at<P16>(w->p, g.nblk, n), mfield_at<P32>(w->r, g.nblk, n));
   LQ_HIP(hipGetLastError());
@@ -629,7 +555,7 @@ MRWork* mrhs_work(lq_ctx* ctx, int nrhs) {
     w->nblk = ctx->geo.nblk;
     const size_t f16 = mrhs_field_bytes(w->nblk, LQ_F16, nrhs);
     const size_t f32 = mrhs_field_bytes(w->nblk, LQ_F32, nrhs);
-    for (void** pp : {&w->p, &w->q, &w->t, &w->s}) LQ_HIP(hipMalloc(pp, f16));
+    for (void** pp : {&w->p, &w->q, &w->t}) LQ_HIP(hipMalloc(pp, f16));
     for (void** pp : {&w->x, &w->r}) LQ_HIP(hipMalloc(pp, f32));
     const size_t nparts = (size_t)std::max(grid_for(ctx->geo.vh, MR_SITES_PER_BLOCK),
                                            MR_UPD_BLOCKS);
@@ -656,7 +582,7 @@ MRWork* mrhs_work(lq_ctx* ctx, int nrhs) {
 void free_mrhs_work(lq_ctx* ctx) {
   MRWork* w = ctx->mrwork;
   if (!w) return;
-  for (void* p : {w->p, w->q, w->t, w->s, w->x, w->r})
+  for (void* p : {w->p, w->q, w->t, w->x, w->r})
     if (p) (void)hipFree(p);
   if (w->part) (void)hipFree(w->part);
   if (w->part2) (void)hipFree(w->part2);
@@ -715,8 +641,10 @@ double mrhs_iteration_site_bytes(int nrhs) {
   const double L = link_site_bytes(LQ_F16), S = spinor_site_bytes(LQ_F16),
                C = clover_site_bytes(LQ_F16), S32 = spinor_site_bytes(LQ_F32);
   const double hop = 8 * L + 2.0 * nrhs * S + C;
-  return 2 * hop + 2 * (hop + nrhs * S)          // two A^-1 H, two A x - k2 H t
-         + nrhs * (4 * S32 + 2 * S)               // x, r read/write, p, s read
+  return 2 * hop                                  // two A^-1 H
+         + (hop + nrhs * S)                       // A p - k2 H t (p read beside t)
+         + (hop + nrhs * (4 * S32 + S))           // A q - k2 H^+ t, no output, fused with
+                                                  // x += alpha p, r -= alpha s
          + nrhs * (S32 + 2 * S);                  // p = r + beta p
 }
 

@@ -245,7 +245,7 @@ struct MRState {
 struct MRWork {
   int nrhs = 0;
   int64_t nblk = 0;
-  void *p = nullptr, *q = nullptr, *t = nullptr, *s = nullptr;  // FP16 multi-RHS
+  void *p = nullptr, *q = nullptr, *t = nullptr;  // FP16 multi-RHS
   void *x = nullptr, *r = nullptr;                              // FP32 multi-RHS
   double* part = nullptr;   // per-block partials [blocks][MR_MAX]
   double* part2 = nullptr;  // first reduction stage [MR_ROWS2][MR_MAX]
@@ -259,7 +259,28 @@ struct MRWork {
 };
 
 
-enum { MR_EPI_NONE = 0, MR_EPI_CLOVINV = 1, MR_EPI_SCHUR2 = 2 };
+enum { MR_EPI_NONE = 0, MR_EPI_CLOVINV = 1, MR_EPI_SCHUR2 = 2, MR_EPI_UPDATE = 3 };
+
+// Operands of the CG update fused into the second Schur sweep
+// (MR_EPI_UPDATE): x_r += alpha_r p_r and r_r -= alpha_r s_r with s the
+// sweep's result, which is never stored.
+struct MRUpd {
+  MField<P32> x, r;
+  MField<P16> p;
+  const MRState* st;
+};
+
+// Eight halves (16 bytes) to floats.  The word is taken by value and split
+// with shifts (element access through a reference to a vector in global
+// memory read only its first element).
+__device__ __forceinline__ void mr_h2f(const mr_u4 w, float f[8]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const unsigned u = w[k];
+    f[2 * k] = (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xffffu));
+    f[2 * k + 1] = (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
+  }
+}
 constexpr int MR_BLK = 256;
 #ifndef LQ_MR_SITES_PER_BLOCK
 #define LQ_MR_SITES_PER_BLOCK 32
@@ -268,13 +289,17 @@ constexpr int MR_SITES_PER_BLOCK = LQ_MR_SITES_PER_BLOCK;  // 4 waves, each ever
 
 // out = H in (EPI_NONE), A^-1 H in (EPI_CLOVINV) or A x - k2 H in
 // (EPI_SCHUR2, with per-workgroup partial |out|^2 per RHS in part[block][r]),
-// for the sites of parity p of all right-hand sides.  `active`: skip when 0.
-// links / clov: the FP16 site-major copies (clov: the table of parity p).
+// for the sites of parity p of all right-hand sides.  EPI_UPDATE forms
+// s = A x - k2 H in like EPI_SCHUR2 but, instead of storing it, applies the
+// CG update of `upd` and writes the partial |r_new|^2 per RHS.
+// `active`: skip when 0.  links / clov: the FP16 site-major copies (clov:
+// the table of parity p).
 template <bool DAG, int EPI>
 __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
     Geo g, int p, const int* __restrict__ active, MField<P16> out, MField<P16> in,
     MField<P16> x, const unsigned* __restrict__ links, const unsigned* __restrict__ clov,
-    const int* __restrict__ nbr, float k2, double* __restrict__ part) {
+    const int* __restrict__ nbr, float k2, double* __restrict__ part, MRUpd upd) {
+  constexpr bool AXPY = EPI == MR_EPI_SCHUR2 || EPI == MR_EPI_UPDATE;  // A x - k2 H in
   __shared__ double red[4][MR_MAX];
   if (active && !*active) return;
   const int lane = threadIdx.x & 63;
@@ -349,7 +374,7 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
     // the x block
     mr_u4 xv = {0u, 0u, 0u, 0u};
     float xn = 0.f;
-    if constexpr (EPI == MR_EPI_SCHUR2) {
+    if constexpr (AXPY) {
       xv = mr_ld<mr_u4>(reinterpret_cast<const unsigned*>(x.d) + s * sblk, bofs);
       xn = mr_ld<float>(x.norm + s * nrhs, 4u * (unsigned)lic);
     }
@@ -411,7 +436,7 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
       for (int k = 0; k < 8; ++k) y[k] = acc[k];
     } else {
       mr_u2 xb[2];
-      if constexpr (EPI == MR_EPI_SCHUR2) {
+      if constexpr (AXPY) {
         xb[0] = mr_u2{xv[0], xv[1]};
         xb[1] = mr_u2{xv[2], xv[3]};
       } else {
@@ -427,12 +452,51 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
         const mr_float4 d = mr_clover(ce[cb], q, xb[cb]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          if constexpr (EPI == MR_EPI_SCHUR2)
+          if constexpr (AXPY)
             y[4 * cb + j] = xn * d[j] - k2 * acc[4 * cb + j];
           else
             y[4 * cb + j] = colmax * d[j];
         }
       }
+    }
+    if constexpr (EPI == MR_EPI_UPDATE) {
+      // x += alpha p, r -= alpha s for the lane's colour and RHS: 8 floats
+      // of x and r, 8 halves of p, all contiguous
+      if (bl) {
+        const int64_t e0 = (s * nrhs + li) * 12 + grp * 4;  // complex index
+        float4* xp = reinterpret_cast<float4*>(upd.x.d + e0);
+        float4* rp = reinterpret_cast<float4*>(upd.r.d + e0);
+        const mr_u4 pw = *reinterpret_cast<const mr_u4*>(upd.p.d + e0);
+        const float al = (float)upd.st->alpha[li];
+        const float ap = al * upd.p.norm[s * nrhs + li];
+        float4 x0 = xp[0], x1 = xp[1], r0 = rp[0], r1 = rp[1];
+        float pf[8];
+        mr_h2f(pw, pf);
+        x0.x += ap * pf[0];
+        x0.y += ap * pf[1];
+        x0.z += ap * pf[2];
+        x0.w += ap * pf[3];
+        x1.x += ap * pf[4];
+        x1.y += ap * pf[5];
+        x1.z += ap * pf[6];
+        x1.w += ap * pf[7];
+        r0.x -= al * y[0];
+        r0.y -= al * y[1];
+        r0.z -= al * y[2];
+        r0.w -= al * y[3];
+        r1.x -= al * y[4];
+        r1.y -= al * y[5];
+        r1.z -= al * y[6];
+        r1.w -= al * y[7];
+        xp[0] = x0;
+        xp[1] = x1;
+        rp[0] = r0;
+        rp[1] = r1;
+        nsum += (double)r0.x * r0.x + (double)r0.y * r0.y + (double)r0.z * r0.z +
+                (double)r0.w * r0.w + (double)r1.x * r1.x + (double)r1.y * r1.y +
+                (double)r1.z * r1.z + (double)r1.w * r1.w;
+      }
+      continue;
     }
     float mx = 0.f;
 #pragma unroll
@@ -455,7 +519,7 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
       }
     }
   }
-  if (EPI == MR_EPI_SCHUR2 && part) {
+  if (AXPY && part) {
     // per-RHS totals: the three colour lanes of a column, then the four waves
     nsum += __shfl_xor(nsum, 16, 64);
     nsum += __shfl_xor(nsum, 32, 64);
