@@ -50,6 +50,7 @@ struct Net {
   void* act = nullptr;      // (L + 1) full FP32 fields
   void* gbuf[2] = {nullptr, nullptr};
   void* fbuf[2] = {nullptr, nullptr};  // FP16 full fields of the fast path (lazy)
+  unsigned* wh = nullptr;   // the applied weight set as FP16 pairs [L][9][16][2]
   int64_t step = 0;
   bool adj_ok = false;
 };
@@ -61,6 +62,17 @@ char* half32(void* full, const lq_ctx* ctx, int p) {
   return reinterpret_cast<char*>(full) + (p ? parity_field_bytes(ctx->geo.nblk, LQ_F32) : 0);
 }
 
+// z += a b and z += conj(a) b as four multiply-adds (the operators on C
+// round each product before the sum)
+__device__ __forceinline__ void cmac(C<float>& z, C<float> a, C<float> b) {
+  z.re = fmaf(a.re, b.re, fmaf(-a.im, b.im, z.re));
+  z.im = fmaf(a.re, b.im, fmaf(a.im, b.re, z.im));
+}
+__device__ __forceinline__ void cmac_conj(C<float>& z, C<float> a, C<float> b) {
+  z.re = fmaf(a.re, b.re, fmaf(a.im, b.im, z.re));
+  z.im = fmaf(a.re, b.im, fmaf(-a.im, b.re, z.im));
+}
+
 // acc[s][a] += c * sum_t W[s][t] v[t][a]  (component index spin * 3 + colour)
 __device__ __forceinline__ void spin_mix_add(const C<float>* __restrict__ W, const C<float> v[12],
                                              float c, C<float> acc[12]) {
@@ -70,7 +82,7 @@ __device__ __forceinline__ void spin_mix_add(const C<float>* __restrict__ W, con
     for (int t = 0; t < 4; ++t) {
       const C<float> wst = c * W[s * 4 + t];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) acc[s * 3 + a] = acc[s * 3 + a] + wst * v[t * 3 + a];
+      for (int a = 0; a < 3; ++a) cmac(acc[s * 3 + a], wst, v[t * 3 + a]);
     }
 }
 
@@ -105,8 +117,12 @@ __device__ __forceinline__ void transport(const Geo& g, const Field<PI>& other,
     for (int a = 0; a < 3; ++a) {
       C<float> z = {0.f, 0.f};
 #pragma unroll
-      for (int b = 0; b < 3; ++b)
-        z = z + (BACK ? cmul_conj(u[3 * b + a], v[t * 3 + b]) : u[3 * a + b] * v[t * 3 + b]);
+      for (int b = 0; b < 3; ++b) {
+        if constexpr (BACK)
+          cmac_conj(z, u[3 * b + a], v[t * 3 + b]);
+        else
+          cmac(z, u[3 * a + b], v[t * 3 + b]);
+      }
       w[t * 3 + a] = sign * z;
     }
 }
@@ -160,6 +176,242 @@ __global__ __launch_bounds__(NET_BLK) void net_layer_kernel(Geo g, int p, Field<
     layer_hop<3, true, PO, PL>(g, other, gauge, p, s, l, tc, x3, ws, acc);
   }
   store_spinor<POUT>(out, s, acc);
+}
+
+// ---------------------------------------------------------------- FP16 form
+// The solvers' form of a layer multiplies FP16 operands: every complex
+// product a b is two v_dot2_f32_f16 (two half products summed into an FP32
+// accumulator), with a written as the half pairs (re, -im) and (im, re).
+// The neighbour spinor (raw FP16 components without its site scale) is
+// carried by the FP16 link, the result rounded to FP16 pairs, mixed over
+// spin by the layer's weights (FP16 pairs, read as wave-uniform scalars)
+// and added to the FP32 output with the neighbour's scale.  Per hop that is
+// 72 + 96 dot products instead of 336 FP32 multiply-adds.
+typedef _Float16 nh2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float dot2(unsigned a, unsigned b, float c) {
+  return __builtin_amdgcn_fdot2(__builtin_bit_cast(nh2, a), __builtin_bit_cast(nh2, b), c, false);
+}
+// a.x b.x + a.y b.y alone: the three-operand form with an inline zero (the
+// builtin's two-operand form would first copy a zero into the accumulator)
+__device__ __forceinline__ float dot2_first(unsigned a, unsigned b) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+// the same with a wave-uniform a (a scalar register)
+__device__ __forceinline__ float dot2_first_u(unsigned a, unsigned b) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "s"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ unsigned pack_h(float re, float im) {
+  return __builtin_bit_cast(unsigned, nh2{(_Float16)re, (_Float16)im});
+}
+__device__ __forceinline__ C<float> unpack_h(unsigned u) {
+  const nh2 h = __builtin_bit_cast(nh2, u);
+  return {(float)h.x, (float)h.y};
+}
+__device__ __forceinline__ unsigned swap_h(unsigned u) { return (u >> 16) | (u << 16); }
+
+// Indices in the FP16 form are 32-bit: a parity of the lattices the library
+// accepts has at most 2^24 sites, so the largest element index (a link
+// entry) stays below 2^30.
+__device__ __forceinline__ unsigned spin_base(unsigned s) { return (s >> 6) * 768u + (s & 63u); }
+// element i of an array of T at base, with a 32-bit byte offset (so that the
+// load takes the base from scalar registers and only the offset per lane)
+template <class T>
+__device__ __forceinline__ const T& at32(const T* base, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ T& at32(T* base, unsigned i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T));
+}
+
+// The 12 components of site s as FP16 pairs scaled to a largest component
+// of 1, and that scale (FP16 fields store exactly this; an FP32 field is
+// rounded the same way).
+template <class P>
+__device__ __forceinline__ float load_h(const Field<P>& f, unsigned s, unsigned v[12]) {
+  const unsigned b = spin_base(s);
+  if constexpr (P::has_norm) {
+    const unsigned* d = reinterpret_cast<const unsigned*>(f.d);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = at32(d, b + 64u * c);
+    return at32(f.norm, s);
+  } else {
+    C<float> x[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 q = at32(f.d, b + 64u * c);
+      x[c] = C<float>{q.x, q.y};
+    }
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(x[c].re), fabsf(x[c].im)));
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = pack_h(inv * x[c].re, inv * x[c].im);
+    return m;
+  }
+}
+
+// Store the 12 components of site s (FP16: scaled to a largest component of
+// 1, with the scale), as store_spinor with 32-bit indices.
+template <class P>
+__device__ __forceinline__ void store_h(const Field<P>& f, unsigned s, const C<float> v[12]) {
+  const unsigned b = spin_base(s);
+  if constexpr (P::has_norm) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    at32(f.norm, s) = m;
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+    unsigned* d = reinterpret_cast<unsigned*>(f.d);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) at32(d, b + 64u * c) = pack_h(inv * v[c].re, inv * v[c].im);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) at32(f.d, b + 64u * c) = make_float2(v[c].re, v[c].im);
+  }
+}
+
+// acc[s][a] += c sum_t W[s][t] v[t][a], with v as FP16 pairs (re, im) and
+// the hop's weights as pairs F[2 (4 s + t)] = (re, -im), F[2 (4 s + t) + 1] = (im, re).
+__device__ __forceinline__ void mix_h(const unsigned* __restrict__ F, const unsigned v[12], float c,
+                                      C<float> acc[12]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float yr = dot2_first_u(F[8 * s], v[a]);
+      float yi = dot2_first_u(F[8 * s + 1], v[a]);
+#pragma unroll
+      for (int t = 1; t < 4; ++t) {
+        yr = dot2(F[2 * (4 * s + t)], v[3 * t + a], yr);
+        yi = dot2(F[2 * (4 * s + t) + 1], v[3 * t + a], yi);
+      }
+      acc[3 * s + a].re = fmaf(c, yr, acc[3 * s + a].re);
+      acc[3 * s + a].im = fmaf(c, yi, acc[3 * s + a].im);
+    }
+}
+
+// The hop (MU, BACK) of site s: the neighbour's raw spinor carried by the
+// FP16 link (U, or U^+ backwards) as FP16 pairs w, and the neighbour's scale
+// times the boundary phase.
+template <int MU, bool BACK, class PI>
+__device__ __forceinline__ float transport_h(const Geo& g, const Field<PI>& other,
+                                             const unsigned* __restrict__ gauge, int p, unsigned s,
+                                             const int l[4], const int tc[4], int x3,
+                                             unsigned w[12]) {
+  float sign = 1.f;
+  if constexpr (MU == 3) {
+    if (g.apt && x3 == (BACK ? 0 : g.L[3] - 1)) sign = -1.f;
+  }
+  int y[4] = {tc[0] * g.T[0] + l[0], tc[1] * g.T[1] + l[1], tc[2] * g.T[2] + l[2], x3};
+  if constexpr (!BACK)
+    y[MU] = (y[MU] + 1 == g.L[MU]) ? 0 : y[MU] + 1;
+  else
+    y[MU] = (y[MU] == 0) ? g.L[MU] - 1 : y[MU] - 1;
+  const unsigned sy = (unsigned)cb_index(g, y);
+  unsigned v[12];
+  const float scale = sign * load_h<PI>(other, sy, v);
+  // link entry c of (parity, MU, site ls): ((parity * 4 + MU) nblk + ls / 64) 384 + 64 c + ls % 64
+  const unsigned ls = BACK ? sy : s;
+  const unsigned lb = (unsigned)(((BACK ? 1 - p : p) * 4 + MU) * (int)g.nblk) * 384u +
+                      (ls >> 6) * 384u + (ls & 63u);
+  unsigned u[9];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) u[c] = __builtin_nontemporal_load(&at32(gauge, lb + 64u * c));
+  {  // row 2 = conj(row 0 x row 1)
+    C<float> r[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) r[c] = unpack_h(u[c]);
+    const C<float> z6 = conj(r[1] * r[5] - r[2] * r[4]);
+    const C<float> z7 = conj(r[2] * r[3] - r[0] * r[5]);
+    const C<float> z8 = conj(r[0] * r[4] - r[1] * r[3]);
+    u[6] = pack_h(z6.re, z6.im);
+    u[7] = pack_h(z7.re, z7.im);
+    u[8] = pack_h(z8.re, z8.im);
+  }
+  // forward: (U v)_a = sum_b u[a][b] v_b: re with (u.re, -u.im), im with (u.im, u.re)
+  // backward: (U^+ v)_a = sum_b conj(u[b][a]) v_b: re with (u.re, u.im), im with (-u.im, u.re)
+  unsigned fr[9], fi[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    fr[c] = BACK ? u[c] : (u[c] ^ 0x80000000u);
+    fi[c] = BACK ? (swap_h(u[c]) ^ 0x00008000u) : swap_h(u[c]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int e0 = BACK ? a : 3 * a;
+      float zr = dot2_first(fr[e0], v[3 * t]);
+      float zi = dot2_first(fi[e0], v[3 * t]);
+#pragma unroll
+      for (int b = 1; b < 3; ++b) {
+        const int e = BACK ? 3 * b + a : 3 * a + b;
+        zr = dot2(fr[e], v[3 * t + b], zr);
+        zi = dot2(fi[e], v[3 * t + b], zi);
+      }
+      w[3 * t + a] = pack_h(zr, zi);
+    }
+  return scale;
+}
+
+template <int MU, bool BACK, class PO>
+__device__ __forceinline__ void layer_hop_h(const Geo& g, const Field<PO>& other,
+                                            const unsigned* __restrict__ gauge, int p, unsigned s,
+                                            const int l[4], const int tc[4], int x3,
+                                            const unsigned* __restrict__ F, C<float> acc[12]) {
+  unsigned w[12];
+  const float c = transport_h<MU, BACK, PO>(g, other, gauge, p, s, l, tc, x3, w);
+  mix_h(F + 32 * (BACK ? 2 + 2 * MU : 1 + 2 * MU), w, c, acc);
+}
+
+// As net_layer_kernel, in the FP16 form: F = the layer's weights as FP16
+// pairs (net_half_forms_kernel), FP16 links.
+template <class PS, class PO, class POUT, int MODE>
+__global__ __launch_bounds__(NET_BLK) __attribute__((amdgpu_waves_per_eu(4))) void net_layer_h_kernel(Geo g, int p, Field<POUT> out,
+                                                              Field<PS> same, Field<PO> other,
+                                                              const unsigned* __restrict__ gauge,
+                                                              const unsigned* __restrict__ F) {
+  const unsigned s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (unsigned)g.vh) return;
+  C<float> acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = C<float>{0.f, 0.f};
+  if constexpr (MODE != NET_HOPS) {
+    unsigned v[12];
+    const float sc = load_h<PS>(same, s, v);
+    mix_h(F, v, sc, acc);
+  }
+  if constexpr (MODE != NET_SELF) {
+    int l[4], tc[4];
+    site_local(g, p, s, l, tc);
+    const int x3 = tc[3] * g.T[3] + l[3];
+    layer_hop_h<0, false, PO>(g, other, gauge, p, s, l, tc, x3, F, acc);
+    layer_hop_h<0, true, PO>(g, other, gauge, p, s, l, tc, x3, F, acc);
+    layer_hop_h<1, false, PO>(g, other, gauge, p, s, l, tc, x3, F, acc);
+    layer_hop_h<1, true, PO>(g, other, gauge, p, s, l, tc, x3, F, acc);
+    layer_hop_h<2, false, PO>(g, other, gauge, p, s, l, tc, x3, F, acc);
+    layer_hop_h<2, true, PO>(g, other, gauge, p, s, l, tc, x3, F, acc);
+    layer_hop_h<3, false, PO>(g, other, gauge, p, s, l, tc, x3, F, acc);
+    layer_hop_h<3, true, PO>(g, other, gauge, p, s, l, tc, x3, F, acc);
+  }
+  store_h<POUT>(out, s, acc);
+}
+
+// FP16 pairs of n complex weights: F[2 i] = (re, -im), F[2 i + 1] = (im, re).
+__global__ void net_half_forms_kernel(const float2* __restrict__ w, unsigned* __restrict__ F,
+                                      int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float2 v = w[i];
+  F[2 * i] = pack_h(v.x, -v.y);
+  F[2 * i + 1] = pack_h(v.y, v.x);
 }
 
 // Per-workgroup partial of sum_{x in parity p, colour} g(x) (T_k psi)(x)^+
@@ -331,16 +583,17 @@ void layer(lq_ctx* ctx, const float2* W, void* out, void* in) {
   ctx->bytes += (double)ctx->V * (2.0 * 96 + 8 * 48 + 96);
 }
 
-// one parity of a layer in the fast precision set (FP16 links)
+// one parity of a layer in the fast precision set: FP16 links and FP16
+// arithmetic, F = the layer's weights as FP16 pairs
 template <class PS, class PO, class POUT, int MODE>
-void layer_part(lq_ctx* ctx, const float2* W, int p, void* out, const void* same,
+void layer_part(lq_ctx* ctx, const unsigned* F, int p, void* out, const void* same,
                 const void* other) {
   const Geo& g = ctx->geo;
-  const auto* gauge = reinterpret_cast<const __half2*>(ctx->gauge[LQ_F16]);
-  hipLaunchKernelGGL((net_layer_kernel<PS, PO, POUT, P16, MODE>), dim3(grid_for(g.vh, NET_BLK)),
+  const auto* gauge = reinterpret_cast<const unsigned*>(ctx->gauge[LQ_F16]);
+  hipLaunchKernelGGL((net_layer_h_kernel<PS, PO, POUT, MODE>), dim3(grid_for(g.vh, NET_BLK)),
                      dim3(NET_BLK), 0, ctx->cur, g, p, field_at<POUT>(out, g.nblk),
                      field_at<PS>(const_cast<void*>(same), g.nblk),
-                     field_at<PO>(const_cast<void*>(other), g.nblk), gauge, W);
+                     field_at<PO>(const_cast<void*>(other), g.nblk), gauge, F);
   LQ_HIP(hipGetLastError());
   double b = spinor_site_bytes(POUT::id);
   if (MODE != NET_HOPS) b += spinor_site_bytes(PS::id);
@@ -381,6 +634,7 @@ Net* net_create(lq_ctx* ctx, int L) {
     LQ_HIP(hipMalloc(&n->m1, wb));
     LQ_HIP(hipMalloc(&n->m2, wb));
     LQ_HIP(hipMalloc(&n->grad, (size_t)L * NET_W * sizeof(double2)));
+    LQ_HIP(hipMalloc(&n->wh, (size_t)L * NET_W * 2 * sizeof(unsigned)));
     LQ_HIP(hipMemset(n->w, 0, wb));
     LQ_HIP(hipMemset(n->m1, 0, wb));
     LQ_HIP(hipMemset(n->m2, 0, wb));
@@ -400,7 +654,7 @@ Net* net_create(lq_ctx* ctx, int L) {
 
 void net_destroy(Net* n) {
   if (!n) return;
-  for (void* p : {(void*)n->w, (void*)n->wadj, (void*)n->m1, (void*)n->m2, (void*)n->grad,
+  for (void* p : {(void*)n->w, (void*)n->wadj, (void*)n->wh, (void*)n->m1, (void*)n->m2, (void*)n->grad,
                   (void*)n->part, n->act, n->gbuf[0], n->gbuf[1], n->fbuf[0], n->fbuf[1]})
     if (p) (void)hipFree(p);
   delete n;
@@ -562,8 +816,11 @@ void net_apply_even_fast(Net* n, void* y_e, const void* x_e, bool adjoint) {
     LQ_HIP(hipMalloc(&n->fbuf[1], 2 * h16));
   }
   if (adjoint) ensure_adjoint(n);
-  const float2* W = adjoint ? n->wadj : n->w;
-  auto wl = [&](int i) { return W + (adjoint ? n->L - 1 - i : i) * NET_W; };
+  const int tot = n->L * NET_W;
+  hipLaunchKernelGGL(net_half_forms_kernel, dim3(grid_for(tot, 256)), dim3(256), 0, ctx->cur,
+                     adjoint ? n->wadj : n->w, n->wh, tot);
+  LQ_HIP(hipGetLastError());
+  auto wl = [&](int i) { return n->wh + (adjoint ? n->L - 1 - i : i) * NET_W * 2; };
   char* f[2][2] = {{reinterpret_cast<char*>(n->fbuf[0]), reinterpret_cast<char*>(n->fbuf[0]) + h16},
                    {reinterpret_cast<char*>(n->fbuf[1]), reinterpret_cast<char*>(n->fbuf[1]) + h16}};
   if (n->L == 1) {
