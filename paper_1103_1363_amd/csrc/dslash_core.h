@@ -88,20 +88,6 @@ __device__ __forceinline__ void load_link(const typename P::S* __restrict__ gaug
   (void)sizeof(R);
 }
 
-// z + a b and z + conj(a) b as chains of multiply-adds (the operators on C
-// round each product before the sum, and the compiler does not fuse across
-// them).
-__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
-template <class R>
-__device__ __forceinline__ C<R> cfma(C<R> a, C<R> b, C<R> z) {
-  return {fmadd(a.re, b.re, fmadd(-a.im, b.im, z.re)), fmadd(a.re, b.im, fmadd(a.im, b.re, z.im))};
-}
-template <class R>
-__device__ __forceinline__ C<R> cfma_conj(C<R> a, C<R> b, C<R> z) {
-  return {fmadd(a.re, b.re, fmadd(a.im, b.im, z.re)), fmadd(a.re, b.im, fmadd(-a.im, b.re, z.im))};
-}
-
 // w = U h (both colour vectors), or U^+ h when DAGU.
 template <bool DAGU, class R>
 __device__ __forceinline__ void link_mul(const C<R> u[9], const C<R> h[6], C<R> w[6]) {
@@ -112,12 +98,12 @@ __device__ __forceinline__ void link_mul(const C<R> u[9], const C<R> h[6], C<R> 
       C<R> acc;
       if constexpr (!DAGU) {
         acc = u[3 * a] * h[3 * k];
-        acc = cfma(u[3 * a + 1], h[3 * k + 1], acc);
-        acc = cfma(u[3 * a + 2], h[3 * k + 2], acc);
+        acc = acc + u[3 * a + 1] * h[3 * k + 1];
+        acc = acc + u[3 * a + 2] * h[3 * k + 2];
       } else {
         acc = cmul_conj(u[a], h[3 * k]);
-        acc = cfma_conj(u[3 + a], h[3 * k + 1], acc);
-        acc = cfma_conj(u[6 + a], h[3 * k + 2], acc);
+        acc = acc + cmul_conj(u[3 + a], h[3 * k + 1]);
+        acc = acc + cmul_conj(u[6 + a], h[3 * k + 2]);
       }
       w[3 * k + a] = acc;
     }
