@@ -404,6 +404,237 @@ __global__ __launch_bounds__(NET_BLK) __attribute__((amdgpu_waves_per_eu(4))) vo
   store_h<POUT>(out, s, acc);
 }
 
+// ---------------------------------------------------------------- matrix-core form
+// A layer whose input is FP16 in both parities, on the matrix cores.  The
+// output at a site is sum_h W_h T_h over h = 0 (the site's own spinor) and
+// the eight hops (h = the weight index: 1 + 2 mu forward, 2 + 2 mu
+// backward), T_h the transported spinor (4 spins x 3 colours).  In real
+// form, over the 64 sites of a wave and the 3 colours, that is one product
+//   Y[(s, re/im)][(site, a)] = sum_(h, t, re/im) A[(s, re/im)][(h, t, re/im)] B[(h, t, re/im)][(site, a)]
+// of the 8 x 72 weight matrix and a 72 x 192 block, computed in
+// v_mfma_f32_16x16x32_f16 tiles of 4 terms (K = 32) by 16 sites of one
+// colour (N = 16); rows 8-15 of A are zero, and so is K beyond the ninth
+// term.  Operand layout (lane l, i = l % 16, g = l / 16): A[i][8 g + j],
+// B[8 g + j][i] (eight halves per lane), D[4 g + j][i] (j = 0..3).  Row
+// (s, re) of A holds the pairs (re, -im) of W_h[s][t] and row (s, im) the
+// pairs (im, re): exactly the FP16 weight pairs of the dot-product form.
+// Each lane computes the transported spinors of its own site as in
+// net_layer_h_kernel, scaled by the ratio of the term's scale to the
+// largest of the site's nine scales (so that FP16 holds them), and writes
+// them to LDS, from where the lanes read their B operands; the output comes
+// back through LDS to one site per lane and is multiplied by that largest
+// scale.
+constexpr int NET_MBLK = 64;  // one wave per workgroup
+
+typedef _Float16 nh8 __attribute__((ext_vector_type(8)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef unsigned nu4 __attribute__((ext_vector_type(4)));
+
+// Neighbour number of site (l, tc) for hop (MU, BACK) and the hop's
+// boundary sign.
+template <int MU, bool BACK>
+__device__ __forceinline__ unsigned nb_of(const Geo& g, const int l[4], const int tc[4], int x3,
+                                          float& sign) {
+  sign = 1.f;
+  if constexpr (MU == 3) {
+    if (g.apt && x3 == (BACK ? 0 : g.L[3] - 1)) sign = -1.f;
+  }
+  int y[4] = {tc[0] * g.T[0] + l[0], tc[1] * g.T[1] + l[1], tc[2] * g.T[2] + l[2], x3};
+  if constexpr (!BACK)
+    y[MU] = (y[MU] + 1 == g.L[MU]) ? 0 : y[MU] + 1;
+  else
+    y[MU] = (y[MU] == 0) ? g.L[MU] - 1 : y[MU] - 1;
+  return (unsigned)cb_index(g, y);
+}
+
+// The raw FP16 spinor of neighbour sy carried by the FP16 link of hop
+// (MU, BACK) from site s: FP16 pairs w (without the neighbour's scale).
+template <int MU, bool BACK>
+__device__ __forceinline__ void carry_h(const Geo& g, const Field<P16>& other,
+                                        const unsigned* __restrict__ gauge, int p, unsigned s,
+                                        unsigned sy, unsigned w[12]) {
+  unsigned v[12];
+  const unsigned b = spin_base(sy);
+  const unsigned* d = reinterpret_cast<const unsigned*>(other.d);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = at32(d, b + 64u * c);
+  const unsigned ls = BACK ? sy : s;
+  const unsigned lb = (unsigned)(((BACK ? 1 - p : p) * 4 + MU) * (int)g.nblk) * 384u +
+                      (ls >> 6) * 384u + (ls & 63u);
+  unsigned u[9];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) u[c] = __builtin_nontemporal_load(&at32(gauge, lb + 64u * c));
+  {
+    C<float> r[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) r[c] = unpack_h(u[c]);
+    const C<float> z6 = conj(r[1] * r[5] - r[2] * r[4]);
+    const C<float> z7 = conj(r[2] * r[3] - r[0] * r[5]);
+    const C<float> z8 = conj(r[0] * r[4] - r[1] * r[3]);
+    u[6] = pack_h(z6.re, z6.im);
+    u[7] = pack_h(z7.re, z7.im);
+    u[8] = pack_h(z8.re, z8.im);
+  }
+  unsigned fr[9], fi[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    fr[c] = BACK ? u[c] : (u[c] ^ 0x80000000u);
+    fi[c] = BACK ? (swap_h(u[c]) ^ 0x00008000u) : swap_h(u[c]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int e0 = BACK ? a : 3 * a;
+      float zr = dot2_first(fr[e0], v[3 * t]);
+      float zi = dot2_first(fi[e0], v[3 * t]);
+#pragma unroll
+      for (int b2 = 1; b2 < 3; ++b2) {
+        const int e = BACK ? 3 * b2 + a : 3 * a + b2;
+        zr = dot2(fr[e], v[3 * t + b2], zr);
+        zi = dot2(fi[e], v[3 * t + b2], zi);
+      }
+      w[3 * t + a] = pack_h(zr, zi);
+    }
+}
+
+// Term h of the site in lane `lane`: its FP16 pairs times ratio, into LDS
+// slot `slot` as [slot][site][colour][spin].
+template <int H>
+__device__ __forceinline__ void stage_term(const Geo& g, const Field<P16>& same,
+                                           const Field<P16>& other,
+                                           const unsigned* __restrict__ gauge, int p, unsigned s,
+                                           const unsigned sy[9], float ratio, unsigned* st,
+                                           int slot, int lane) {
+  unsigned w[12];
+  if constexpr (H == 0) {
+    const unsigned b = spin_base(s);
+    const unsigned* d = reinterpret_cast<const unsigned*>(same.d);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) w[c] = at32(d, b + 64u * c);
+  } else {
+    carry_h<(H - 1) / 2, ((H - 1) & 1) != 0>(g, other, gauge, p, s, sy[H], w);
+  }
+  const nh2 r2 = {(_Float16)ratio, (_Float16)ratio};
+  unsigned* dst = st + (slot * NET_MBLK + lane) * 12;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    nu4 q;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      q[t] = __builtin_bit_cast(unsigned, __builtin_bit_cast(nh2, w[3 * t + a]) * r2);
+    *reinterpret_cast<nu4*>(dst + 4 * a) = q;
+  }
+}
+
+template <class POUT>
+__global__ __launch_bounds__(NET_MBLK) __attribute__((amdgpu_waves_per_eu(4))) void net_layer_mfma_kernel(Geo g, int p, Field<POUT> out,
+                                                                  Field<P16> same, Field<P16> other,
+                                                                  const unsigned* __restrict__ gauge,
+                                                                  const unsigned* __restrict__ F) {
+  __shared__ __align__(16) unsigned st[2 * NET_MBLK * 12];
+  const int lane = threadIdx.x;
+  const unsigned vh = (unsigned)g.vh;
+  const unsigned s0 = blockIdx.x * NET_MBLK + lane;
+  const bool valid = s0 < vh;
+  const unsigned s = valid ? s0 : vh - 1;  // every lane takes part in the matrix products
+  int l[4], tc[4];
+  site_local(g, p, s, l, tc);
+  const int x3 = tc[3] * g.T[3] + l[3];
+  // neighbour numbers and signed scales of the nine terms
+  unsigned sy[9];
+  float c[9];
+  sy[0] = s;
+  float sg[9];
+  sg[0] = 1.f;
+  sy[1] = nb_of<0, false>(g, l, tc, x3, sg[1]);
+  sy[2] = nb_of<0, true>(g, l, tc, x3, sg[2]);
+  sy[3] = nb_of<1, false>(g, l, tc, x3, sg[3]);
+  sy[4] = nb_of<1, true>(g, l, tc, x3, sg[4]);
+  sy[5] = nb_of<2, false>(g, l, tc, x3, sg[5]);
+  sy[6] = nb_of<2, true>(g, l, tc, x3, sg[6]);
+  sy[7] = nb_of<3, false>(g, l, tc, x3, sg[7]);
+  sy[8] = nb_of<3, true>(g, l, tc, x3, sg[8]);
+  c[0] = at32(same.norm, s);
+#pragma unroll
+  for (int h = 1; h < 9; ++h) c[h] = sg[h] * at32(other.norm, sy[h]);
+  float cmax = 0.f;
+#pragma unroll
+  for (int h = 0; h < 9; ++h) cmax = fmaxf(cmax, fabsf(c[h]));
+  const float rinv = cmax > 0.f ? 1.f / cmax : 0.f;
+  const int gg = lane >> 4, i = lane & 15;
+  // D[4 P + q]: colours 2 P + (row / 8) of sites 16 q .. 16 q + 15
+  nf4 D[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) D[q] = nf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    if (k == 0) {
+      stage_term<0>(g, same, other, gauge, p, s, sy, c[0] * rinv, st, 0, lane);
+      stage_term<1>(g, same, other, gauge, p, s, sy, c[1] * rinv, st, 1, lane);
+    } else if (k == 1) {
+      stage_term<2>(g, same, other, gauge, p, s, sy, c[2] * rinv, st, 0, lane);
+      stage_term<3>(g, same, other, gauge, p, s, sy, c[3] * rinv, st, 1, lane);
+    } else if (k == 2) {
+      stage_term<4>(g, same, other, gauge, p, s, sy, c[4] * rinv, st, 0, lane);
+      stage_term<5>(g, same, other, gauge, p, s, sy, c[5] * rinv, st, 1, lane);
+    } else if (k == 3) {
+      stage_term<6>(g, same, other, gauge, p, s, sy, c[6] * rinv, st, 0, lane);
+      stage_term<7>(g, same, other, gauge, p, s, sy, c[7] * rinv, st, 1, lane);
+    } else {
+      stage_term<8>(g, same, other, gauge, p, s, sy, c[8] * rinv, st, 0, lane);
+    }
+    // A operand, lane (gg, i): row i = (colour slot i / 8, spin, re/im) against
+    // K block gg = (term slot gg / 2, colour slot gg % 2); zero off the
+    // colour diagonal and past the ninth term
+    const int ts = gg >> 1, cb = gg & 1;
+    const int h = 2 * k + ts;
+    nu4 A;
+    {
+      const bool on = (i >> 3) == cb && h < 9;
+      const unsigned* f = F + 32 * (on ? h : 0) + 8 * ((i >> 1) & 3) + (i & 1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A[t] = on ? f[2 * t] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int P = 0; P < 2; ++P)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = 2 * P + cb;
+        const bool live = h < 9 && a < 3;
+        const unsigned* src = st + (ts * NET_MBLK + 16 * q + i) * 12 + 4 * (a < 3 ? a : 2);
+        const nu4 B = live ? *reinterpret_cast<const nu4*>(src) : nu4{0u, 0u, 0u, 0u};
+        D[4 * P + q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+            __builtin_bit_cast(nh8, A), __builtin_bit_cast(nh8, B), D[4 * P + q], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+  // D[4 P + q], lane (gg, i): rows 4 gg + j = colour 2 P + gg / 2, spin
+  // 2 (gg % 2) + j / 2, re/im j % 2, of site 16 q + i  ->  LDS [site][spin * 3 + colour]
+  float* o = reinterpret_cast<float*>(st);
+#pragma unroll
+  for (int P = 0; P < 2; ++P) {
+    const int a = 2 * P + (gg >> 1);
+    if (a < 3) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float* e = o + ((16 * q + i) * 12 + 2 * (gg & 1) * 3 + a) * 2;
+        e[0] = D[4 * P + q][0];
+        e[1] = D[4 * P + q][1];
+        e[6] = D[4 * P + q][2];  // next spin: 3 components further
+        e[7] = D[4 * P + q][3];
+      }
+    }
+  }
+  __syncthreads();
+  C<float> acc[12];
+#pragma unroll
+  for (int e = 0; e < 12; ++e)
+    acc[e] = C<float>{cmax * o[(lane * 12 + e) * 2], cmax * o[(lane * 12 + e) * 2 + 1]};
+  if (valid) store_h<POUT>(out, s, acc);
+}
+
 // FP16 pairs of n complex weights: F[2 i] = (re, -im), F[2 i + 1] = (im, re).
 __global__ void net_half_forms_kernel(const float2* __restrict__ w, unsigned* __restrict__ F,
                                       int n) {
@@ -598,6 +829,23 @@ void layer_part(lq_ctx* ctx, const unsigned* F, int p, void* out, const void* sa
   double b = spinor_site_bytes(POUT::id);
   if (MODE != NET_HOPS) b += spinor_site_bytes(PS::id);
   if (MODE != NET_SELF) b += spinor_site_bytes(PO::id) + 8 * link_site_bytes(LQ_F16);
+  ctx->bytes += (double)g.vh * b;
+}
+
+// one parity of a layer with FP16 input in both parities, on the matrix
+// cores (net_layer_mfma_kernel)
+template <class POUT>
+void layer_part_mfma(lq_ctx* ctx, const unsigned* F, int p, void* out, const void* same,
+                     const void* other) {
+  const Geo& g = ctx->geo;
+  const auto* gauge = reinterpret_cast<const unsigned*>(ctx->gauge[LQ_F16]);
+  hipLaunchKernelGGL(net_layer_mfma_kernel<POUT>, dim3(grid_for(g.vh, NET_MBLK)), dim3(NET_MBLK),
+                     0, ctx->cur, g, p, field_at<POUT>(out, g.nblk),
+                     field_at<P16>(const_cast<void*>(same), g.nblk),
+                     field_at<P16>(const_cast<void*>(other), g.nblk), gauge, F);
+  LQ_HIP(hipGetLastError());
+  const double b = spinor_site_bytes(POUT::id) + 2 * spinor_site_bytes(LQ_F16) +
+                   8 * link_site_bytes(LQ_F16);
   ctx->bytes += (double)g.vh * b;
 }
 
@@ -832,10 +1080,10 @@ void net_apply_even_fast(Net* n, void* y_e, const void* x_e, bool adjoint) {
   int cur = 0;
   for (int i = 1; i < n->L - 1; ++i) {
     for (int p = 0; p < 2; ++p)
-      layer_part<P16, P16, P16, NET_FULL>(ctx, wl(i), p, f[1 - cur][p], f[cur][p], f[cur][1 - p]);
+      layer_part_mfma<P16>(ctx, wl(i), p, f[1 - cur][p], f[cur][p], f[cur][1 - p]);
     cur = 1 - cur;
   }
-  layer_part<P16, P16, P32, NET_FULL>(ctx, wl(n->L - 1), LQ_EVEN, y_e, f[cur][0], f[cur][1]);
+  layer_part_mfma<P32>(ctx, wl(n->L - 1), LQ_EVEN, y_e, f[cur][0], f[cur][1]);
 }
 
 // Loss mean_i |N_e b_i - x_i|^2 / |x_i|^2 over npairs pairs of FP32 even
