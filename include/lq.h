@@ -234,9 +234,11 @@ lq_status lq_net_get_weights(lq_net* net, double* host_w);
 lq_status lq_net_init_neumann(lq_net* net, double kappa);
 
 /* dev_out = N_e dev_in (distinct buffers); mode is a sum of flags:
- * LQ_NET_ADJOINT applies N_e^+; LQ_NET_FP16 computes with FP16 links and
- * FP16 activations (per-site FP32 scales) and FP32 accumulation, the form the
- * solvers use (otherwise FP32 links and activations). */
+ * LQ_NET_ADJOINT applies N_e^+; LQ_NET_FP16 computes with FP16 links, FP16
+ * weights and FP16 activations (per-site FP32 scales) and FP32 accumulation
+ * (spin mixing on the matrix cores), the form the solvers use; its result
+ * agrees with the FP32 form to a few 1e-4 relative.  Otherwise FP32 links,
+ * weights and activations. */
 enum { LQ_NET_ADJOINT = 1, LQ_NET_FP16 = 2 };
 lq_status lq_net_apply(lq_net* net, void* dev_out, const void* dev_in, int mode);
 
