@@ -197,6 +197,44 @@ lq_status lq_solve_device(lq_ctx* ctx, void* dev_x, const void* dev_b, int nrhs,
                           lq_solve_report* report);
 
 /* ------------------------------------------------------------------------
+ * SAP preconditioner and FGCR: the solver of section 5 of the paper.
+ * The lattice is cut into non-overlapping blocks coloured like a
+ * checkerboard.  One application K of the Schwarz alternating procedure runs
+ * ncycles cycles from zero.  A cycle takes, for each colour in turn (colour
+ * 0 = even sum of block coordinates first), nmr minimal-residual steps on
+ * the Wilson-clover equation restricted to every block of that colour
+ * (Dirichlet boundary conditions: hops leaving a block are dropped), then
+ * recomputes the residual.  K is not a fixed matrix, so it serves as the
+ * right preconditioner of a flexible GCR (FGCR), restarted every `restart`
+ * steps with the residual recomputed in FP64 and the FP32 correction added
+ * to the FP64 solution (iterative refinement).  Block solves and the inner
+ * FGCR run in FP32. */
+typedef struct {
+  int block[4];  /* block extents (x, y, z, t): each divides the lattice extent an even
+                    number of times; at most 512 sites per block */
+  int ncycles;   /* SAP cycles per application (0: 5) */
+  int nmr;       /* MR steps per block solve (0: 4) */
+  int restart;   /* FGCR steps between FP64 restarts (0: 16, at most 64) */
+  int maxiter;   /* FGCR steps in all (0: 2000) */
+} lq_sap_params;
+
+/* dev_out = K dev_in on full-lattice FP32 fields (lq_field_bytes(ctx,
+ * LQ_FULL, LQ_F32, 1) bytes; distinct buffers), with the clover term of the
+ * last lq_set_clover or solve.  Runs on the context's stream; LQ_EINVAL for
+ * a block layout the lattice does not admit, LQ_ESTATE without gauge field
+ * or clover term. */
+lq_status lq_sap_apply(lq_ctx* ctx, void* dev_out, const void* dev_in,
+                       const lq_sap_params* params);
+
+/* Solve M x = b by SAP-preconditioned FGCR to ||b - M x|| <= tol ||b|| (FP64
+ * true residual).  dev_b, dev_x: full-lattice FP64 fields as for
+ * lq_solve_device (distinct; dev_x is overwritten).  report (may be NULL):
+ * iterations = FGCR steps, reliable_updates = FP64 restarts, true_residual.
+ * LQ_ENOCONV when maxiter steps do not reach tol. */
+lq_status lq_solve_sap(lq_ctx* ctx, void* dev_x, const void* dev_b, double kappa, double csw,
+                       double tol, const lq_sap_params* params, lq_solve_report* report);
+
+/* ------------------------------------------------------------------------
  * Learned preconditioner.  The paper's solvers are flexible Krylov methods
  * (its FGCR, equivalent to FGMRES, around a preconditioner that is itself an
  * iteration: section 5), which admit a preconditioner that is not a fixed

@@ -170,6 +170,7 @@ void lq_destroy(lq_ctx* ctx) {
   lq::free_mrhs_work(ctx);
   lq::free_mrhs_tables(ctx);
   lq::free_clover(ctx);
+  lq::sap_destroy(ctx->sap);
   for (int p = 0; p < 3; ++p)
     if (ctx->gauge[p]) (void)hipFree(ctx->gauge[p]);
   if (ctx->staging) (void)hipFree(ctx->staging);
@@ -364,6 +365,36 @@ lq_status lq_solve_device(lq_ctx* ctx, void* dev_x, const void* dev_b, int nrhs,
     LQ_CHECK(kappa > 0.0 && kappa < 0.25 && csw >= 0.0, LQ_EINVAL, "bad kappa or csw");
     LQ_CHECK(tol > 0.0 && tol < 1.0, LQ_EINVAL, "tol must lie in (0, 1)");
     lq::solve(ctx, nullptr, nullptr, dev_x, dev_b, nrhs, kappa, csw, tol, params, report);
+  });
+}
+
+// ------------------------------------------------------------ SAP and FGCR
+lq_status lq_sap_apply(lq_ctx* ctx, void* dev_out, const void* dev_in,
+                       const lq_sap_params* params) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(dev_out && dev_in && params, LQ_EINVAL, "null pointer");
+    LQ_CHECK(dev_out != dev_in, LQ_EINVAL, "in and out must be distinct buffers");
+    LQ_CHECK(ctx->have_gauge, LQ_ESTATE, "no gauge field uploaded");
+    lq::sap_apply(ctx, dev_out, dev_in, *params);
+  });
+}
+
+lq_status lq_solve_sap(lq_ctx* ctx, void* dev_x, const void* dev_b, double kappa, double csw,
+                       double tol, const lq_sap_params* params, lq_solve_report* report) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(dev_x && dev_b && params, LQ_EINVAL, "null pointer");
+    LQ_CHECK(dev_x != dev_b, LQ_EINVAL, "x and b must be distinct buffers");
+    LQ_CHECK(ctx->have_gauge, LQ_ESTATE, "no gauge field uploaded");
+    LQ_CHECK(kappa > 0.0 && kappa < 0.25 && csw >= 0.0, LQ_EINVAL, "bad kappa or csw");
+    LQ_CHECK(tol > 0.0 && tol < 1.0, LQ_EINVAL, "tol must lie in (0, 1)");
+    // after the caller's work, on the library stream
+    if (ctx->stream) LQ_HIP(hipStreamSynchronize(ctx->stream));
+    else LQ_HIP(hipDeviceSynchronize());
+    ctx->cur = ctx->sstream;
+    if (!ctx->clov.valid || ctx->clov.kappa != kappa || ctx->clov.csw != csw)
+      lq::build_clover(ctx, kappa, csw);
+    const bool ok = lq::solve_sap(ctx, dev_x, dev_b, tol, *params, report);
+    LQ_CHECK(ok, LQ_ENOCONV, "SAP-FGCR did not reach the tolerance");
   });
 }
 

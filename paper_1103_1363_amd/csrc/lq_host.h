@@ -23,6 +23,7 @@ struct Work;    // solver work space (solver.hip)
 struct MRWork;  // batched multi-RHS solver work space (mrhs.hip)
 struct Net;     // learned preconditioner (net.hip)
 struct Ensemble;  // uneven batch of independent solves (ensemble.hip)
+struct Sap;       // SAP preconditioner state (sap.hip)
 
 }  // namespace lq
 
@@ -50,6 +51,7 @@ struct lq_ctx {
   void* mr_nbr = nullptr;  // neighbour table (geometry only)
   void* mr_clov[2] = {nullptr, nullptr};  // A_ee (even sites), A_oo^-1 (odd sites)
   bool mr_links_ok = false, mr_clov_ok = false;
+  lq::Sap* sap = nullptr;   // SAP preconditioner state (lazy)
   std::string err;
   double bytes = 0.0;       // algorithmic bytes of every kernel launched so far
 };
@@ -78,6 +80,13 @@ void schur(lq_ctx* ctx, void* out, const void* in, void* tmp, int dagger, int pr
 
 // clover.hip
 void build_clover(lq_ctx* ctx, double kappa, double csw);
+
+// sap.hip: SAP preconditioner on full FP32 fields, and FGCR around it on
+// full FP64 fields (returns whether ||b - M x|| <= tol ||b||)
+void sap_apply(lq_ctx* ctx, void* out, const void* in, const lq_sap_params& q);
+bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_params& q,
+               lq_solve_report* rep);
+void sap_destroy(Sap* sp);
 void free_clover(lq_ctx* ctx);
 
 // blas.hip

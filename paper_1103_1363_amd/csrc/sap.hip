@@ -1,0 +1,534 @@
+// Schwarz alternating procedure (SAP) preconditioner and the flexible GCR
+// solver around it (section 5 of the paper: its SAP-FGCR solver).
+//
+// The lattice is cut into blocks of B0 x B1 x B2 x B3 sites, coloured like a
+// checkerboard; every extent holds an even number of blocks, so two blocks
+// of one colour never share a face.  One application K eta of the
+// preconditioner runs ncy cycles from psi = 0; a cycle, for each colour in
+// turn (0 first), takes nmr minimal-residual steps on every block of that
+// colour with Dirichlet boundary conditions (hops that leave the block are
+// dropped) and then recomputes the residual r = eta - M psi on the whole
+// lattice.  One workgroup solves one block: the block's residual lives in
+// LDS (one site per thread), the links and clover blocks stream from HBM.
+// All of it is FP32 on full-lattice fields (even half, then odd half).
+//
+// FGCR: right-preconditioned GCR, z_k = K r, w_k = M z_k orthonormalised by
+// modified Gram-Schmidt against the earlier w (the z transformed alike),
+// x += <w_k, r> z_k; the recursion restarts every `restart` steps, where the
+// residual is recomputed in FP64 and the FP32 correction added to the FP64
+// solution (iterative refinement, as the paper describes).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "dslash_core.h"
+#include "lq_internal.h"
+#include "reduce.h"
+
+namespace lq {
+
+struct Sap {
+  void* a32[2] = {nullptr, nullptr};  // FP32 clover blocks A of each parity
+  double kappa = -1.0, csw = -1.0;
+  void* r = nullptr;    // residual (FP32 full field)
+  void* tmp = nullptr;  // FP32 full field
+  std::vector<void*> z, w;                 // FGCR directions (FP32 full fields)
+  void* xc = nullptr;   // FP32 correction
+  void* r64 = nullptr;  // FP64 full field
+  double* part = nullptr;  // dot-product partials
+  double* hpart = nullptr; // host copy (pinned)
+};
+
+namespace {
+
+constexpr int SBLK = 256;     // workgroup of the full-lattice kernels
+constexpr int DOT_BLOCKS = 1024;
+constexpr int SAP_MAXV = 512;  // sites per block at most (one per thread)
+
+size_t half_bytes(const lq_ctx* ctx, int prec) { return parity_field_bytes(ctx->geo.nblk, prec); }
+template <class P>
+Field<P> half_of(const void* full, const lq_ctx* ctx, int p) {
+  char* b = const_cast<char*>(reinterpret_cast<const char*>(full));
+  return field_at<P>(b + (p ? half_bytes(ctx, P::id) : 0), ctx->geo.nblk);
+}
+
+// out_p = A_p psi_p - kappa H psi_{1-p} at the sites of parity p, or
+// eta_p minus that (SUB): the full operator M, one parity per launch.
+template <class P, bool SUB>
+LQ_HOP_KERNEL(P) void sap_m_kernel(Geo g, int p, Field<P> out, Field<P> eta, Field<P> same,
+                                   Field<P> other, const typename P::S* __restrict__ gauge,
+                                   const typename P::S* __restrict__ acl, typename P::R kappa) {
+  using R = typename P::R;
+  const int64_t s = xcd_block(blockIdx.x, gridDim.x) * SBLK + threadIdx.x;
+  if (s >= g.vh) return;
+  C<R> acc[12], x[12], y[12];
+  hop_site<false>(g, other, gauge, p, s, acc);
+  load_spinor<P>(same, s, x);
+  clover_mul<P>(acl, s, x, y);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) y[c] = y[c] - kappa * acc[c];
+  if constexpr (SUB) {
+    load_spinor<P>(eta, s, x);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) y[c] = x[c] - y[c];
+  }
+  store_spinor<P>(out, s, y);
+}
+
+struct SapBlocks {
+  int B[4];   // block extents
+  int NB[4];  // blocks per direction
+  int vb;     // sites per block
+};
+
+// One hop of the block operator at block-local site t: the neighbour's
+// spinor from LDS (component-major, vb sites), the link from HBM.
+template <int MU>
+__device__ __forceinline__ void block_hops(const Geo& g, const float2* __restrict__ gauge, int p,
+                                           int64_t s, int64_t sback, const float2* rho, int vb,
+                                           int t, int stride, bool fwd, bool bwd,
+                                           C<float> acc[12]) {
+  if (fwd) {
+    C<float> v[12], h[6], u[9], w[6];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 e = rho[c * vb + t + stride];
+      v[c] = C<float>{e.x, e.y};
+    }
+    project<MU, 1>(v, h);
+    load_link<P32>(gauge, g.nblk, p, MU, s, u);
+    link_mul<false>(u, h, w);
+    reconstruct_add<MU, 1>(acc, w);
+  }
+  if (bwd) {
+    C<float> v[12], h[6], u[9], w[6];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 e = rho[c * vb + t - stride];
+      v[c] = C<float>{e.x, e.y};
+    }
+    project<MU, -1>(v, h);
+    load_link<P32>(gauge, g.nblk, 1 - p, MU, sback, u);
+    link_mul<true>(u, h, w);
+    reconstruct_add<MU, -1>(acc, w);
+  }
+}
+
+// nmr MR steps on block blockIdx.x of colour `colour` (blocks of one colour
+// numbered with the x block index fastest), from delta = 0 and rho = r on
+// the block; psi += delta there.  One thread per site of the block.
+__global__ __launch_bounds__(SAP_MAXV) void sap_mr_kernel(Geo g, SapBlocks sb, int colour, int nmr,
+                                                          float kappa, Field<P32> r0, Field<P32> r1,
+                                                          Field<P32> psi0, Field<P32> psi1,
+                                                          const float2* __restrict__ gauge,
+                                                          const float2* __restrict__ a0,
+                                                          const float2* __restrict__ a1) {
+  extern __shared__ float2 rho[];  // [12][vb]
+  __shared__ double tot[3];
+  __shared__ double sh[3][16];
+  const int t = threadIdx.x;
+  const bool on = t < sb.vb;
+  const int tt = on ? t : 0;
+  // block coordinates: every x row of blocks holds NB0 / 2 of each colour
+  const int half = sb.NB[0] >> 1;
+  int j = blockIdx.x;
+  const int jx = j % half;
+  j /= half;
+  const int by = j % sb.NB[1];
+  j /= sb.NB[1];
+  const int bz = j % sb.NB[2];
+  const int bt = j / sb.NB[2];
+  const int bx = 2 * jx + ((by + bz + bt + colour) & 1);
+  int l[4];
+  {
+    int q = tt;
+    l[0] = q % sb.B[0];
+    q /= sb.B[0];
+    l[1] = q % sb.B[1];
+    q /= sb.B[1];
+    l[2] = q % sb.B[2];
+    l[3] = q / sb.B[2];
+  }
+  int x[4] = {bx * sb.B[0] + l[0], by * sb.B[1] + l[1], bz * sb.B[2] + l[2], bt * sb.B[3] + l[3]};
+  const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+  const int64_t s = cb_index(g, x);
+  int64_t sback[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    y[mu] = l[mu] > 0 ? y[mu] - 1 : y[mu];  // inside the block whenever used
+    sback[mu] = cb_index(g, y);
+  }
+  const int stride[4] = {1, sb.B[0], sb.B[0] * sb.B[1], sb.B[0] * sb.B[1] * sb.B[2]};
+  Field<P32> rf, pf;  // (selected by value: a reference would put the arguments in memory)
+  rf.d = p ? r1.d : r0.d;
+  rf.norm = nullptr;
+  pf.d = p ? psi1.d : psi0.d;
+  pf.norm = nullptr;
+  const float2* acl = p ? a1 : a0;
+  C<float> rt[12], del[12];
+  if (on) load_spinor<P32>(rf, s, rt);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    if (!on) rt[c] = C<float>{0.f, 0.f};
+    del[c] = C<float>{0.f, 0.f};
+    if (on) rho[c * sb.vb + t] = make_float2(rt[c].re, rt[c].im);
+  }
+  for (int it = 0; it < nmr; ++it) {
+    __syncthreads();
+    C<float> q[12];
+    double v[3] = {0.0, 0.0, 0.0};
+    if (on) {
+      C<float> acc[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = C<float>{0.f, 0.f};
+      block_hops<0>(g, gauge, p, s, sback[0], rho, sb.vb, t, stride[0], l[0] + 1 < sb.B[0], l[0] > 0, acc);
+      block_hops<1>(g, gauge, p, s, sback[1], rho, sb.vb, t, stride[1], l[1] + 1 < sb.B[1], l[1] > 0, acc);
+      block_hops<2>(g, gauge, p, s, sback[2], rho, sb.vb, t, stride[2], l[2] + 1 < sb.B[2], l[2] > 0, acc);
+      block_hops<3>(g, gauge, p, s, sback[3], rho, sb.vb, t, stride[3], l[3] + 1 < sb.B[3], l[3] > 0, acc);
+      clover_mul<P32>(acl, s, rt, q);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        q[c] = q[c] - kappa * acc[c];
+        v[0] += (double)q[c].re * rt[c].re + (double)q[c].im * rt[c].im;  // <q, rho>
+        v[1] += (double)q[c].re * rt[c].im - (double)q[c].im * rt[c].re;
+        v[2] += (double)q[c].re * q[c].re + (double)q[c].im * q[c].im;    // <q, q>
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) q[c] = C<float>{0.f, 0.f};
+    }
+    block_sum<3>(v, sh);  // (its barriers also end every read of rho above)
+    if (t == 0) {
+      tot[0] = v[0];
+      tot[1] = v[1];
+      tot[2] = v[2];
+    }
+    __syncthreads();
+    const double qq = tot[2];
+    const C<float> al = qq > 0.0 ? C<float>{(float)(tot[0] / qq), (float)(tot[1] / qq)}
+                                 : C<float>{0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      del[c] = del[c] + al * rt[c];
+      rt[c] = rt[c] - al * q[c];
+      if (on) rho[c * sb.vb + t] = make_float2(rt[c].re, rt[c].im);
+    }
+  }
+  if (on) {
+    C<float> o[12];
+    load_spinor<P32>(pf, s, o);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] = o[c] + del[c];
+    store_spinor<P32>(pf, s, o);
+  }
+}
+
+// FP64 clover blocks -> FP32
+__global__ void sap_a32_kernel(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+// Entries of a full field that belong to sites (not the padding of the last
+// 64-site block of each parity): entry i of parity half h.
+__device__ __forceinline__ bool live_entry(int64_t i, int64_t per_half, int64_t vh) {
+  const int64_t k = i % per_half;
+  const int64_t site = (k / (12 * SB)) * SB + (k % SB);
+  return site < vh;
+}
+
+// partials of <a, b> (re, im) and |b|^2 over the live entries of two full fields
+template <class TA, class TB>
+__global__ __launch_bounds__(256) void sap_dot_kernel(const TA* __restrict__ a,
+                                                      const TB* __restrict__ b, int64_t n,
+                                                      int64_t per_half, int64_t vh,
+                                                      double* __restrict__ part) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (!live_entry(i, per_half, vh)) continue;
+    const double ax = a[i].x, ay = a[i].y, bx = b[i].x, by = b[i].y;
+    v[0] += ax * bx + ay * by;
+    v[1] += ax * by - ay * bx;
+    v[2] += bx * bx + by * by;
+  }
+  block_partial<3>(v, part);
+}
+
+// y = ca x + cb y on FP32 entries (complex ca, cb)
+__global__ void sap_caxpby_kernel(float2* __restrict__ y, float ar, float ai,
+                                  const float2* __restrict__ x, float br, float bi, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float2 u = x[i], v = y[i];
+  y[i] = make_float2(ar * u.x - ai * u.y + br * v.x - bi * v.y,
+                     ar * u.y + ai * u.x + br * v.y + bi * v.x);
+}
+
+// FP64 -> FP32 and FP64 += FP32, entrywise
+__global__ void sap_to32_kernel(float2* __restrict__ out, const double2* __restrict__ in, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+__global__ void sap_add64_kernel(double2* __restrict__ y, const float2* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    double2 v = y[i];
+    v.x += x[i].x;
+    v.y += x[i].y;
+    y[i] = v;
+  }
+}
+
+int64_t entries(const lq_ctx* ctx) { return 2 * ctx->geo.nblk * SB * 12; }
+
+__global__ void sap_zero_kernel(float2* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_float2(0.f, 0.f);
+}
+
+void fill_zero(lq_ctx* ctx, void* p, size_t bytes) {
+  const int64_t n = (int64_t)(bytes / 8);
+  hipLaunchKernelGGL(sap_zero_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<float2*>(p), n);
+  LQ_HIP(hipGetLastError());
+}
+
+Sap* sap_state(lq_ctx* ctx) {
+  if (!ctx->sap) ctx->sap = new Sap();
+  Sap* sp = ctx->sap;
+  LQ_CHECK(ctx->clov.valid, LQ_ESTATE, "no clover term set (lq_set_clover or a solve)");
+  // clover tables: 36 complex per site (two 6x6 blocks in 18 slots each)
+  const int64_t ncl = ctx->geo.nblk * SB * 36;
+  if (!sp->a32[0]) {
+    for (int p = 0; p < 2; ++p) LQ_HIP(hipMalloc(&sp->a32[p], (size_t)ncl * sizeof(float2)));
+    LQ_HIP(hipMalloc(&sp->r, 2 * half_bytes(ctx, LQ_F32)));
+    LQ_HIP(hipMalloc(&sp->tmp, 2 * half_bytes(ctx, LQ_F32)));
+    LQ_HIP(hipMalloc(&sp->part, DOT_BLOCKS * 3 * sizeof(double)));
+    LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&sp->hpart), DOT_BLOCKS * 3 * sizeof(double)));
+  }
+  if (sp->kappa != ctx->clov.kappa || sp->csw != ctx->clov.csw) {
+    for (int p = 0; p < 2; ++p)
+      hipLaunchKernelGGL(sap_a32_kernel, dim3(grid_for(ncl, 256)), dim3(256), 0, ctx->cur,
+                         reinterpret_cast<const double2*>(ctx->clov.a64[p]),
+                         reinterpret_cast<float2*>(sp->a32[p]), ncl);
+    LQ_HIP(hipGetLastError());
+    sp->kappa = ctx->clov.kappa;
+    sp->csw = ctx->clov.csw;
+  }
+  return sp;
+}
+
+// out = M in (SUB: out = eta - M in) on full fields of precision P
+template <class P, bool SUB>
+void full_m(lq_ctx* ctx, void* out, const void* eta, const void* in) {
+  const Geo& g = ctx->geo;
+  const auto* gauge = reinterpret_cast<const typename P::S*>(ctx->gauge[P::id]);
+  for (int p = 0; p < 2; ++p) {
+    const void* acl;
+    if constexpr (P::id == LQ_F64)
+      acl = ctx->clov.a64[p];
+    else
+      acl = ctx->sap->a32[p];
+    hipLaunchKernelGGL((sap_m_kernel<P, SUB>), dim3(grid_for(g.vh, SBLK)), dim3(SBLK), 0,
+                       ctx->cur, g, p, half_of<P>(out, ctx, p),
+                       half_of<P>(SUB ? eta : in, ctx, p), half_of<P>(in, ctx, p),
+                       half_of<P>(in, ctx, 1 - p), gauge,
+                       reinterpret_cast<const typename P::S*>(acl),
+                       (typename P::R)ctx->clov.kappa);
+  }
+  LQ_HIP(hipGetLastError());
+  const double site = 8 * link_site_bytes(P::id) + clover_site_bytes(P::id) +
+                      (SUB ? 4 : 3) * spinor_site_bytes(P::id);
+  ctx->bytes += (double)ctx->V * site;
+}
+
+// <a, b> and |b|^2 over two full fields (host values)
+template <class TA, class TB>
+void dot3(lq_ctx* ctx, const void* a, const void* b, double out[3]) {
+  Sap* sp = ctx->sap;
+  const int64_t n = entries(ctx);
+  hipLaunchKernelGGL((sap_dot_kernel<TA, TB>), dim3(DOT_BLOCKS), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<const TA*>(a), reinterpret_cast<const TB*>(b), n, n / 2,
+                     ctx->geo.vh, sp->part);
+  LQ_HIP(hipGetLastError());
+  LQ_HIP(hipMemcpyAsync(sp->hpart, sp->part, DOT_BLOCKS * 3 * sizeof(double),
+                        hipMemcpyDeviceToHost, ctx->cur));
+  LQ_HIP(hipStreamSynchronize(ctx->cur));
+  out[0] = out[1] = out[2] = 0.0;
+  for (int i = 0; i < DOT_BLOCKS; ++i)
+    for (int k = 0; k < 3; ++k) out[k] += sp->hpart[3 * i + k];
+}
+
+void caxpby(lq_ctx* ctx, void* y, std::complex<double> a, const void* x, std::complex<double> b) {
+  const int64_t n = entries(ctx);
+  hipLaunchKernelGGL(sap_caxpby_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<float2*>(y), (float)a.real(), (float)a.imag(),
+                     reinterpret_cast<const float2*>(x), (float)b.real(), (float)b.imag(), n);
+  LQ_HIP(hipGetLastError());
+}
+
+SapBlocks blocks_of(const lq_ctx* ctx, const lq_sap_params& q) {
+  SapBlocks sb;
+  sb.vb = 1;
+  for (int k = 0; k < 4; ++k) {
+    const int b = q.block[k], L = ctx->dims[k];
+    LQ_CHECK(b >= 1 && L % b == 0 && (L / b) % 2 == 0, LQ_EINVAL,
+             "each block extent must divide the lattice extent an even number of times");
+    sb.B[k] = b;
+    sb.NB[k] = L / b;
+    sb.vb *= b;
+  }
+  LQ_CHECK(sb.vb <= SAP_MAXV, LQ_EINVAL, "a block holds at most 512 sites");
+  return sb;
+}
+
+void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params& q) {
+  Sap* sp = sap_state(ctx);
+  const SapBlocks sb = blocks_of(ctx, q);
+  const int ncy = q.ncycles > 0 ? q.ncycles : 5;
+  const int nmr = q.nmr > 0 ? q.nmr : 4;
+  const size_t f32 = 2 * half_bytes(ctx, LQ_F32);
+  const size_t lds = (size_t)sb.vb * 12 * sizeof(float2);
+  int dev = 0, maxlds = 0;
+  LQ_HIP(hipGetDevice(&dev));
+  LQ_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  LQ_CHECK(lds + 4096 <= (size_t)maxlds, LQ_EINVAL, "block too large for the workgroup's LDS");
+  const int threads = (sb.vb + 63) / 64 * 64;
+  const int nblk_colour = sb.NB[0] * sb.NB[1] * sb.NB[2] * sb.NB[3] / 2;
+  fill_zero(ctx, out, f32);
+  LQ_HIP(hipMemcpyAsync(sp->r, in, f32, hipMemcpyDeviceToDevice, ctx->cur));
+  const auto* gauge = reinterpret_cast<const float2*>(ctx->gauge[LQ_F32]);
+  const Geo& g = ctx->geo;
+  for (int cy = 0; cy < ncy; ++cy)
+    for (int c = 0; c < 2; ++c) {
+      hipLaunchKernelGGL(sap_mr_kernel, dim3(nblk_colour), dim3(threads), lds, ctx->cur, g, sb, c,
+                         nmr, (float)ctx->clov.kappa, half_of<P32>(sp->r, ctx, 0),
+                         half_of<P32>(sp->r, ctx, 1), half_of<P32>(out, ctx, 0),
+                         half_of<P32>(out, ctx, 1), gauge,
+                         reinterpret_cast<const float2*>(sp->a32[0]),
+                         reinterpret_cast<const float2*>(sp->a32[1]));
+      LQ_HIP(hipGetLastError());
+      // per site of the colour, per MR step: 8 links, the clover blocks, and
+      // the residual read and the solution read and written once
+      ctx->bytes += ctx->V / 2.0 * (nmr * (8 * link_site_bytes(LQ_F32) +
+                                           clover_site_bytes(LQ_F32)) +
+                                    3 * spinor_site_bytes(LQ_F32));
+      full_m<P32, true>(ctx, sp->r, in, out);
+    }
+}
+
+}  // namespace
+
+void sap_destroy(Sap* sp) {
+  if (!sp) return;
+  for (void* p : {sp->a32[0], sp->a32[1], sp->r, sp->tmp, sp->xc, sp->r64, (void*)sp->part})
+    if (p) (void)hipFree(p);
+  for (void* p : sp->z) (void)hipFree(p);
+  for (void* p : sp->w) (void)hipFree(p);
+  if (sp->hpart) (void)hipHostFree(sp->hpart);
+  delete sp;
+}
+
+void sap_apply(lq_ctx* ctx, void* out, const void* in, const lq_sap_params& q) {
+  sap_apply_impl(ctx, out, in, q);
+}
+
+// FGCR with the SAP preconditioner on the full system M x = b (FP64 fields
+// x, b on the device); returns true when ||b - M x|| <= tol ||b||.
+bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_params& q,
+               lq_solve_report* rep) {
+  auto t0 = std::chrono::steady_clock::now();
+  const double bytes0 = ctx->bytes;
+  Sap* sp = sap_state(ctx);
+  (void)blocks_of(ctx, q);
+  const int m = q.restart > 0 ? q.restart : 16;
+  LQ_CHECK(m <= 64, LQ_EINVAL, "restart length above 64");
+  const int maxiter = q.maxiter > 0 ? q.maxiter : 2000;
+  const size_t f32 = 2 * half_bytes(ctx, LQ_F32), f64 = 2 * half_bytes(ctx, LQ_F64);
+  while ((int)sp->z.size() < m) {
+    void *z = nullptr, *w = nullptr;
+    LQ_HIP(hipMalloc(&z, f32));
+    sp->z.push_back(z);
+    LQ_HIP(hipMalloc(&w, f32));
+    sp->w.push_back(w);
+  }
+  if (!sp->xc) LQ_HIP(hipMalloc(&sp->xc, f32));
+  if (!sp->r64) LQ_HIP(hipMalloc(&sp->r64, f64));
+  const int64_t n = entries(ctx);
+  double d[3];
+  dot3<double2, double2>(ctx, b, b, d);
+  const double bn = std::sqrt(d[2]);
+  int iters = 0, restarts = 0;
+  double res = 0.0;
+  bool conv = false;
+  fill_zero(ctx, x, f64);
+  if (bn == 0.0) {
+    conv = true;
+  } else {
+    void* rho = sp->tmp;
+    for (;;) {
+      full_m<P64, true>(ctx, sp->r64, b, x);
+      dot3<double2, double2>(ctx, sp->r64, sp->r64, d);
+      res = std::sqrt(d[2]) / bn;
+      if (res <= tol) {
+        conv = true;
+        break;
+      }
+      if (iters >= maxiter || !std::isfinite(res)) break;
+      ++restarts;
+      hipLaunchKernelGGL(sap_to32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
+                         reinterpret_cast<float2*>(rho),
+                         reinterpret_cast<const double2*>(sp->r64), n);
+      LQ_HIP(hipGetLastError());
+      fill_zero(ctx, sp->xc, f32);
+      const double rn0 = std::sqrt(d[2]);
+      // an FP32 cycle is trusted down to about 1e-5 of its start; the last
+      // stops at what the FP64 residual still needs (with a margin of 2)
+      const double cycle = std::max(1e-5, 0.5 * tol / res);
+      for (int k = 0; k < m && iters < maxiter; ++k) {
+        sap_apply_impl(ctx, sp->z[k], rho, q);
+        full_m<P32, false>(ctx, sp->w[k], nullptr, sp->z[k]);
+        for (int j = 0; j < k; ++j) {
+          dot3<float2, float2>(ctx, sp->w[j], sp->w[k], d);
+          const std::complex<double> beta(d[0], d[1]);
+          caxpby(ctx, sp->w[k], -beta, sp->w[j], 1.0);
+          caxpby(ctx, sp->z[k], -beta, sp->z[j], 1.0);
+        }
+        dot3<float2, float2>(ctx, sp->w[k], sp->w[k], d);
+        const double wn = std::sqrt(d[2]);
+        if (!(wn > 0.0) || !std::isfinite(wn)) break;
+        caxpby(ctx, sp->w[k], 1.0 / wn, sp->w[k], 0.0);
+        caxpby(ctx, sp->z[k], 1.0 / wn, sp->z[k], 0.0);
+        dot3<float2, float2>(ctx, sp->w[k], rho, d);
+        const std::complex<double> al(d[0], d[1]);
+        caxpby(ctx, sp->xc, al, sp->z[k], 1.0);
+        caxpby(ctx, rho, -al, sp->w[k], 1.0);
+        ++iters;
+        dot3<float2, float2>(ctx, rho, rho, d);
+        if (std::sqrt(d[2]) <= cycle * rn0) break;
+      }
+      hipLaunchKernelGGL(sap_add64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
+                         reinterpret_cast<double2*>(x), reinterpret_cast<const float2*>(sp->xc),
+                         n);
+      LQ_HIP(hipGetLastError());
+    }
+  }
+  LQ_HIP(hipStreamSynchronize(ctx->cur));
+  if (rep) {
+    *rep = lq_solve_report{};
+    rep->iterations = iters;
+    rep->reliable_updates = restarts;
+    rep->true_residual = res;
+    rep->schur_residual = res;
+    rep->seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rep->bytes = ctx->bytes - bytes0;
+  }
+  return conv;
+}
+
+}  // namespace lq

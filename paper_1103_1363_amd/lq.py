@@ -55,6 +55,11 @@ class SolveReport(ct.Structure):
         return d
 
 
+class SapParams(ct.Structure):
+    _fields_ = [("block", ct.c_int * 4), ("ncycles", ct.c_int), ("nmr", ct.c_int),
+                ("restart", ct.c_int), ("maxiter", ct.c_int)]
+
+
 class EnsembleReport(ct.Structure):
     _fields_ = [("tile_sites", ct.c_int), ("tile_from_cache", ct.c_int),
                 ("tune_ms", ct.c_double * 3), ("graph_captures", ct.c_int),
@@ -119,6 +124,9 @@ def lib():
         L.lq_net_train.argtypes = [vp, vp, vp, ip, ip, ip, ct.c_double, ct.c_uint, dp]
         L.lq_solve_net.argtypes = [vp, vp, dp, dp, ip, ct.c_double, ct.c_double, ct.c_double,
                                    ct.POINTER(SolverParams), ct.POINTER(SolveReport)]
+        L.lq_sap_apply.argtypes = [vp, vp, vp, ct.POINTER(SapParams)]
+        L.lq_solve_sap.argtypes = [vp, vp, vp, ct.c_double, ct.c_double, ct.c_double,
+                                   ct.POINTER(SapParams), ct.POINTER(SolveReport)]
         L.lq_ensemble_create.argtypes = [ct.POINTER(vp), ip, ct.POINTER(vp)]
         L.lq_ensemble_destroy.argtypes = [vp]
         L.lq_ensemble_destroy.restype = None
@@ -132,7 +140,8 @@ def lib():
             getattr(L, name).restype = ip
         for name in ("lq_upload_gauge", "lq_set_clover", "lq_spinor_to_device",
                      "lq_spinor_to_host", "lq_dslash", "lq_clover_apply", "lq_schur",
-                     "lq_norm2", "lq_dot", "lq_solve", "lq_solve_device", "lq_net_create",
+                     "lq_norm2", "lq_dot", "lq_solve", "lq_solve_device", "lq_sap_apply",
+                     "lq_solve_sap", "lq_net_create",
                      "lq_net_set_weights", "lq_net_get_weights", "lq_net_init_neumann", "lq_net_apply",
                      "lq_net_loss_grad", "lq_net_adam_step", "lq_net_train", "lq_solve_net"):
             getattr(L, name).restype = ip
@@ -299,6 +308,38 @@ class Lattice:
         if rc != 0 and (rc != -4 or raise_on_noconv):
             self._check(rc)
         return reports
+
+
+    # -- SAP preconditioner and FGCR ------------------------------------
+    @staticmethod
+    def _sap_params(block, ncycles, nmr, restart=0, maxiter=0):
+        return SapParams((ct.c_int * 4)(*[int(b) for b in block]), int(ncycles), int(nmr),
+                         int(restart), int(maxiter))
+
+    def sap_apply(self, dev_out, dev_in, block, ncycles=0, nmr=0):
+        """dev_out = K dev_in on full-lattice FP32 fields (see lq_sap_apply)."""
+        p = self._sap_params(block, ncycles, nmr)
+        self._check(self._L.lq_sap_apply(self._h, ct.c_void_p(dev_out.data_ptr()),
+                                         ct.c_void_p(dev_in.data_ptr()), ct.byref(p)))
+
+    def solve_sap_device(self, dev_x, dev_b, kappa, csw, tol=1e-10, block=(4, 4, 4, 4),
+                         ncycles=0, nmr=0, restart=0, maxiter=0, raise_on_noconv=True):
+        """SAP-preconditioned FGCR on full-lattice FP64 device fields (see lq_solve_sap)."""
+        p = self._sap_params(block, ncycles, nmr, restart, maxiter)
+        rep = SolveReport()
+        rc = self._L.lq_solve_sap(self._h, ct.c_void_p(dev_x.data_ptr()),
+                                  ct.c_void_p(dev_b.data_ptr()), float(kappa), float(csw),
+                                  float(tol), ct.byref(p), ct.byref(rep))
+        if rc != 0 and (rc != -4 or raise_on_noconv):
+            self._check(rc)
+        return Report(**rep.as_dict())
+
+    def solve_sap(self, b, kappa, csw, tol=1e-10, block=(4, 4, 4, 4), **kw):
+        """The same from and to host arrays (one full-lattice right-hand side)."""
+        db = self.to_device(b, FULL, F64)
+        dx = self.new_field(FULL, F64)
+        rep = self.solve_sap_device(dx, db, kappa, csw, tol, block, **kw)
+        return self.to_host(dx, FULL, F64).reshape(np.shape(b)), rep
 
 
 NET_K = 9  # weight matrices per layer: W0, then (Wp_mu, Wm_mu) for mu = 0..3
