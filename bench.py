@@ -537,8 +537,8 @@ def main():
                                                                   a.net_epochs)
 
     if not a.no_sap:
-        log("SAP-preconditioned FGCR (blocks 8x4x4x4, 4 cycles of 4 MR steps)")
-        result["sap_fgcr"] = sap_fgcr(lq, lat, torch, db, (8, 4, 4, 4), 4, 4, 16)
+        log("SAP-preconditioned FGCR (blocks 8x4x4x4, 3 cycles of 6 MR steps, restart 48)")
+        result["sap_fgcr"] = sap_fgcr(lq, lat, torch, db, (8, 4, 4, 4), 3, 6, 48)
 
     if not a.no_cpu_baseline:
         log("CPU baseline (oracle)")
