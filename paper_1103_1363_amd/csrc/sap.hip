@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <vector>
 
 #include "dslash_core.h"
@@ -116,9 +117,56 @@ __device__ __forceinline__ void block_hops(const Geo& g, const float2* __restric
   }
 }
 
+// Rows 0 and 1 of the forward link in direction MU of block site ts, from
+// the LDS copy [mu][6][vb], and row 2 rebuilt.
+__device__ __forceinline__ void lds_link(const float2* L, int vb, int mu, int ts, C<float> u[9]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const float2 e = L[(mu * 6 + c) * vb + ts];
+    u[c] = C<float>{e.x, e.y};
+  }
+  u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+  u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+  u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+}
+
+// As block_hops, with the links from the block's LDS copy: the backward hop
+// from t uses the forward link of site t - stride.
+template <int MU>
+__device__ __forceinline__ void block_hops_lds(const float2* rho, const float2* L, int vb, int t,
+                                               int stride, bool fwd, bool bwd, C<float> acc[12]) {
+  if (fwd) {
+    C<float> v[12], h[6], u[9], w[6];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 e = rho[c * vb + t + stride];
+      v[c] = C<float>{e.x, e.y};
+    }
+    project<MU, 1>(v, h);
+    lds_link(L, vb, MU, t, u);
+    link_mul<false>(u, h, w);
+    reconstruct_add<MU, 1>(acc, w);
+  }
+  if (bwd) {
+    C<float> v[12], h[6], u[9], w[6];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 e = rho[c * vb + t - stride];
+      v[c] = C<float>{e.x, e.y};
+    }
+    project<MU, -1>(v, h);
+    lds_link(L, vb, MU, t - stride, u);
+    link_mul<true>(u, h, w);
+    reconstruct_add<MU, -1>(acc, w);
+  }
+}
+
 // nmr MR steps on block blockIdx.x of colour `colour` (blocks of one colour
 // numbered with the x block index fastest), from delta = 0 and rho = r on
-// the block; psi += delta there.  One thread per site of the block.
+// the block; psi += delta there.  One thread per site of the block.  CACHE:
+// the block's forward links are read once into LDS (after the residual,
+// [4][6][vb]) instead of from HBM at every MR step.
+template <bool CACHE>
 __global__ __launch_bounds__(SAP_MAXV) void sap_mr_kernel(Geo g, SapBlocks sb, int colour, int nmr,
                                                           float kappa, Field<P32> r0, Field<P32> r1,
                                                           Field<P32> psi0, Field<P32> psi1,
@@ -168,6 +216,17 @@ __global__ __launch_bounds__(SAP_MAXV) void sap_mr_kernel(Geo g, SapBlocks sb, i
   pf.d = p ? psi1.d : psi0.d;
   pf.norm = nullptr;
   const float2* acl = p ? a1 : a0;
+  float2* links = rho + 12 * sb.vb;
+  if constexpr (CACHE) {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+      if (on && l[mu] + 1 < sb.B[mu])
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const C<float> e = ldnt<P32>(gauge, link_idx(g.nblk, p, mu, s, c));
+          links[(mu * 6 + c) * sb.vb + t] = make_float2(e.re, e.im);
+        }
+  }
   C<float> rt[12], del[12];
   if (on) load_spinor<P32>(rf, s, rt);
 #pragma unroll
@@ -184,10 +243,17 @@ __global__ __launch_bounds__(SAP_MAXV) void sap_mr_kernel(Geo g, SapBlocks sb, i
       C<float> acc[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc[c] = C<float>{0.f, 0.f};
-      block_hops<0>(g, gauge, p, s, sback[0], rho, sb.vb, t, stride[0], l[0] + 1 < sb.B[0], l[0] > 0, acc);
-      block_hops<1>(g, gauge, p, s, sback[1], rho, sb.vb, t, stride[1], l[1] + 1 < sb.B[1], l[1] > 0, acc);
-      block_hops<2>(g, gauge, p, s, sback[2], rho, sb.vb, t, stride[2], l[2] + 1 < sb.B[2], l[2] > 0, acc);
-      block_hops<3>(g, gauge, p, s, sback[3], rho, sb.vb, t, stride[3], l[3] + 1 < sb.B[3], l[3] > 0, acc);
+      if constexpr (CACHE) {
+        block_hops_lds<0>(rho, links, sb.vb, t, stride[0], l[0] + 1 < sb.B[0], l[0] > 0, acc);
+        block_hops_lds<1>(rho, links, sb.vb, t, stride[1], l[1] + 1 < sb.B[1], l[1] > 0, acc);
+        block_hops_lds<2>(rho, links, sb.vb, t, stride[2], l[2] + 1 < sb.B[2], l[2] > 0, acc);
+        block_hops_lds<3>(rho, links, sb.vb, t, stride[3], l[3] + 1 < sb.B[3], l[3] > 0, acc);
+      } else {
+        block_hops<0>(g, gauge, p, s, sback[0], rho, sb.vb, t, stride[0], l[0] + 1 < sb.B[0], l[0] > 0, acc);
+        block_hops<1>(g, gauge, p, s, sback[1], rho, sb.vb, t, stride[1], l[1] + 1 < sb.B[1], l[1] > 0, acc);
+        block_hops<2>(g, gauge, p, s, sback[2], rho, sb.vb, t, stride[2], l[2] + 1 < sb.B[2], l[2] > 0, acc);
+        block_hops<3>(g, gauge, p, s, sback[3], rho, sb.vb, t, stride[3], l[3] + 1 < sb.B[3], l[3] > 0, acc);
+      }
       clover_mul<P32>(acl, s, rt, q);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
@@ -393,10 +459,14 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
   const int nmr = q.nmr > 0 ? q.nmr : 4;
   const size_t f32 = 2 * half_bytes(ctx, LQ_F32);
   const size_t lds = (size_t)sb.vb * 12 * sizeof(float2);
+  const size_t lds_cached = lds + (size_t)sb.vb * 24 * sizeof(float2);
   int dev = 0, maxlds = 0;
   LQ_HIP(hipGetDevice(&dev));
   LQ_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   LQ_CHECK(lds + 4096 <= (size_t)maxlds, LQ_EINVAL, "block too large for the workgroup's LDS");
+  // LQ_SAP_LDS_LINKS=0 keeps the links in HBM (tests of both kernels)
+  const char* env = std::getenv("LQ_SAP_LDS_LINKS");
+  const bool cache = lds_cached + 4096 <= (size_t)maxlds && !(env && env[0] == '0');
   const int threads = (sb.vb + 63) / 64 * 64;
   const int nblk_colour = sb.NB[0] * sb.NB[1] * sb.NB[2] * sb.NB[3] / 2;
   fill_zero(ctx, out, f32);
@@ -405,17 +475,27 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
   const Geo& g = ctx->geo;
   for (int cy = 0; cy < ncy; ++cy)
     for (int c = 0; c < 2; ++c) {
-      hipLaunchKernelGGL(sap_mr_kernel, dim3(nblk_colour), dim3(threads), lds, ctx->cur, g, sb, c,
-                         nmr, (float)ctx->clov.kappa, half_of<P32>(sp->r, ctx, 0),
-                         half_of<P32>(sp->r, ctx, 1), half_of<P32>(out, ctx, 0),
-                         half_of<P32>(out, ctx, 1), gauge,
-                         reinterpret_cast<const float2*>(sp->a32[0]),
-                         reinterpret_cast<const float2*>(sp->a32[1]));
+      if (cache)
+        hipLaunchKernelGGL(sap_mr_kernel<true>, dim3(nblk_colour), dim3(threads), lds_cached,
+                           ctx->cur, g, sb, c, nmr, (float)ctx->clov.kappa,
+                           half_of<P32>(sp->r, ctx, 0), half_of<P32>(sp->r, ctx, 1),
+                           half_of<P32>(out, ctx, 0), half_of<P32>(out, ctx, 1), gauge,
+                           reinterpret_cast<const float2*>(sp->a32[0]),
+                           reinterpret_cast<const float2*>(sp->a32[1]));
+      else
+        hipLaunchKernelGGL(sap_mr_kernel<false>, dim3(nblk_colour), dim3(threads), lds, ctx->cur,
+                           g, sb, c, nmr, (float)ctx->clov.kappa, half_of<P32>(sp->r, ctx, 0),
+                           half_of<P32>(sp->r, ctx, 1), half_of<P32>(out, ctx, 0),
+                           half_of<P32>(out, ctx, 1), gauge,
+                           reinterpret_cast<const float2*>(sp->a32[0]),
+                           reinterpret_cast<const float2*>(sp->a32[1]));
       LQ_HIP(hipGetLastError());
-      // per site of the colour, per MR step: 8 links, the clover blocks, and
-      // the residual read and the solution read and written once
-      ctx->bytes += ctx->V / 2.0 * (nmr * (8 * link_site_bytes(LQ_F32) +
+      // per site of the colour: per MR step the clover blocks (and without
+      // the LDS copy 8 links), 4 links once with it, and the residual read
+      // and the solution read and written once
+      ctx->bytes += ctx->V / 2.0 * (nmr * ((cache ? 0 : 8) * link_site_bytes(LQ_F32) +
                                            clover_site_bytes(LQ_F32)) +
+                                    (cache ? 4 : 0) * link_site_bytes(LQ_F32) +
                                     3 * spinor_site_bytes(LQ_F32));
       full_m<P32, true>(ctx, sp->r, in, out);
     }

@@ -34,10 +34,15 @@ CASES = [
 
 @pytest.mark.parametrize("dims,block,tile", CASES)
 @pytest.mark.parametrize("ncy,nmr", [(1, 1), (2, 4)])
-def test_sap_apply_parity(lq, monkeypatch, dims, block, tile, ncy, nmr):
-    say(f"sap apply dims={dims} block={block} tile={tile} ncy={ncy} nmr={nmr}")
+@pytest.mark.parametrize("lds_links", ["1", "0"])
+def test_sap_apply_parity(lq, monkeypatch, dims, block, tile, ncy, nmr, lds_links):
+    """Both block kernels: links copied to LDS once, or read from HBM at
+    every MR step (LQ_SAP_LDS_LINKS=0)."""
+    say(f"sap apply dims={dims} block={block} tile={tile} ncy={ncy} nmr={nmr} "
+        f"lds_links={lds_links}")
     if tile:
         monkeypatch.setenv("LQ_TILE_SITES", tile)
+    monkeypatch.setenv("LQ_SAP_LDS_LINKS", lds_links)
     u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 31)
     eta = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 31)
     lat = lq.Lattice(dims)
