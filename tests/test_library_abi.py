@@ -84,3 +84,16 @@ def test_ensemble_create_rejects_bad_arguments_on_the_host():
     assert lib.lq_ensemble_create(members, 2, ctypes.byref(out)) == -1
     assert lib.lq_ensemble_create(members, 65, ctypes.byref(out)) == -1
     assert lib.lq_ensemble_create(members, 2, None) == -1
+
+
+def test_sap_calls_reject_missing_context():
+    """The SAP entry points refuse a null context before any device work."""
+    lib = _lib()
+    vp = ctypes.c_void_p
+    lib.lq_sap_apply.argtypes = [vp, vp, vp, vp]
+    lib.lq_solve_sap.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 vp, vp]
+    params = (ctypes.c_int * 8)(4, 4, 4, 4, 0, 0, 0, 0)  # lq_sap_params: block[4] + 4 ints
+    buf = ctypes.create_string_buffer(64)
+    assert lib.lq_sap_apply(None, buf, buf, params) == -1
+    assert lib.lq_solve_sap(None, buf, buf, 0.13, 1.0, 1e-10, params, None) == -1
