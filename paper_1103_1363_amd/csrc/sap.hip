@@ -40,6 +40,12 @@ struct Sap {
   void* r64 = nullptr;  // FP64 full field
   double* part = nullptr;  // dot-product partials
   double* hpart = nullptr; // host copy (pinned)
+  void** wdev = nullptr;   // device arrays of the direction pointers (Gram-Schmidt)
+  void** zdev = nullptr;
+  double* mres = nullptr;  // batched dot products [64][2]
+  double* mpart = nullptr; // their workgroup partials [64][G][2], G = gs_groups()
+  float2* coef = nullptr;  // Gram-Schmidt coefficients [64]
+  float2* hcoef = nullptr; // host staging (pinned)
 };
 
 namespace {
@@ -324,6 +330,86 @@ __global__ __launch_bounds__(256) void sap_dot_kernel(const TA* __restrict__ a,
   block_partial<3>(v, part);
 }
 
+// Batched Gram-Schmidt.  Each thread keeps GS_E entries of x (or y) in
+// registers while it runs over the k earlier directions, so every field is
+// read once per call.
+constexpr int GS_E = 4;
+
+// part[(j G + b) 2 + c] = workgroup b's partial of <V_j, x> (c = re, im)
+__global__ __launch_bounds__(256) void sap_mdot_kernel(const float2* const* __restrict__ V, int k,
+                                                       const float2* __restrict__ x, int64_t n,
+                                                       int64_t per_half, int64_t vh,
+                                                       double* __restrict__ part) {
+  float2 xv[GS_E];
+  int64_t idx[GS_E];
+  bool live[GS_E];
+#pragma unroll
+  for (int e = 0; e < GS_E; ++e) {
+    idx[e] = ((int64_t)blockIdx.x * GS_E + e) * 256 + threadIdx.x;
+    live[e] = idx[e] < n && live_entry(idx[e], per_half, vh);
+    xv[e] = live[e] ? x[idx[e]] : make_float2(0.f, 0.f);
+  }
+  for (int j = 0; j < k; ++j) {
+    const float2* v = V[j];
+    double a[2] = {0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < GS_E; ++e)
+      if (live[e]) {
+        const float2 u = v[idx[e]];
+        a[0] += (double)u.x * xv[e].x + (double)u.y * xv[e].y;
+        a[1] += (double)u.x * xv[e].y - (double)u.y * xv[e].x;
+      }
+    block_partial_at<2>(a, part, (int64_t)j * gridDim.x + blockIdx.x);
+  }
+}
+
+// res[2 j + c] = sum over the G workgroup partials (one workgroup per j)
+__global__ __launch_bounds__(256) void sap_mdot_fin_kernel(const double* __restrict__ part, int G,
+                                                           double* __restrict__ res) {
+  __shared__ double sh[2][16];
+  const int j = blockIdx.x;
+  double a[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < G; b += blockDim.x) {
+    a[0] += part[((int64_t)j * G + b) * 2];
+    a[1] += part[((int64_t)j * G + b) * 2 + 1];
+  }
+  block_sum<2>(a, sh);
+  if (threadIdx.x == 0) {
+    res[2 * j] = a[0];
+    res[2 * j + 1] = a[1];
+  }
+}
+
+// y -= sum_j c_j V_j over the live entries
+__global__ __launch_bounds__(256) void sap_maxpy_kernel(float2* __restrict__ y,
+                                                        const float2* const* __restrict__ V,
+                                                        const float2* __restrict__ c, int k,
+                                                        int64_t n, int64_t per_half, int64_t vh) {
+  float2 yv[GS_E];
+  int64_t idx[GS_E];
+  bool live[GS_E];
+#pragma unroll
+  for (int e = 0; e < GS_E; ++e) {
+    idx[e] = ((int64_t)blockIdx.x * GS_E + e) * 256 + threadIdx.x;
+    live[e] = idx[e] < n && live_entry(idx[e], per_half, vh);
+    yv[e] = live[e] ? y[idx[e]] : make_float2(0.f, 0.f);
+  }
+  for (int j = 0; j < k; ++j) {
+    const float2 cj = c[j];
+    const float2* v = V[j];
+#pragma unroll
+    for (int e = 0; e < GS_E; ++e)
+      if (live[e]) {
+        const float2 u = v[idx[e]];
+        yv[e].x -= cj.x * u.x - cj.y * u.y;
+        yv[e].y -= cj.x * u.y + cj.y * u.x;
+      }
+  }
+#pragma unroll
+  for (int e = 0; e < GS_E; ++e)
+    if (live[e]) y[idx[e]] = yv[e];
+}
+
 // y = ca x + cb y on FP32 entries (complex ca, cb)
 __global__ void sap_caxpby_kernel(float2* __restrict__ y, float ar, float ai,
                                   const float2* __restrict__ x, float br, float bi, int64_t n) {
@@ -437,6 +523,44 @@ void caxpby(lq_ctx* ctx, void* y, std::complex<double> a, const void* x, std::co
   LQ_HIP(hipGetLastError());
 }
 
+// w -= sum_j <W_j, w> W_j and z -= (the same coefficients) Z_j over the k
+// earlier (orthonormal) directions, twice: classical Gram-Schmidt repeated,
+// which orthogonalises as well as the modified form at a fraction of the
+// launches and passes over memory.
+int gs_groups(const lq_ctx* ctx) { return grid_for(entries(ctx), 256 * GS_E); }
+
+void gram_schmidt(lq_ctx* ctx, int k, void* w, void* z) {
+  Sap* sp = ctx->sap;
+  const int64_t n = entries(ctx);
+  const int G = gs_groups(ctx);
+  LQ_CHECK(k >= 1 && k <= 64, LQ_EINVAL, "Gram-Schmidt over 1..64 directions");
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(sap_mdot_kernel, dim3(G), dim3(256), 0, ctx->cur,
+                       reinterpret_cast<const float2* const*>(sp->wdev), k,
+                       reinterpret_cast<const float2*>(w), n, n / 2, ctx->geo.vh, sp->mpart);
+    hipLaunchKernelGGL(sap_mdot_fin_kernel, dim3(k), dim3(256), 0, ctx->cur, sp->mpart, G,
+                       sp->mres);
+    LQ_HIP(hipGetLastError());
+    LQ_HIP(hipMemcpyAsync(sp->hpart, sp->mres, sizeof(double) * 2 * k, hipMemcpyDeviceToHost,
+                          ctx->cur));
+    LQ_HIP(hipStreamSynchronize(ctx->cur));
+    for (int j = 0; j < k; ++j)
+      sp->hcoef[j] = make_float2((float)sp->hpart[2 * j], (float)sp->hpart[2 * j + 1]);
+    LQ_HIP(hipMemcpyAsync(sp->coef, sp->hcoef, sizeof(float2) * k, hipMemcpyHostToDevice,
+                          ctx->cur));
+    const int Gx = grid_for(n, 256 * GS_E);
+    hipLaunchKernelGGL(sap_maxpy_kernel, dim3(Gx), dim3(256), 0, ctx->cur,
+                       reinterpret_cast<float2*>(w),
+                       reinterpret_cast<const float2* const*>(sp->wdev), sp->coef, k, n, n / 2,
+                       ctx->geo.vh);
+    hipLaunchKernelGGL(sap_maxpy_kernel, dim3(Gx), dim3(256), 0, ctx->cur,
+                       reinterpret_cast<float2*>(z),
+                       reinterpret_cast<const float2* const*>(sp->zdev), sp->coef, k, n, n / 2,
+                       ctx->geo.vh);
+    LQ_HIP(hipGetLastError());
+  }
+}
+
 SapBlocks blocks_of(const lq_ctx* ctx, const lq_sap_params& q) {
   SapBlocks sb;
   sb.vb = 1;
@@ -505,8 +629,11 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
 
 void sap_destroy(Sap* sp) {
   if (!sp) return;
-  for (void* p : {sp->a32[0], sp->a32[1], sp->r, sp->tmp, sp->xc, sp->r64, (void*)sp->part})
+  for (void* p : {sp->a32[0], sp->a32[1], sp->r, sp->tmp, sp->xc, sp->r64, (void*)sp->part,
+                  (void*)sp->wdev, (void*)sp->zdev, (void*)sp->mres, (void*)sp->mpart,
+                  (void*)sp->coef})
     if (p) (void)hipFree(p);
+  if (sp->hcoef) (void)hipHostFree(sp->hcoef);
   for (void* p : sp->z) (void)hipFree(p);
   for (void* p : sp->w) (void)hipFree(p);
   if (sp->hpart) (void)hipHostFree(sp->hpart);
@@ -538,6 +665,17 @@ bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_par
   }
   if (!sp->xc) LQ_HIP(hipMalloc(&sp->xc, f32));
   if (!sp->r64) LQ_HIP(hipMalloc(&sp->r64, f64));
+  if (!sp->wdev) {
+    LQ_HIP(hipMalloc(reinterpret_cast<void**>(&sp->wdev), 64 * sizeof(void*)));
+    LQ_HIP(hipMalloc(reinterpret_cast<void**>(&sp->zdev), 64 * sizeof(void*)));
+    LQ_HIP(hipMalloc(reinterpret_cast<void**>(&sp->mres), 64 * 2 * sizeof(double)));
+    LQ_HIP(hipMalloc(reinterpret_cast<void**>(&sp->mpart),
+                     (size_t)64 * gs_groups(ctx) * 2 * sizeof(double)));
+    LQ_HIP(hipMalloc(reinterpret_cast<void**>(&sp->coef), 64 * sizeof(float2)));
+    LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&sp->hcoef), 64 * sizeof(float2)));
+  }
+  LQ_HIP(hipMemcpy(sp->wdev, sp->w.data(), sp->w.size() * sizeof(void*), hipMemcpyHostToDevice));
+  LQ_HIP(hipMemcpy(sp->zdev, sp->z.data(), sp->z.size() * sizeof(void*), hipMemcpyHostToDevice));
   const int64_t n = entries(ctx);
   double d[3];
   dot3<double2, double2>(ctx, b, b, d);
@@ -572,12 +710,7 @@ bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_par
       for (int k = 0; k < m && iters < maxiter; ++k) {
         sap_apply_impl(ctx, sp->z[k], rho, q);
         full_m<P32, false>(ctx, sp->w[k], nullptr, sp->z[k]);
-        for (int j = 0; j < k; ++j) {
-          dot3<float2, float2>(ctx, sp->w[j], sp->w[k], d);
-          const std::complex<double> beta(d[0], d[1]);
-          caxpby(ctx, sp->w[k], -beta, sp->w[j], 1.0);
-          caxpby(ctx, sp->z[k], -beta, sp->z[j], 1.0);
-        }
+        if (k > 0) gram_schmidt(ctx, k, sp->w[k], sp->z[k]);
         dot3<float2, float2>(ctx, sp->w[k], sp->w[k], d);
         const double wn = std::sqrt(d[2]);
         if (!(wn > 0.0) || !std::isfinite(wn)) break;
