@@ -13,7 +13,8 @@
 // All of it is FP32 on full-lattice fields (even half, then odd half).
 //
 // FGCR: right-preconditioned GCR, z_k = K r, w_k = M z_k orthonormalised by
-// modified Gram-Schmidt against the earlier w (the z transformed alike),
+// Gram-Schmidt against the earlier w (classical, applied twice; the z
+// transformed alike),
 // x += <w_k, r> z_k; the recursion restarts every `restart` steps, where the
 // residual is recomputed in FP64 and the FP32 correction added to the FP64
 // solution (iterative refinement, as the paper describes).
