@@ -104,3 +104,46 @@ def test_fgcr_with_sap_matches_direct_solve():
     # the preconditioner pays: fewer steps than plain GCR
     _, plain = sap.fgcr(wc.M, b, lambda v: v, m=8, tol=1e-10)
     assert info.iterations < plain.iterations
+
+
+@pytest.mark.parametrize("nmr", [1, 3])
+def test_even_odd_block_mr_against_dense_schur(nmr):
+    """MR on the even-odd reduced block operator, against dense MR on the
+    Schur complement of each block submatrix of the brute-force matrix, with
+    the odd sites reconstructed densely."""
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    kappa = 0.13
+    u = fields.gauge_field(dims, "smooth", 219)
+    r = fields.gaussian_spinor(dims, 220)
+    wc, mat = full_matrix(u, dims, kappa, 1.0)
+    bid, colour = sap.block_layout(dims, block)
+    nblocks = int(bid.max()) + 1
+    odd = evenodd.odd_mask(dims).reshape(-1)
+    for c in (0, 1):
+        got = sap.mr_blocks_eo(wc, r, colour == c, bid, nblocks, nmr,
+                               evenodd.odd_mask(dims)).reshape(-1)
+        flat_r = r.reshape(-1)
+        ref = np.zeros_like(flat_r)
+        for b in range(nblocks):
+            sites = np.nonzero(bid.reshape(-1) == b)[0]
+            if colour.reshape(-1)[sites[0]] != c:
+                continue
+            se, so = sites[~odd[sites]], sites[odd[sites]]
+            ie = (se[:, None] * 12 + np.arange(12)[None, :]).reshape(-1)
+            io = (so[:, None] * 12 + np.arange(12)[None, :]).reshape(-1)
+            mee = mat[ie][:, ie].toarray()
+            meo = mat[ie][:, io].toarray()
+            moe = mat[io][:, ie].toarray()
+            moo = mat[io][:, io].toarray()
+            mooi = np.linalg.inv(moo)
+            schur = mee - meo @ mooi @ moe
+            rho = flat_r[ie] - meo @ mooi @ flat_r[io]
+            de = np.zeros_like(rho)
+            for _ in range(nmr):
+                q = schur @ rho
+                alpha = np.vdot(q, rho) / np.vdot(q, q)
+                de += alpha * rho
+                rho -= alpha * q
+            ref[ie] = de
+            ref[io] = mooi @ (flat_r[io] - moe @ de)
+        assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
