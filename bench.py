@@ -26,6 +26,11 @@ Printed (one JSON line):
                 (source, solution) pairs the solver generated on a 16^3x32
                 field, then used on the benchmark's 32^3x64 field in flexible
                 CG and FGMRES, beside the plain solves of the same system;
+  uneven_batch  eight lattices of different volumes and kappas solved as one
+                batch, beside the same solves one after another;
+  sap_fgcr      the paper's own solver on the benchmark system: FGCR with the
+                SAP preconditioner (FP32 block MR, FP64 restarts), and one SAP
+                application alone;
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample.
 
 roofline.traffic is the HBM traffic per launch of the roofline kernel from
