@@ -27,8 +27,16 @@ upstream g = dL/d conj(y),
     dL/d conj(psi) = sum_k T_k^dagger W_k^dagger g,
 and the real gradients are dL/dRe W = 2 Re(dL/d conj W), dL/dIm W = 2 Im(...).
 
+Training uses Adam (Kingma and Ba's published rule) on the real parameters
+(Re W, Im W) with the real gradient above: first and second moment averages
+with decay rates beta1, beta2, both divided by their bias factors
+(1 - beta^t) at step t, and the step lr * m_hat / (sqrt(v_hat) + eps).
+
 Pins (CPU tests): the Neumann identity against the hopping term; central
-finite differences of the loss; gauge equivariance N[U'](g psi) = g N[U] psi.
+finite differences of the loss; gauge equivariance N[U'](g psi) = g N[U] psi;
+Adam against its closed forms (a constant gradient gives steps of exactly
+lr * |g| / (|g| + eps) at every t; two steps give the bias-corrected weighted
+means (beta g1 + g2) / (1 + beta) of the gradients and of their squares).
 """
 from __future__ import annotations
 
@@ -122,3 +130,28 @@ def loss_and_grad(u, weights, sources_e, targets_e, dims, antiperiodic_t=True):
         gw, _ = backward(u, weights, acts, g_full, antiperiodic_t)
         grads += gw
     return loss, grads
+
+
+class Adam:
+    """Adam on complex weights W, taken as the real parameters (Re W, Im W).
+
+    step(w, g) takes the Wirtinger gradient g = dL/d conj(W); the real
+    gradient is (2 Re g, 2 Im g).  Moments start at zero, the step counter at
+    0; step t (1, 2, ...) divides the moments by (1 - beta1^t) and
+    (1 - beta2^t)."""
+
+    def __init__(self, shape, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        self.m = np.zeros(shape + (2,))
+        self.v = np.zeros(shape + (2,))
+        self.t = 0
+
+    def step(self, w, g):
+        gr = np.stack([2.0 * g.real, 2.0 * g.imag], axis=-1)
+        self.t += 1
+        self.m = self.beta1 * self.m + (1.0 - self.beta1) * gr
+        self.v = self.beta2 * self.v + (1.0 - self.beta2) * gr * gr
+        mhat = self.m / (1.0 - self.beta1 ** self.t)
+        vhat = self.v / (1.0 - self.beta2 ** self.t)
+        d = self.lr * mhat / (np.sqrt(vhat) + self.eps)
+        return w - (d[..., 0] + 1j * d[..., 1])

@@ -40,6 +40,11 @@ Pins (tests/test_oracle_sap.py):
   complement of those submatrices;
 * the Schwarz property: after a half cycle with converged block solves, the
   residual vanishes on the solved blocks;
+* the multiplicative structure: one cycle with converged block solves equals
+  the dense block Gauss-Seidel sweep psi_0 = M_00^-1 eta_0,
+  psi_1 = M_11^-1 (eta_1 - M_10 psi_0), and several cycles of few MR steps
+  equal the procedure run block by block on dense submatrices (an additive
+  variant fails both);
 * M = 1 gives K = 1 exactly;
 * FGCR against a direct sparse solve.
 """

@@ -20,7 +20,9 @@ Every solver stops on the true residual ||b - A x|| / ||b|| <= tol computed
 from the operator, never on a recurrence value alone.  Functions take
 callables on NumPy arrays of any shape.
 
-Pin (CPU tests): dense LU solutions on 2^4 and 4^4 lattices.
+Pins (CPU tests): dense LU solutions on 2^4 and 4^4 lattices; fcg with a
+preconditioner that changes at every call against the direct solve of the
+dense normal Schur operator.
 """
 from __future__ import annotations
 

@@ -291,6 +291,7 @@ void build_clover(lq_ctx* ctx, double kappa, double csw) {
   c.kappa = kappa;
   c.csw = csw;
   c.valid = true;
+  ++c.gen;
   ctx->mr_clov_ok = false;
 }
 

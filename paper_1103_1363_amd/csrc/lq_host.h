@@ -17,6 +17,10 @@ struct Clover {
   void* ainv_oo[3] = {nullptr, nullptr, nullptr};
   double kappa = 0, csw = 0;
   bool valid = false;
+  // Incremented by every build: caches derived from the clover tables (the
+  // SAP solver's FP32 copy) compare it instead of (kappa, csw), which stay
+  // equal when a new gauge field is uploaded.
+  uint64_t gen = 0;
 };
 
 struct Work;    // solver work space (solver.hip)

@@ -8,8 +8,9 @@
 // turn (0 first), takes nmr minimal-residual steps on every block of that
 // colour with Dirichlet boundary conditions (hops that leave the block are
 // dropped) and then recomputes the residual r = eta - M psi on the whole
-// lattice.  One workgroup solves one block: the block's residual lives in
-// LDS (one site per thread), the links and clover blocks stream from HBM.
+// lattice.  One workgroup solves one block: the block's residual and its
+// links are copied into LDS once per launch (one site per thread); the
+// clover blocks stream from HBM.
 // All of it is FP32 on full-lattice fields (even half, then odd half).
 //
 // FGCR: right-preconditioned GCR, z_k = K r, w_k = M z_k orthonormalised by
@@ -33,7 +34,7 @@ namespace lq {
 
 struct Sap {
   void* a32[2] = {nullptr, nullptr};  // FP32 clover blocks A of each parity
-  double kappa = -1.0, csw = -1.0;
+  uint64_t clov_gen = 0;               // clover build they were copied from (0: none)
   void* r = nullptr;    // residual (FP32 full field)
   void* tmp = nullptr;  // FP32 full field
   std::vector<void*> z, w;                 // FGCR directions (FP32 full fields)
@@ -422,16 +423,20 @@ __global__ void sap_caxpby_kernel(float2* __restrict__ y, float ar, float ai,
 }
 
 // FP64 -> FP32 and FP64 += FP32, entrywise
-__global__ void sap_to32_kernel(float2* __restrict__ out, const double2* __restrict__ in, int64_t n) {
+// out = s * in, rounded to FP32 (s = 1 / |in| keeps any FP64 magnitude in range)
+__global__ void sap_to32_kernel(float2* __restrict__ out, const double2* __restrict__ in,
+                                double s, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
+  if (i < n) out[i] = make_float2((float)(s * in[i].x), (float)(s * in[i].y));
 }
-__global__ void sap_add64_kernel(double2* __restrict__ y, const float2* __restrict__ x, int64_t n) {
+// y += s * x
+__global__ void sap_add64_kernel(double2* __restrict__ y, const float2* __restrict__ x,
+                                 double s, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     double2 v = y[i];
-    v.x += x[i].x;
-    v.y += x[i].y;
+    v.x += s * (double)x[i].x;
+    v.y += s * (double)x[i].y;
     y[i] = v;
   }
 }
@@ -463,14 +468,13 @@ Sap* sap_state(lq_ctx* ctx) {
     LQ_HIP(hipMalloc(&sp->part, DOT_BLOCKS * 3 * sizeof(double)));
     LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&sp->hpart), DOT_BLOCKS * 3 * sizeof(double)));
   }
-  if (sp->kappa != ctx->clov.kappa || sp->csw != ctx->clov.csw) {
+  if (sp->clov_gen != ctx->clov.gen) {
     for (int p = 0; p < 2; ++p)
       hipLaunchKernelGGL(sap_a32_kernel, dim3(grid_for(ncl, 256)), dim3(256), 0, ctx->cur,
                          reinterpret_cast<const double2*>(ctx->clov.a64[p]),
                          reinterpret_cast<float2*>(sp->a32[p]), ncl);
     LQ_HIP(hipGetLastError());
-    sp->kappa = ctx->clov.kappa;
-    sp->csw = ctx->clov.csw;
+    sp->clov_gen = ctx->clov.gen;
   }
   return sp;
 }
@@ -689,6 +693,11 @@ bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_par
     conv = true;
   } else {
     void* rho = sp->tmp;
+    // Stall guard: a cycle that takes no step, or kStall restarts in a row
+    // that do not halve the best FP64 residual, end the solve unconverged.
+    constexpr int kStall = 5;
+    double best = INFINITY;
+    int stalled = 0;
     for (;;) {
       full_m<P64, true>(ctx, sp->r64, b, x);
       dot3<double2, double2>(ctx, sp->r64, sp->r64, d);
@@ -698,16 +707,26 @@ bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_par
         break;
       }
       if (iters >= maxiter || !std::isfinite(res)) break;
+      if (res <= 0.5 * best) {
+        best = res;
+        stalled = 0;
+      } else if (++stalled >= kStall) {
+        break;
+      }
       ++restarts;
+      // The FP32 cycle solves for the normalised residual r / |r|, so that
+      // residuals far outside FP32's range (tiny or huge sources) still
+      // convert; the correction is scaled back by |r| in FP64.
+      const double rn = std::sqrt(d[2]);
       hipLaunchKernelGGL(sap_to32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
                          reinterpret_cast<float2*>(rho),
-                         reinterpret_cast<const double2*>(sp->r64), n);
+                         reinterpret_cast<const double2*>(sp->r64), 1.0 / rn, n);
       LQ_HIP(hipGetLastError());
       fill_zero(ctx, sp->xc, f32);
-      const double rn0 = std::sqrt(d[2]);
       // an FP32 cycle is trusted down to about 1e-5 of its start; the last
       // stops at what the FP64 residual still needs (with a margin of 2)
       const double cycle = std::max(1e-5, 0.5 * tol / res);
+      const int iters0 = iters;
       for (int k = 0; k < m && iters < maxiter; ++k) {
         sap_apply_impl(ctx, sp->z[k], rho, q);
         full_m<P32, false>(ctx, sp->w[k], nullptr, sp->z[k]);
@@ -723,11 +742,12 @@ bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_par
         caxpby(ctx, rho, -al, sp->w[k], 1.0);
         ++iters;
         dot3<float2, float2>(ctx, rho, rho, d);
-        if (std::sqrt(d[2]) <= cycle * rn0) break;
+        if (std::sqrt(d[2]) <= cycle) break;
       }
+      if (iters == iters0) break;  // breakdown at the cycle's first direction
       hipLaunchKernelGGL(sap_add64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
                          reinterpret_cast<double2*>(x), reinterpret_cast<const float2*>(sp->xc),
-                         n);
+                         rn, n);
       LQ_HIP(hipGetLastError());
     }
   }

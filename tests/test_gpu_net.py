@@ -171,6 +171,8 @@ def test_net_loss_grad_parity(lq, dims):
 
 
 def test_adam_step(lq):
+    """Three consecutive GPU Adam steps (moments accumulated, bias factors at
+    t = 1, 2, 3) against the oracle's Adam fed the same gradients."""
     dims = (4, 4, 4, 4)
     u, _, _, _ = case(dims, "smooth", 1)
     lat = lq.Lattice(dims)
@@ -178,25 +180,19 @@ def test_adam_step(lq):
     w = random_weights(2, 14, scale=0.2)
     net = lq.Net(lat, 2)
     net.set_weights(w)
-    b, x = even_fields(dims, 1, 8), even_fields(dims, 1, 9)
+    b, x = even_fields(dims, 2, 8), even_fields(dims, 2, 9)
     db, dx = lat.to_device(b, lq.EVEN, lq.F32), lat.to_device(x, lq.EVEN, lq.F32)
-    _, g = net.loss_grad(db, dx, 1)
-    w0 = net.get_weights()
     lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
-    net.adam_step(lr, b1, b2, eps)
-    # Adam on the real parameters with gradient 2 Re g, 2 Im g, first step
-    out = np.empty_like(w0)
-    for part, sel in ((np.real, 0), (np.imag, 1)):
-        gr = 2 * part(g)
-        m = (1 - b1) * gr
-        v = (1 - b2) * gr * gr
-        step = lr * (m / (1 - b1)) / (np.sqrt(v / (1 - b2)) + eps)
-        if sel == 0:
-            out.real = w0.real - step
-        else:
-            out.imag = w0.imag - step
-    got = net.get_weights()
-    assert np.max(np.abs(got - out)) <= 1e-6
+    opt = onet.Adam(w.shape, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    ref = net.get_weights()
+    for t in range(3):
+        # alternate the pair so that the gradients differ from step to step
+        _, g = net.loss_grad(db, dx, 2) if t % 2 == 0 else net.loss_grad(db, dx, 1)
+        ref = opt.step(ref, g)
+        net.adam_step(lr, b1, b2, eps)
+        got = net.get_weights()
+        assert np.max(np.abs(got - ref)) <= 2e-6, t
+        ref = got  # continue from the FP32 weights the GPU holds
 
 
 def oracle_residual(u, kappa, csw, x, b):

@@ -124,3 +124,53 @@ def test_full_size_sap_fgcr(lq):
     rs = sampled_residuals(u, kappa, csw, x, b, [], 24, 303)
     say(f"  largest sampled site residual {max(rs):.2e} (bound {bound:.2e})")
     assert max(rs) <= 1.01 * bound
+
+
+def test_sap_after_gauge_reupload(lq):
+    """A second gauge field on the same context at the same (kappa, csw):
+    the SAP block solves and FGCR's FP32 operator use the new clover term
+    (its FP32 copy is rebuilt with every clover build, not keyed on kappa and
+    csw alone)."""
+    dims, block = (8, 4, 4, 8), (4, 2, 2, 4)
+    say("sap after gauge re-upload")
+    u1 = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 34)
+    u2 = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 35)
+    eta = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 34)
+    lat = lq.Lattice(dims)
+    din = lat.to_device(eta, lq.FULL, lq.F32)
+    dout = lat.new_field(lq.FULL, lq.F32)
+    for u in (u1, u2):
+        lat.upload_gauge(u)
+        lat.set_clover(KAPPA, CSW)
+        lat.sap_apply(dout, din, block, 2, 4)
+        wc = evenodd.WilsonClover(u, KAPPA, CSW)
+        ref = sap.sap(wc.M, eta, dims, block, 2, 4)
+        got = lat.to_host(dout, lq.FULL, lq.F32).reshape(ref.shape)
+        assert rel(got, ref) <= 1e-4
+    # and a solve on the re-uploaded field without an explicit set_clover
+    lat.upload_gauge(u1)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 35)
+    x, rep = lat.solve_sap(b, KAPPA, CSW, 1e-10, block, ncycles=2, nmr=4, restart=16)
+    wc = evenodd.WilsonClover(u1, KAPPA, CSW)
+    assert dirac.norm(b - wc.M(x)) <= 1e-10 * dirac.norm(b)
+
+
+@pytest.mark.parametrize("scale", [1e-42, 1e40])
+def test_solve_sap_extreme_source_scales(lq, scale):
+    """Sources whose entries underflow or overflow FP32: the FP32 cycles work
+    on the residual divided by its norm, so the solve converges as for a
+    source of unit size."""
+    dims, block = (8, 4, 4, 8), (4, 2, 2, 4)
+    say(f"sap-fgcr source scale {scale:g}")
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 36)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 36)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    x1, rep1 = lat.solve_sap(b, KAPPA, CSW, 1e-10, block, ncycles=2, nmr=4, restart=16)
+    xs, reps = lat.solve_sap(scale * b, KAPPA, CSW, 1e-10, block, ncycles=2, nmr=4,
+                             restart=16)
+    wc = evenodd.WilsonClover(u, KAPPA, CSW)
+    bs = scale * b
+    assert dirac.norm(bs - wc.M(xs)) <= 1e-10 * dirac.norm(bs)
+    assert reps.iterations <= rep1.iterations + 4
+    assert rel(xs / scale, x1) <= 1e-7

@@ -104,3 +104,58 @@ def test_net_gauge_equivariance():
     lhs = net.forward(gauge_rotate(u, g), w, dirac.colour_mul(g, psi))[-1]
     rhs = dirac.colour_mul(g, net.forward(u, w, psi)[-1])
     assert dirac.norm(lhs - rhs) <= 1e-13 * dirac.norm(rhs)
+
+
+def test_adam_constant_gradient_closed_form():
+    """With the same gradient at every step the bias-corrected moments are
+    exactly g and g^2, so every step moves each real parameter by
+    lr * |g| / (|g| + eps) against the sign of its gradient, for any t (a
+    missing or wrong bias correction changes the steps with t)."""
+    g = np.array([[0.3 - 2.0j, -1e-3 + 0.7j]])
+    w0 = np.array([[1.0 + 1.0j, -0.5 + 0.25j]])
+    lr, eps = 0.01, 1e-8
+    opt = net.Adam(w0.shape, lr=lr, beta1=0.9, beta2=0.999, eps=eps)
+    w = w0.copy()
+    for t in range(1, 8):
+        w = opt.step(w, g)
+        gr, gi = 2 * g.real, 2 * g.imag
+        ref = w0 - t * lr * (gr / (np.abs(gr) + eps) + 1j * gi / (np.abs(gi) + eps))
+        assert np.max(np.abs(w - ref)) <= 1e-14, t
+
+
+def test_adam_two_steps_are_weighted_means():
+    """After gradients g1, g2 the bias-corrected moments are the normalised
+    weighted means (b1 g1 + g2) / (1 + b1) and (b2 g1^2 + g2^2) / (1 + b2)
+    of the real gradients; the second step is lr times their quotient."""
+    rng = fields.rng(270)
+    g1 = fields.complex_gaussian(rng, (2, 3))
+    g2 = fields.complex_gaussian(rng, (2, 3))
+    w0 = fields.complex_gaussian(rng, (2, 3))
+    b1, b2, lr, eps = 0.8, 0.95, 0.05, 1e-8
+    opt = net.Adam(w0.shape, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    w1 = opt.step(w0, g1)
+    w2 = opt.step(w1, g2)
+    for part, unit in ((np.real, 1.0), (np.imag, 1j)):
+        a1, a2 = 2 * part(g1), 2 * part(g2)
+        step1 = lr * a1 / (np.abs(a1) + eps)
+        mhat = (b1 * a1 + a2) / (1 + b1)
+        vhat = (b2 * a1 * a1 + a2 * a2) / (1 + b2)
+        step2 = lr * mhat / (np.sqrt(vhat) + eps)
+        assert np.max(np.abs(part(w2) - (part(w0) - step1 - step2))) <= 1e-14
+    # the moments are rescaled by their bias factors, not carried raw
+    assert opt.t == 2
+
+
+def test_adam_is_invariant_to_gradient_scale():
+    """Adam's steps do not depend on a positive scale of the gradients (up to
+    eps): 1e3 g and g give the same trajectory."""
+    rng = fields.rng(271)
+    gs = [fields.complex_gaussian(rng, (4,)) for _ in range(5)]
+    w0 = fields.complex_gaussian(rng, (4,))
+    a = net.Adam(w0.shape, lr=0.02, eps=1e-12)
+    b = net.Adam(w0.shape, lr=0.02, eps=1e-12)
+    wa, wb = w0.copy(), w0.copy()
+    for g in gs:
+        wa = a.step(wa, g)
+        wb = b.step(wb, 1e3 * g)
+    assert np.max(np.abs(wa - wb)) <= 1e-12

@@ -147,3 +147,101 @@ def test_even_odd_block_mr_against_dense_schur(nmr):
             ref[ie] = de
             ref[io] = mooi @ (flat_r[io] - moe @ de)
         assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def _colour_blocks(dims, block, colour_id):
+    """Per block of the colour: its sites' 12-component matrix indices."""
+    bid, colour = sap.block_layout(dims, block)
+    out = []
+    for b in range(int(bid.max()) + 1):
+        sites = np.nonzero(bid.reshape(-1) == b)[0]
+        if colour.reshape(-1)[sites[0]] == colour_id:
+            out.append((sites[:, None] * 12 + np.arange(12)[None, :]).reshape(-1))
+    return out
+
+
+def _dense_sap(mat, eta, dims, block, ncy, nmr):
+    """The Schwarz alternating procedure written on the brute-force matrix:
+    per cycle and colour (0 first), dense MR (nmr steps, or a direct solve
+    when nmr is None) on each block submatrix with the current residual as
+    source, then the residual recomputed with the whole matrix."""
+    m = mat.toarray()
+    eta = eta.reshape(-1)
+    psi = np.zeros_like(eta)
+    r = eta.copy()
+    for _ in range(ncy):
+        for c in (0, 1):
+            for idx in _colour_blocks(dims, block, c):
+                mb = m[np.ix_(idx, idx)]
+                if nmr is None:
+                    psi[idx] += np.linalg.solve(mb, r[idx])
+                    continue
+                rho = r[idx].copy()
+                for _ in range(nmr):
+                    q = mb @ rho
+                    alpha = np.vdot(q, rho) / np.vdot(q, q)
+                    psi[idx] += alpha * rho
+                    rho -= alpha * q
+            r = eta - m @ psi
+    return psi
+
+
+def _additive_sap(op, eta, dims, block, ncy, nmr):
+    """A plausible mistake: both colours solved against the same residual
+    (additive Schwarz) instead of the second against the residual the first
+    left.  Used only to show that the pins below tell the two apart."""
+    bid, colour = sap.block_layout(dims, block)
+    nblocks = int(bid.max()) + 1
+    psi = np.zeros_like(eta)
+    r = eta.copy()
+    for _ in range(ncy):
+        d0 = sap.mr_blocks(op, r, colour == 0, bid, nblocks, nmr)
+        d1 = sap.mr_blocks(op, r, colour == 1, bid, nblocks, nmr)
+        psi = psi + d0 + d1
+        r = eta - op(psi)
+    return psi
+
+
+def test_sap_cycle_is_block_gauss_seidel():
+    """One cycle with converged block solves is one multiplicative block
+    Gauss-Seidel sweep over the two colours (section 5: the second colour is
+    solved with the residual the first left):
+        psi_0 = M_00^-1 eta_0,   psi_1 = M_11^-1 (eta_1 - M_10 psi_0),
+    with M_cc block diagonal over the blocks of colour c (two blocks of one
+    colour never touch).  Built here from the brute-force matrix by dense
+    solves; an additive variant misses it by far."""
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    u = fields.gauge_field(dims, "smooth", 281)
+    eta = fields.gaussian_spinor(dims, 282)
+    wc, mat = full_matrix(u, dims, 0.12, 1.0)
+    m = mat.toarray()
+    e = eta.reshape(-1)
+    idx0 = np.concatenate(_colour_blocks(dims, block, 0))
+    idx1 = np.concatenate(_colour_blocks(dims, block, 1))
+    psi0 = np.linalg.solve(m[np.ix_(idx0, idx0)], e[idx0])
+    psi1 = np.linalg.solve(m[np.ix_(idx1, idx1)], e[idx1] - m[np.ix_(idx1, idx0)] @ psi0)
+    ref = np.zeros_like(e)
+    ref[idx0], ref[idx1] = psi0, psi1
+    # the block-by-block dense procedure agrees with the two-colour closed form
+    dense = _dense_sap(mat, eta, dims, block, 1, None)
+    assert np.linalg.norm(dense - ref) <= 1e-12 * np.linalg.norm(ref)
+    got = sap.sap(wc.M, eta, dims, block, ncy=1, nmr=300).reshape(-1)
+    assert np.linalg.norm(got - ref) <= 1e-9 * np.linalg.norm(ref)
+    add = _additive_sap(wc.M, eta, dims, block, ncy=1, nmr=300).reshape(-1)
+    assert np.linalg.norm(add - ref) >= 1e-2 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("ncy,nmr", [(2, 2), (3, 1)])
+def test_sap_cycles_against_dense_block_mr(ncy, nmr):
+    """Several cycles of few MR steps, against the same procedure run block by
+    block with dense submatrices of the brute-force matrix; the additive
+    variant fails the same comparison."""
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    u = fields.gauge_field(dims, "smooth", 283)
+    eta = fields.gaussian_spinor(dims, 284)
+    wc, mat = full_matrix(u, dims, 0.13, 1.0)
+    ref = _dense_sap(mat, eta, dims, block, ncy, nmr)
+    got = sap.sap(wc.M, eta, dims, block, ncy=ncy, nmr=nmr).reshape(-1)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    add = _additive_sap(wc.M, eta, dims, block, ncy=ncy, nmr=nmr).reshape(-1)
+    assert np.linalg.norm(add - ref) >= 1e-2 * np.linalg.norm(ref)

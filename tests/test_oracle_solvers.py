@@ -121,3 +121,41 @@ def test_reconstruct_solves_full_system():
     x, info = solvers.solve_evenodd(wc, b, tol=1e-10)
     assert info.converged
     assert dirac.norm(b - wc.M(x)) <= 1e-10 * dirac.norm(b)
+
+
+def test_fcg_with_varying_preconditioner_against_direct_solve():
+    """The flexible branch of fcg (beta = -<q_prev, z> / <p_prev, q_prev>)
+    with a preconditioner that changes at every call: a random positive
+    diagonal drawn afresh each time (Hermitian positive definite, so flexible
+    CG must converge).  The operator is the normal Schur operator built
+    densely from the brute-force matrix, and the answer its direct solve."""
+    from tests import bruteforce
+    dims, kappa = (4, 4, 2, 4), 0.12
+    u = fields.gauge_field(dims, "haar", 291)
+    wc = evenodd.WilsonClover(u, kappa, 0.0)
+    m = (bruteforce.clover_block_matrix(wc.a.reshape(-1, 12, 12))
+         - kappa * bruteforce.hopping_matrix(u, dims)).toarray()
+    odd = bruteforce.parity_of_sites(dims).astype(bool)
+    comp = np.repeat(odd, 12)
+    ie, io = np.nonzero(~comp)[0], np.nonzero(comp)[0]
+    mhat = (m[np.ix_(ie, ie)]
+            - m[np.ix_(ie, io)] @ np.linalg.solve(m[np.ix_(io, io)], m[np.ix_(io, ie)]))
+    a = mhat.conj().T @ mhat
+    rng = fields.rng(292)
+    b = fields.complex_gaussian(rng, (ie.size,))
+    calls = [0]
+
+    def prec(v):
+        calls[0] += 1
+        d = fields.rng(300 + calls[0]).uniform(0.3, 3.0, v.size)
+        return d * v
+
+    x, info = solvers.fcg(lambda v: a @ v, b, precond=prec, tol=1e-12)
+    assert info.converged
+    assert calls[0] == info.iterations
+    xr = np.linalg.solve(a, b)
+    cond = np.linalg.cond(a)
+    assert np.linalg.norm(x - xr) <= 10 * cond * 1e-12 * np.linalg.norm(xr)
+    # the varying preconditioner was used: the iterates differ from plain CG
+    x1, info1 = solvers.fcg(lambda v: a @ v, b, tol=1e-12)
+    assert info1.iterations != info.iterations or np.linalg.norm(x1 - x) > 0
