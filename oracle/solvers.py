@@ -14,7 +14,10 @@ Recurrences are not printed in the paper; the textbook forms are used:
 * fgmres:   right-preconditioned restarted FGMRES(m), modified Gram-Schmidt
             Arnoldi, true residual recomputed at every restart;
 * fcg:      flexible (Notay) preconditioned CG on a Hermitian positive
-            definite operator.
+            definite operator;
+* fgmres_dr: FGMRES with deflated restarting (section 7 of the paper, after
+            Morgan's GMRES-DR): k harmonic Ritz vectors of smallest modulus
+            are carried across each restart.
 
 Every solver stops on the true residual ||b - A x|| / ||b|| <= tol computed
 from the operator, never on a recurrence value alone.  Functions take
@@ -22,7 +25,11 @@ callables on NumPy arrays of any shape.
 
 Pins (CPU tests): dense LU solutions on 2^4 and 4^4 lattices; fcg with a
 preconditioner that changes at every call against the direct solve of the
-dense normal Schur operator.
+dense normal Schur operator; fgmres_dr against the dense Schur solve, equal
+to fgmres for k = 0, with the flexible Arnoldi relation after each deflated
+restart, and deflating a known set of small eigenvalues; harmonic Ritz
+values exact on an invariant subspace and satisfying their Petrov-Galerkin
+condition.
 """
 from __future__ import annotations
 
@@ -233,3 +240,114 @@ def solve_evenodd(wc, b_full, tol=1e-10, method="cgnr", maxiter=20000):
             break
         t *= 0.5
     return x, SolveInfo(iterations=iters, converged=res <= tol, true_residual=res)
+
+
+def harmonic_ritz(hbar, k):
+    """The k harmonic Ritz pairs of smallest modulus from an (j+1) x j
+    upper Hessenberg Arnoldi matrix hbar (A Z_j = V_{j+1} hbar): the
+    eigenpairs of H_j + |h_{j+1,j}|^2 f e_j^dagger with f = H_j^-dagger e_j
+    (H_j the square top of hbar).  Returns (theta[k], G[j, k])."""
+    j = hbar.shape[1]
+    hm = hbar[:j, :j]
+    ej = np.zeros(j, dtype=np.complex128)
+    ej[-1] = 1.0
+    f = np.linalg.solve(hm.conj().T, ej)
+    g = hm + abs(hbar[j, j - 1]) ** 2 * np.outer(f, ej)
+    theta, vecs = np.linalg.eig(g)
+    order = np.argsort(np.abs(theta))[:k]
+    return theta[order], vecs[:, order]
+
+
+def fgmres_dr(op, b, precond=None, m=32, k=0, tol=1e-10, maxiter=10000, x0=None,
+              on_restart=None):
+    """Right-preconditioned flexible GMRES with deflated restarting (Morgan's
+    GMRES-DR with the flexible Arnoldi relation A Z_m = V_{m+1} Hbar_m).
+
+    m is the largest subspace dimension, including the k deflated vectors.
+    A cycle runs the Arnoldi process (modified Gram-Schmidt) to m columns,
+    solves the small least-squares problem min |c - Hbar y| and updates
+    x += Z y.  Without deflation (k = 0, or after a cycle that stopped early)
+    the next cycle starts afresh from the residual.  With deflation:
+      1. the k harmonic Ritz vectors g_i of smallest |theta| (harmonic_ritz);
+      2. P_{k+1}: orthonormalise [g_1 .. g_k] (a zero appended to each) and
+         then the least-squares residual s = c - Hbar y;
+      3. V <- V_{m+1} P_{k+1}, Z <- Z_m P_k (P_k = the top m rows of the
+         first k columns), Hbar <- P_{k+1}^dagger Hbar_m P_k, c <- P_{k+1}^dagger s;
+      4. the Arnoldi process continues from column k.
+    The stopping test is the true residual |b - op x| / |b| <= tol at the end
+    of every cycle.  on_restart(V, Z, hbar), if given, sees the basis after
+    each deflated restart (for tests of A Z_k = V_{k+1} Hbar_k)."""
+    if precond is None:
+        precond = lambda v: v  # noqa: E731
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    bnorm = norm(b)
+    info = SolveInfo()
+    if bnorm == 0.0:
+        info.converged, info.true_residual = True, 0.0
+        return x, info
+    total = 0
+    vs = zs = None
+    h = c = None
+    j0 = 0
+    while True:
+        if j0 == 0:  # fresh start from the residual
+            r = b - op(x)
+            beta = norm(r)
+            vs, zs = [r / beta], []
+            h = np.zeros((m + 1, m), dtype=np.complex128)
+            c = np.zeros(m + 1, dtype=np.complex128)
+            c[0] = beta
+        jend = j0
+        broke = False
+        for j in range(j0, m):
+            z = precond(vs[j])
+            zs.append(z)
+            w = op(z)
+            for i in range(j + 1):
+                h[i, j] = inner(vs[i], w)
+                w = w - h[i, j] * vs[i]
+            h[j + 1, j] = norm(w)
+            jend = j + 1
+            total += 1
+            y, *_ = np.linalg.lstsq(h[: j + 2, : j + 1], c[: j + 2], rcond=None)
+            est = norm(c[: j + 2] - h[: j + 2, : j + 1] @ y)
+            if h[j + 1, j].real == 0.0 or est <= 0.5 * tol * bnorm or total >= maxiter:
+                broke = True
+                break
+            vs.append(w / h[j + 1, j])
+        hb = h[: jend + 1, :jend]
+        y, *_ = np.linalg.lstsq(hb, c[: jend + 1], rcond=None)
+        for i in range(jend):
+            x = x + y[i] * zs[i]
+        res = norm(b - op(x)) / bnorm
+        info.history.append(res)
+        info.true_residual = res
+        if res <= tol:
+            info.converged = True
+            break
+        if total >= maxiter:
+            break
+        if k == 0 or broke or jend < m:
+            j0 = 0
+            continue
+        # deflated restart
+        s = c[: m + 1] - hb @ y
+        _, g = harmonic_ritz(hb, k)
+        p = np.zeros((m + 1, k + 1), dtype=np.complex128)
+        p[:m, :k] = g
+        p[:, k] = s
+        p, _ = np.linalg.qr(p)
+        pk = p[:m, :k]
+        vs = [sum(p[i, a] * vs[i] for i in range(m + 1)) for a in range(k + 1)]
+        zs = [sum(pk[i, a] * zs[i] for i in range(m)) for a in range(k)]
+        hk = p.conj().T @ hb @ pk
+        c_new = p.conj().T @ s
+        h = np.zeros((m + 1, m), dtype=np.complex128)
+        h[: k + 1, :k] = hk
+        c = np.zeros(m + 1, dtype=np.complex128)
+        c[: k + 1] = c_new
+        j0 = k
+        if on_restart is not None:
+            on_restart(vs, zs, hk)
+    info.iterations = total
+    return x, info

@@ -159,3 +159,138 @@ def test_fcg_with_varying_preconditioner_against_direct_solve():
     # the varying preconditioner was used: the iterates differ from plain CG
     x1, info1 = solvers.fcg(lambda v: a @ v, b, tol=1e-12)
     assert info1.iterations != info.iterations or np.linalg.norm(x1 - x) > 0
+
+
+def _known_spectrum(n=300, seed=5):
+    """A normal matrix with six eigenvalues of modulus 1e-3 .. 5e-3 and the
+    rest of modulus 1 .. 2 (phases within +-0.3 rad), and a source."""
+    rng = np.random.default_rng(seed)
+    lam = (np.concatenate([np.linspace(1e-3, 5e-3, 6), rng.uniform(1, 2, n - 6)])
+           * np.exp(1j * rng.uniform(-0.3, 0.3, n)))
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    a = q @ np.diag(lam) @ q.conj().T
+    return a, lam, rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def _arnoldi(a, v0, m):
+    n = a.shape[0]
+    v = np.zeros((n, m + 1), dtype=np.complex128)
+    h = np.zeros((m + 1, m), dtype=np.complex128)
+    v[:, 0] = v0 / np.linalg.norm(v0)
+    for j in range(m):
+        w = a @ v[:, j]
+        for i in range(j + 1):
+            h[i, j] = np.vdot(v[:, i], w)
+            w = w - h[i, j] * v[:, i]
+        h[j + 1, j] = np.linalg.norm(w)
+        if h[j + 1, j] > 0:
+            v[:, j + 1] = w / h[j + 1, j]
+    return v, h
+
+
+def test_harmonic_ritz_pins():
+    """(1) On an invariant Krylov space (Arnoldi run to the full dimension,
+    last subdiagonal zero) harmonic Ritz values are exact eigenvalues: the k
+    of smallest modulus equal those of the matrix.  (2) On a truncated
+    Arnoldi matrix each pair satisfies its defining Petrov-Galerkin
+    condition Hbar^dagger (Hbar g - theta [g; 0]) = 0."""
+    rng = np.random.default_rng(7)
+    n = 30
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    _, h = _arnoldi(a, rng.standard_normal(n) + 0j, n)
+    theta, _ = solvers.harmonic_ritz(h, 5)
+    ev = np.linalg.eigvals(a)
+    ev = ev[np.argsort(np.abs(ev))][:5]
+    for t in theta:
+        assert np.min(np.abs(ev - t)) <= 1e-9 * np.abs(t)
+    _, h = _arnoldi(a, rng.standard_normal(n) + 0j, 12)
+    theta, g = solvers.harmonic_ritz(h, 4)
+    for i in range(4):
+        gi = np.concatenate([g[:, i], [0.0]])
+        resid = h.conj().T @ (h @ g[:, i] - theta[i] * gi)
+        assert np.linalg.norm(resid) <= 1e-10 * np.linalg.norm(h) ** 2 * np.linalg.norm(g[:, i])
+    # and they are the smallest-modulus solutions of that condition
+    hm = h[:12, :12]
+    gen = np.linalg.solve(hm.conj().T, h.conj().T @ h)
+    allt = np.linalg.eigvals(gen)
+    assert np.allclose(np.sort(np.abs(theta)), np.sort(np.abs(allt))[:4], rtol=1e-9)
+
+
+def test_fgmres_dr_without_deflation_is_fgmres():
+    """k = 0: the same iterates as restarted FGMRES(m), with a preconditioner
+    that varies from call to call."""
+    dims = (4, 4, 4, 4)
+    u = fields.gauge_field(dims, "smooth", 301)
+    wc = evenodd.WilsonClover(u, 0.135, 1.0)
+    bhat = wc.prepare_source(fields.gaussian_spinor(dims, 302))
+
+    def make_prec():
+        calls = [0]
+
+        def prec(v):
+            calls[0] += 1
+            return (1.0 + 0.1 * (calls[0] % 3)) * v
+        return prec
+
+    x0, i0 = solvers.fgmres(wc.schur, bhat, precond=make_prec(), m=12, tol=1e-10)
+    x1, i1 = solvers.fgmres_dr(wc.schur, bhat, precond=make_prec(), m=12, k=0, tol=1e-10)
+    assert i0.iterations == i1.iterations
+    assert dirac.norm(x1 - x0) <= 1e-14 * dirac.norm(x0)
+
+
+def test_fgmres_dr_against_direct_solve():
+    """Deflated restarts on the indefinite Schur system (kappa 0.135, clover)
+    reach the direct solution of the Schur complement built densely from the
+    brute-force matrix; the flexible Arnoldi relation A Z_k = V_{k+1} Hbar_k
+    and the orthonormality of V_{k+1} hold after every deflated restart."""
+    from tests import bruteforce
+    dims, kappa, csw = (4, 4, 4, 4), 0.135, 1.0
+    u = fields.gauge_field(dims, "smooth", 303)
+    b = fields.gaussian_spinor(dims, 304)
+    wc = evenodd.WilsonClover(u, kappa, csw)
+    m = (bruteforce.clover_block_matrix(wc.a.reshape(-1, 12, 12))
+         - kappa * bruteforce.hopping_matrix(u, dims)).toarray()
+    odd = np.repeat(bruteforce.parity_of_sites(dims).astype(bool), 12)
+    ie, io = np.nonzero(~odd)[0], np.nonzero(odd)[0]
+    mhat = (m[np.ix_(ie, ie)]
+            - m[np.ix_(ie, io)] @ np.linalg.solve(m[np.ix_(io, io)], m[np.ix_(io, ie)]))
+    bhat = wc.prepare_source(b)
+    checks = []
+
+    def on_restart(vs, zs, hk):
+        az = np.stack([wc.schur(z).reshape(-1) for z in zs], 1)
+        vm = np.stack([v.reshape(-1) for v in vs], 1)
+        checks.append((np.linalg.norm(az - vm @ hk) / np.linalg.norm(az),
+                       np.linalg.norm(vm.conj().T @ vm - np.eye(vm.shape[1]))))
+
+    calls = [0]
+
+    def prec(v):  # varying: a few CG steps on the normal equations
+        calls[0] += 1
+        y, _ = solvers.cgnr(wc.schur, lambda z: wc.schur(z, dagger=True), v,
+                            tol=1e-30, maxiter=1 + calls[0] % 3)
+        return y
+
+    x, info = solvers.fgmres_dr(wc.schur, bhat, precond=prec, m=12, k=4, tol=1e-11,
+                                on_restart=on_restart)
+    assert info.converged
+    xr = np.linalg.solve(mhat, bhat.reshape(-1))
+    cond = np.linalg.cond(mhat)
+    assert np.linalg.norm(x.reshape(-1) - xr) <= 2 * cond * 1e-11 * np.linalg.norm(xr)
+    assert checks, "no deflated restart happened"
+    for rel_az, orth in checks:
+        assert rel_az <= 1e-6 and orth <= 1e-6  # MGS in FP64, once
+
+
+def test_fgmres_dr_deflates_small_eigenvalues():
+    """Six eigenvalues near zero slow restarted FGMRES(20) down; keeping
+    k = 6 harmonic Ritz vectors across restarts removes them (Morgan's
+    argument, which the paper invokes for the low modes of the Dirac
+    operator), so FGMRES-DR(20, 6) needs well under half the steps."""
+    a, _, b = _known_spectrum()
+    op = lambda v: a @ v  # noqa: E731
+    _, plain = solvers.fgmres_dr(op, b, m=20, k=0, tol=1e-10, maxiter=5000)
+    x, dr = solvers.fgmres_dr(op, b, m=20, k=6, tol=1e-10, maxiter=5000)
+    assert plain.converged and dr.converged
+    assert np.linalg.norm(b - a @ x) <= 1e-10 * np.linalg.norm(b)
+    assert dr.iterations * 2 < plain.iterations, (dr.iterations, plain.iterations)
