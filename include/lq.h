@@ -172,6 +172,24 @@ lq_status lq_clover_apply(lq_ctx* ctx, void* dev_out, const void* dev_in, int pa
 lq_status lq_schur(lq_ctx* ctx, void* dev_out, const void* dev_in, void* dev_tmp, int dagger,
                    int prec, int nrhs);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: lq_schur
+ * without dev_tmp.  The odd-parity intermediate A_oo^-1 H_oe in lives in a
+ * static device array of LQ_SCRATCH_BYTES bytes that every GPU the library
+ * runs on holds until the process ends; the call allocates nothing (the
+ * array's address on a device is resolved by lq_create).  prec: LQ_F64,
+ * LQ_F32 or LQ_F16 (LQ_EINVAL for LQ_F16X, whose operator tables the library
+ * allocates); LQ_EINVAL when one odd field of the lattice in prec exceeds
+ * LQ_SCRATCH_BYTES (lq_field_bytes(ctx, LQ_ODD, prec, 1) > LQ_SCRATCH_BYTES;
+ * e.g. a 32^3x64 lattice fits in FP16 only).  nrhs fields run one after
+ * another.  Every call on one GPU shares the array, which keeps the last
+ * call's contents: calls that overlap in time on one GPU (other streams,
+ * other threads, other contexts) race, and the caller must serialise them.
+ * Results equal lq_schur's. */
+#define LQ_SCRATCH_BYTES ((size_t)64 << 20)
+lq_status lq_schur_noalloc(lq_ctx* ctx, void* dev_out, const void* dev_in, int dagger, int prec,
+                           int nrhs);
+
 /* Global reductions on a device field (FP64 accumulation, fixed tree order):
  * out[0] = sum |a|^2; dot: out[0] + i out[1] = sum conj(a) b. */
 lq_status lq_norm2(lq_ctx* ctx, double* out, const void* dev_a, int parity, int prec);

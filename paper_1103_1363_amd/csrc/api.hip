@@ -135,8 +135,21 @@ lq_status lq_create(const int dims[4], int t_antiperiodic, void* hip_stream, lq_
     g_create_error = "lattice too large for the reduction scratch";
     return LQ_EINVAL;
   }
+  int device = 0;
+  const hipError_t de = hipGetDevice(&device);
+  if (de != hipSuccess) {
+    g_create_error = std::string("hipGetDevice failed: ") + hipGetErrorString(de);
+    return LQ_EHIP;
+  }
+  try {
+    lq::noalloc_init(device);  // address of the no-allocation scratch array on this device
+  } catch (const lq::Error& e) {
+    g_create_error = e.what();
+    return e.code;
+  }
   lq_ctx* ctx = new (std::nothrow) lq_ctx();
   if (!ctx) return LQ_ENOMEM;
+  ctx->device = device;
   for (int k = 0; k < 4; ++k) {
     ctx->dims[k] = dims[k];
     ctx->geo.L[k] = dims[k];
@@ -321,6 +334,15 @@ lq_status lq_schur(lq_ctx* ctx, void* dev_out, const void* dev_in, void* dev_tmp
       lq::schur(ctx, reinterpret_cast<char*>(dev_out) + r * fb,
                 reinterpret_cast<const char*>(dev_in) + r * fb,
                 reinterpret_cast<char*>(dev_tmp) + r * fb, dagger, prec);
+  });
+}
+
+lq_status lq_schur_noalloc(lq_ctx* ctx, void* dev_out, const void* dev_in, int dagger,
+                           int prec, int nrhs) {
+  return guarded(ctx, [&] {
+    LQ_CHECK(dev_out && dev_in && nrhs >= 1, LQ_EINVAL, "null pointer or nrhs < 1");
+    LQ_CHECK(dev_out != dev_in, LQ_EINVAL, "schur needs distinct input and output buffers");
+    lq::schur_noalloc(ctx, dev_out, dev_in, dagger, prec, nrhs);
   });
 }
 

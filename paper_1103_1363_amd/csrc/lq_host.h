@@ -39,6 +39,7 @@ struct lq_ctx {
   lq::Geo mr_geo;
   int dims[4];
   int64_t V;
+  int device = 0;                 // HIP device current at lq_create
   hipStream_t stream = nullptr;   // caller's stream (public per-operation calls)
   hipStream_t sstream = nullptr;  // library-owned stream used by the solvers
   hipStream_t cur = nullptr;      // stream the kernel wrappers launch on
@@ -92,6 +93,11 @@ bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_par
                lq_solve_report* rep);
 void sap_destroy(Sap* sp);
 void free_clover(lq_ctx* ctx);
+
+// noalloc.hip: the scratch array's device address, resolved once per
+// device (with that device current); the Schur operator that uses it
+void noalloc_init(int device);
+void schur_noalloc(lq_ctx* ctx, void* out, const void* in, int dagger, int prec, int nrhs);
 
 // blas.hip
 void norm2(lq_ctx* ctx, double* out_host, const void* a, int prec);

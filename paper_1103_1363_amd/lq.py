@@ -106,6 +106,7 @@ def lib():
         L.lq_dslash.argtypes = [vp, vp, vp, ip, ip, ip, ip]
         L.lq_clover_apply.argtypes = [vp, vp, vp, ip, ip, ip, ip]
         L.lq_schur.argtypes = [vp, vp, vp, vp, ip, ip, ip]
+        L.lq_schur_noalloc.argtypes = [vp, vp, vp, ip, ip, ip]
         L.lq_norm2.argtypes = [vp, dp, vp, ip, ip]
         L.lq_dot.argtypes = [vp, dp, vp, vp, ip, ip]
         L.lq_solve.argtypes = [vp, dp, dp, ip, ct.c_double, ct.c_double, ct.c_double,
@@ -140,6 +141,7 @@ def lib():
             getattr(L, name).restype = ip
         for name in ("lq_upload_gauge", "lq_set_clover", "lq_spinor_to_device",
                      "lq_spinor_to_host", "lq_dslash", "lq_clover_apply", "lq_schur",
+                     "lq_schur_noalloc",
                      "lq_norm2", "lq_dot", "lq_solve", "lq_solve_device", "lq_sap_apply",
                      "lq_solve_sap", "lq_net_create",
                      "lq_net_set_weights", "lq_net_get_weights", "lq_net_init_neumann", "lq_net_apply",
@@ -260,6 +262,13 @@ class Lattice:
         self._check(self._L.lq_schur(self._h, ct.c_void_p(out.data_ptr()),
                                      ct.c_void_p(inp.data_ptr()), ct.c_void_p(tmp.data_ptr()),
                                      int(dagger), prec, nrhs))
+
+    def schur_noalloc(self, out, inp, dagger=False, prec=F64, nrhs=1):
+        """lq_schur without a temporary buffer (static device scratch; allocates
+        nothing)."""
+        self._check(self._L.lq_schur_noalloc(self._h, ct.c_void_p(out.data_ptr()),
+                                             ct.c_void_p(inp.data_ptr()), int(dagger), prec,
+                                             nrhs))
 
     def norm2(self, a, parity=EVEN, prec=F64):
         v = np.zeros(1)
