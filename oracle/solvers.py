@@ -17,7 +17,10 @@ Recurrences are not printed in the paper; the textbook forms are used:
             definite operator;
 * fgmres_dr: FGMRES with deflated restarting (section 7 of the paper, after
             Morgan's GMRES-DR): k harmonic Ritz vectors of smallest modulus
-            are carried across each restart.
+            are carried across each restart;
+* block_cg: O'Leary's block CG for several right-hand sides sharing one
+            block Krylov space (breakdown-free form with a rank-revealing
+            search block).
 
 Every solver stops on the true residual ||b - A x|| / ||b|| <= tol computed
 from the operator, never on a recurrence value alone.  Functions take
@@ -29,7 +32,10 @@ dense normal Schur operator; fgmres_dr against the dense Schur solve, equal
 to fgmres for k = 0, with the flexible Arnoldi relation after each deflated
 restart, and deflating a known set of small eigenvalues; harmonic Ritz
 values exact on an invariant subspace and satisfying their Petrov-Galerkin
-condition.
+condition; block_cg's iterates equal to the Galerkin projection onto the
+block Krylov space built densely, its 12 point-source solutions equal to the
+dense Schur solve, its A-norm errors never above single-RHS CG's, and
+dependent right-hand sides.
 """
 from __future__ import annotations
 
@@ -351,3 +357,74 @@ def fgmres_dr(op, b, precond=None, m=32, k=0, tol=1e-10, maxiter=10000, x0=None,
             on_restart(vs, zs, hk)
     info.iterations = total
     return x, info
+
+
+def _orth(w, drop_tol):
+    """Orthonormal basis of the column space of w (N x s), dropping the
+    directions whose singular value is below drop_tol."""
+    u, sv, _ = np.linalg.svd(w, full_matrices=False)
+    return u[:, sv > drop_tol]
+
+
+def block_cg(op, b, tol=1e-10, maxiter=10000, x0=None, drop_tol=1e-13, resid=None,
+             fixed_iterations=None):
+    """Block CG for s right-hand sides of a Hermitian positive definite
+    operator (O'Leary's block conjugate gradient, in the breakdown-free form
+    that keeps an orthonormal, rank-revealing search block).
+
+    b: (s, ...) stack of right-hand sides; op acts on one field.  The columns
+    are first scaled to unit norm (the block Krylov space does not change).
+    With R = B - A X and P = orth(R):
+        Q = A P,  alpha = (P^H Q)^-1 P^H R,  X += P alpha,  R -= Q alpha,
+        beta = -(P^H Q)^-1 Q^H R,  P = orth(R + P beta),
+    where orth drops directions of singular value below drop_tol (in units of
+    the scaled right-hand sides): directions that became dependent, and those
+    of columns already solved to that level.  Each iteration applies op to
+    the columns of P (at most s).  Stops when resid(j, x_j) <= tol for every
+    column (default |b_j - op x_j| / |b_j|), checked every iteration, or after
+    fixed_iterations iterations when given."""
+    s = b.shape[0]
+    shape = b.shape[1:]
+    bm = b.reshape(s, -1).T  # N x s
+    scale = np.linalg.norm(bm, axis=0)
+    scale[scale == 0.0] = 1.0
+    bs = bm / scale
+    x = np.zeros_like(bs) if x0 is None else x0.reshape(s, -1).T / scale
+
+    def apply(p):
+        return np.stack([op(p[:, j].reshape(shape)).reshape(-1) for j in range(p.shape[1])], 1)
+
+    if resid is None:
+        bn = np.linalg.norm(bm, axis=0)
+
+        def resid(j, xj):
+            return norm(b[j] - op(xj)) / bn[j] if bn[j] > 0 else 0.0
+
+    info = SolveInfo()
+    r = bs - apply(x) if x0 is not None else bs.copy()
+    p = _orth(r, drop_tol)
+    applications = 0
+    for k in range(maxiter):
+        if p.shape[1] == 0:
+            break
+        q = apply(p)
+        applications += p.shape[1]
+        pq = p.conj().T @ q
+        alpha = np.linalg.solve(pq, p.conj().T @ r)
+        x = x + p @ alpha
+        r = r - q @ alpha
+        info.iterations = k + 1
+        if fixed_iterations is not None:
+            if k + 1 >= fixed_iterations:
+                break
+        else:
+            res = [resid(j, (x[:, j] * scale[j]).reshape(shape)) for j in range(s)]
+            info.history.append(max(res))
+            if max(res) <= tol:
+                info.converged = True
+                info.true_residual = max(res)
+                break
+        beta = -np.linalg.solve(pq, q.conj().T @ r)
+        p = _orth(r + p @ beta, drop_tol)
+    info.applications = applications
+    return (x * scale).T.reshape(b.shape), info
