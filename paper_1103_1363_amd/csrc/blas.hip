@@ -103,3 +103,37 @@ void dot(lq_ctx* ctx, double* out, const void* a, const void* b, int prec) {
 }
 
 }  // namespace lq
+
+namespace {
+
+// Streaming copy, 16 bytes per lane and four per thread in flight: the
+// achievable-bandwidth reference of the roofline figures.
+constexpr int CPY_BLK = 256, CPY_U = 4;
+__global__ __launch_bounds__(CPY_BLK) void stream_copy_kernel(uint4* __restrict__ dst,
+                                                              const uint4* __restrict__ src,
+                                                              int64_t n) {
+  const int64_t i0 = (int64_t)blockIdx.x * CPY_BLK * CPY_U + threadIdx.x;
+  uint4 v[CPY_U];
+#pragma unroll
+  for (int k = 0; k < CPY_U; ++k)
+    if (i0 + k * CPY_BLK < n) v[k] = src[i0 + k * CPY_BLK];
+#pragma unroll
+  for (int k = 0; k < CPY_U; ++k)
+    if (i0 + k * CPY_BLK < n) dst[i0 + k * CPY_BLK] = v[k];
+}
+
+}  // namespace
+
+extern "C" lq_status lq_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || (bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+    return LQ_EINVAL;
+  const int64_t n = (int64_t)(bytes / 16);
+  if (n == 0) return LQ_OK;
+  const int64_t per = (int64_t)CPY_BLK * CPY_U;
+  const int64_t grid = (n + per - 1) / per;
+  if (grid > 0x7fffffff) return LQ_EINVAL;
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)grid), dim3(CPY_BLK), 0,
+                     reinterpret_cast<hipStream_t>(stream), reinterpret_cast<uint4*>(dst),
+                     reinterpret_cast<const uint4*>(src), n);
+  return hipGetLastError() == hipSuccess ? LQ_OK : LQ_EHIP;
+}

@@ -19,6 +19,16 @@
 
 #include "lq_internal.h"
 
+// Hops per scheduling group of the hopping kernels (1, 2, 4 or 8).
+#ifndef LQ_HOP_GROUP
+#define LQ_HOP_GROUP 2
+#endif
+// FP16 hops on packed halves and dot2 (1) or in FP32 after conversion (0).
+#ifndef LQ_HOP16_PACKED
+#define LQ_HOP16_PACKED 1
+#endif
+
+
 namespace lq {
 
 // XCD-aware block order: the hardware deals workgroups round-robin to the 8
@@ -109,12 +119,156 @@ __device__ __forceinline__ void link_mul(const C<R> u[9], const C<R> h[6], C<R> 
     }
 }
 
-template <int MU, int S, bool BACK, class P>
+// ---------------------------------------------------------------- FP16 hops
+// The FP16 operator keeps the neighbour spinor and the link as half pairs:
+// the spin projection is one packed half add per complex component (the
+// sum rounds once to FP16, as the stored components already did), and the
+// link product runs on v_dot2_f32_f16, two half products summed into an
+// FP32 accumulator per instruction.  A complex product u h is
+//   Re = dot2(u, (h.re, -h.im)),  Im = dot2(u, (h.im, h.re)),
+// and conj(u) h is
+//   Re = dot2(u, (h.re, h.im)),   Im = dot2(u, (h.im, -h.re)),
+// so the projection produces the two forms of h that the direction needs.
+// The third row of the link, conj(row0 x row1), is formed the same way and
+// rounded once to FP16.  The neighbour's scale and the accumulation are FP32.
+typedef _Float16 hf2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ hf2 hf2_bits(unsigned u) {
+  hf2 h;
+  __builtin_memcpy(&h, &u, 4);
+  return h;
+}
+__device__ __forceinline__ float dot2(hf2 a, hf2 b, float c) {
+  return __builtin_amdgcn_fdot2(a, b, c, false);
+}
+// c * q for c = +1 (K = 0), -1 (1), +i (2), -i (3)
+template <int K>
+__device__ __forceinline__ hf2 cmulk(hf2 q) {
+  if constexpr (K == 0) return q;
+  else if constexpr (K == 1) return hf2{-q.x, -q.y};
+  else if constexpr (K == 2) return hf2{-q.y, q.x};
+  else return hf2{q.y, -q.x};
+}
+// h = a + c b in the two forms the link product takes: (re, -im) and
+// (im, re) for U h; (re, im) and (im, -re) for U^+ h.
+template <int K, bool DAGU>
+__device__ __forceinline__ void hform(hf2 a, hf2 b, hf2& f0, hf2& f1) {
+  const hf2 q = cmulk<K>(b);
+  if constexpr (!DAGU) {
+    f0 = hf2{a.x, -a.y} + hf2{q.x, -q.y};
+    f1 = hf2{a.y, a.x} + hf2{q.y, q.x};
+  } else {
+    f0 = a + q;
+    f1 = hf2{a.y, -a.x} + hf2{q.y, -q.x};
+  }
+}
+// coefficient codes of the projector (1 - S gamma_mu) in the chiral basis:
+// h0 = p0 + c0 p(b0), h1 = p1 + c1 p(b1)
+template <int MU, int S>
+struct Proj;
+template <int S>
+struct Proj<0, S> {  // h0 = p0 + S i p3, h1 = p1 + S i p2
+  static constexpr int b0 = 3, b1 = 2, k0 = S > 0 ? 2 : 3, k1 = S > 0 ? 2 : 3;
+};
+template <int S>
+struct Proj<1, S> {  // h0 = p0 + S p3, h1 = p1 - S p2
+  static constexpr int b0 = 3, b1 = 2, k0 = S > 0 ? 0 : 1, k1 = S > 0 ? 1 : 0;
+};
+template <int S>
+struct Proj<2, S> {  // h0 = p0 + S i p2, h1 = p1 - S i p3
+  static constexpr int b0 = 2, b1 = 3, k0 = S > 0 ? 2 : 3, k1 = S > 0 ? 3 : 2;
+};
+template <int S>
+struct Proj<3, S> {  // h0 = p0 - S p2, h1 = p1 - S p3
+  static constexpr int b0 = 2, b1 = 3, k0 = S > 0 ? 1 : 0, k1 = S > 0 ? 1 : 0;
+};
+
+// STEP: the neighbour's number by the division-free step (fewer
+// instructions, but the compiler then computes the numbers of all hops
+// early and holds them: 157 instead of 105 registers; right for the plain
+// hopping kernel, wrong for the fused solver kernels, which add the clover
+// term and the vector updates) or from the neighbour's coordinates.
+template <int MU, int S, bool BACK, bool STEP>
+__device__ __forceinline__ void hop_dir16(const Geo& g, const Field<P16>& in,
+                                          const __half2* __restrict__ gauge, int p, int64_t s,
+                                          const int l[4], const int tc[4], int x3, C<float> acc[12]) {
+  float sign = 1.f;
+  if constexpr (MU == 3) {
+    if (g.apt && x3 == (BACK ? 0 : g.L[3] - 1)) sign = -1.f;
+  }
+  int64_t sy;
+  if constexpr (STEP) {
+    sy = neighbour(g, s, l, tc, MU, !BACK);
+  } else {
+    int y[4] = {tc[0] * g.T[0] + l[0], tc[1] * g.T[1] + l[1], tc[2] * g.T[2] + l[2], x3};
+    if constexpr (!BACK)
+      y[MU] = (y[MU] + 1 == g.L[MU]) ? 0 : y[MU] + 1;
+    else
+      y[MU] = (y[MU] == 0) ? g.L[MU] - 1 : y[MU] - 1;
+    sy = cb_index(g, y);
+  }
+  const unsigned* din = reinterpret_cast<const unsigned*>(in.d);
+  unsigned v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = din[spin_idx(sy, c)];
+  const float scale = in.norm[sy] * sign;
+  using PJ = Proj<MU, S>;
+  hf2 f0[6], f1[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    hform<PJ::k0, BACK>(hf2_bits(v[a]), hf2_bits(v[3 * PJ::b0 + a]), f0[a], f1[a]);
+    hform<PJ::k1, BACK>(hf2_bits(v[3 + a]), hf2_bits(v[3 * PJ::b1 + a]), f0[3 + a], f1[3 + a]);
+  }
+  // the link: rows 0 and 1 as stored, row 2 = conj(row0 x row1)
+  const int lp = BACK ? 1 - p : p;
+  const int64_t ls = BACK ? sy : s;
+  const unsigned* gl = reinterpret_cast<const unsigned*>(gauge);
+  hf2 u[9];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+    u[c] = hf2_bits(__builtin_nontemporal_load(gl + link_idx(g.nblk, lp, MU, ls, c)));
+  {
+    // conj(a b - c d): Re = dot2(a, cj(b)) - dot2(c, cj(d)), -Im = dot2(c, sw(d)) - dot2(a, sw(b))
+    auto cj = [](hf2 z) { return hf2{z.x, -z.y}; };
+    auto sw = [](hf2 z) { return hf2{z.y, z.x}; };
+    auto ng = [](hf2 z) { return hf2{-z.x, -z.y}; };
+    auto row2 = [&](hf2 a, hf2 b, hf2 c, hf2 d) {
+      const float re = dot2(a, cj(b), dot2(ng(c), cj(d), 0.f));
+      const float mi = dot2(c, sw(d), dot2(ng(a), sw(b), 0.f));
+      return hf2{(_Float16)re, (_Float16)mi};
+    };
+    u[6] = row2(u[1], u[5], u[2], u[4]);
+    u[7] = row2(u[2], u[3], u[0], u[5]);
+    u[8] = row2(u[0], u[4], u[1], u[3]);
+  }
+  // w = U h (forward) or U^+ h (backward), FP32
+  C<float> w[6];
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const hf2 ub = BACK ? u[3 * b + a] : u[3 * a + b];
+        re = dot2(ub, f0[3 * k + b], re);
+        im = dot2(ub, f1[3 * k + b], im);
+      }
+      w[3 * k + a] = C<float>{scale * re, scale * im};
+    }
+  reconstruct_add<MU, S>(acc, w);
+}
+
+template <int MU, int S, bool BACK, bool STEP, class P>
 __device__ __forceinline__ void hop_dir(const Geo& g, const Field<P>& in,
                                         const typename P::S* __restrict__ gauge, int p,
                                         int64_t s, const int l[4], const int tc[4], int x3,
                                         C<typename P::R> acc[12]) {
   using R = typename P::R;
+  if constexpr (P::id == LQ_F16 && LQ_HOP16_PACKED) {
+    hop_dir16<MU, S, BACK, STEP>(g, in, gauge, p, s, l, tc, x3, acc);
+    return;
+  }
   R sign = (R)1;
   if constexpr (MU == 3) {
     if (g.apt && x3 == (BACK ? 0 : g.L[3] - 1)) sign = (R)-1;
@@ -145,7 +299,10 @@ __device__ __forceinline__ void hop_dir(const Geo& g, const Field<P>& in,
 }
 
 // acc = (H psi)(x) (DAG: H^dagger) restricted to output site s of parity p.
-template <bool DAG, class P>
+// STEP, GROUP: the FP16 neighbour numbering (hop_dir16) and the hops per
+// scheduling group; the plain hopping kernel takes (true, 8), the fused
+// solver kernels the defaults.
+template <bool DAG, bool STEP = false, int GROUP = LQ_HOP_GROUP, class P>
 __device__ __forceinline__ void hop_site(const Geo& g, const Field<P>& in,
                                          const typename P::S* __restrict__ gauge, int p,
                                          int64_t s, C<typename P::R> acc[12]) {
@@ -156,20 +313,25 @@ __device__ __forceinline__ void hop_site(const Geo& g, const Field<P>& in,
   site_local(g, p, s, l, tc);
   const int x3 = tc[3] * g.T[3] + l[3];
   constexpr int SF = DAG ? -1 : 1;  // forward-hop projector sign
-  // The scheduling barriers keep the loads of at most two hops in flight per
-  // thread: hoisting all eight (144 loads) would cost registers and with them
-  // the occupancy that hides memory latency on this bandwidth-bound kernel.
-  hop_dir<0, SF, false>(g, in, gauge, p, s, l, tc, x3, acc);
-  hop_dir<0, -SF, true>(g, in, gauge, p, s, l, tc, x3, acc);
-  __builtin_amdgcn_sched_barrier(0);
-  hop_dir<1, SF, false>(g, in, gauge, p, s, l, tc, x3, acc);
-  hop_dir<1, -SF, true>(g, in, gauge, p, s, l, tc, x3, acc);
-  __builtin_amdgcn_sched_barrier(0);
-  hop_dir<2, SF, false>(g, in, gauge, p, s, l, tc, x3, acc);
-  hop_dir<2, -SF, true>(g, in, gauge, p, s, l, tc, x3, acc);
-  __builtin_amdgcn_sched_barrier(0);
-  hop_dir<3, SF, false>(g, in, gauge, p, s, l, tc, x3, acc);
-  hop_dir<3, -SF, true>(g, in, gauge, p, s, l, tc, x3, acc);
+  // The scheduling barriers keep the loads of at most GROUP hops in flight
+  // per thread: hoisting all eight (144 loads) would cost registers and with
+  // them the occupancy that hides memory latency on this bandwidth-bound
+  // kernel.
+  hop_dir<0, SF, false, STEP>(g, in, gauge, p, s, l, tc, x3, acc);
+  if constexpr (GROUP < 2) __builtin_amdgcn_sched_barrier(0);
+  hop_dir<0, -SF, true, STEP>(g, in, gauge, p, s, l, tc, x3, acc);
+  if constexpr (GROUP < 4) __builtin_amdgcn_sched_barrier(0);
+  hop_dir<1, SF, false, STEP>(g, in, gauge, p, s, l, tc, x3, acc);
+  if constexpr (GROUP < 2) __builtin_amdgcn_sched_barrier(0);
+  hop_dir<1, -SF, true, STEP>(g, in, gauge, p, s, l, tc, x3, acc);
+  if constexpr (GROUP < 8) __builtin_amdgcn_sched_barrier(0);
+  hop_dir<2, SF, false, STEP>(g, in, gauge, p, s, l, tc, x3, acc);
+  if constexpr (GROUP < 2) __builtin_amdgcn_sched_barrier(0);
+  hop_dir<2, -SF, true, STEP>(g, in, gauge, p, s, l, tc, x3, acc);
+  if constexpr (GROUP < 4) __builtin_amdgcn_sched_barrier(0);
+  hop_dir<3, SF, false, STEP>(g, in, gauge, p, s, l, tc, x3, acc);
+  if constexpr (GROUP < 2) __builtin_amdgcn_sched_barrier(0);
+  hop_dir<3, -SF, true, STEP>(g, in, gauge, p, s, l, tc, x3, acc);
 }
 
 // ---------------------------------------------------------------- clover
