@@ -765,4 +765,58 @@ bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_par
   return conv;
 }
 
+// FGMRES with deflated restarting and the SAP preconditioner on the full
+// system (FP32 Krylov basis, FP64 solution and restart residuals).
+bool solve_sap_dr(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_params& q,
+                  lq_solve_report* rep) {
+  auto t0 = std::chrono::steady_clock::now();
+  const double bytes0 = ctx->bytes;
+  Sap* sp = sap_state(ctx);
+  (void)blocks_of(ctx, q);
+  const int m = q.restart > 0 ? q.restart : 70;
+  LQ_CHECK(m >= 2 && m <= 128, LQ_EINVAL, "FGMRES-DR Krylov dimension must be 2..128");
+  LQ_CHECK(q.deflate > 0 && q.deflate < m && q.deflate <= 32, LQ_EINVAL,
+           "deflated vectors must be 1..min(m-1, 32)");
+  const int maxiter = q.maxiter > 0 ? q.maxiter : 2000;
+  const size_t f64 = 2 * half_bytes(ctx, LQ_F64);
+  if (!sp->r64) LQ_HIP(hipMalloc(&sp->r64, f64));
+  double d[3];
+  dot3<double2, double2>(ctx, b, b, d);
+  const double bn = std::sqrt(d[2]);
+  fill_zero(ctx, x, f64);
+  SolveTally t;
+  bool conv = true, brk = false;
+  double last2 = 0.0;
+  if (bn > 0.0) {
+    KrylovSpace S;
+    S.n = entries(ctx);
+    S.halves = 2;
+    S.vh = ctx->geo.vh;
+    S.x64 = x;
+    S.r64 = sp->r64;
+    S.precond = [&](void* z, const void* v) { sap_apply_impl(ctx, z, v, q); };
+    S.op = [&](void* w, const void* z) { full_m<P32, false>(ctx, w, nullptr, z); };
+    S.residual64 = [&]() {
+      full_m<P64, true>(ctx, sp->r64, b, x);
+      double e[3];
+      dot3<double2, double2>(ctx, sp->r64, sp->r64, e);
+      last2 = e[2];
+      return e[2];
+    };
+    conv = fgmres_dr(ctx, S, m, q.deflate, tol * bn, maxiter, t, brk);
+  }
+  LQ_HIP(hipStreamSynchronize(ctx->cur));
+  if (rep) {
+    *rep = lq_solve_report{};
+    rep->iterations = t.iterations;
+    rep->reliable_updates = t.reliable;
+    rep->true_residual = bn > 0.0 ? std::sqrt(last2) / bn : 0.0;
+    rep->schur_residual = rep->true_residual;
+    rep->seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rep->bytes = ctx->bytes - bytes0;
+  }
+  return conv;
+}
+
 }  // namespace lq

@@ -174,3 +174,46 @@ def test_solve_sap_extreme_source_scales(lq, scale):
     assert dirac.norm(bs - wc.M(xs)) <= 1e-10 * dirac.norm(bs)
     assert reps.iterations <= rep1.iterations + 4
     assert rel(xs / scale, x1) <= 1e-7
+
+
+@pytest.mark.parametrize("dims,block,m,k", [((8, 4, 4, 8), (4, 2, 2, 4), 16, 4),
+                                            ((8, 8, 8, 8), (4, 4, 4, 4), 12, 6)])
+def test_solve_sap_fgmres_dr(lq, dims, block, m, k):
+    """SAP-FGMRES-DR (deflated restarts, section 7): the solution meets the
+    tolerance by the oracle's own operator, and the step count is close to
+    the oracle's FGMRES-DR with the oracle's SAP (iterates are not unique:
+    FP32 cycles against FP64)."""
+    from oracle import solvers
+    say(f"sap-fgmres-dr dims={dims} block={block} m={m} k={k}")
+    kappa, csw, tol = 0.135, 1.0, 1e-10
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 37)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 37)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    db = lat.to_device(b, lq.FULL, lq.F64)
+    dx = lat.new_field(lq.FULL, lq.F64)
+    rep = lat.solve_sap_device(dx, db, kappa, csw, tol, block, ncycles=2, nmr=4, restart=m,
+                               deflate=k)
+    x = lat.to_host(dx, lq.FULL, lq.F64).reshape(b.shape)
+    wc = evenodd.WilsonClover(u, kappa, csw)
+    res = dirac.norm(b - wc.M(x)) / dirac.norm(b)
+    say(f"  iterations={rep.iterations} restarts={rep.reliable_updates} res={res:.2e}")
+    assert res <= tol, (res, rep)
+    assert abs(rep.true_residual - res) <= 0.1 * res + 1e-14
+    _, info = solvers.fgmres_dr(wc.M, b, lambda v: sap.sap(wc.M, v, dims, block, 2, 4), m=m, k=k,
+                                tol=tol)
+    say(f"  oracle FGMRES-DR steps={info.iterations}")
+    assert abs(rep.iterations - info.iterations) <= max(4, info.iterations // 4), (
+        rep.iterations, info.iterations)
+
+
+def test_solve_sap_fgmres_dr_rejects_bad_deflation(lq):
+    dims = (8, 4, 4, 8)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 38))
+    db = lat.to_device(fields.gaussian_spinor(dims, 1), lq.FULL, lq.F64)
+    dx = lat.new_field(lq.FULL, lq.F64)
+    for m, k in [(8, 8), (200, 4), (40, 33)]:
+        with pytest.raises(lq.LQError):
+            lat.solve_sap_device(dx, db, 0.13, 1.0, 1e-10, (4, 2, 2, 4), 2, 4, restart=m,
+                                 deflate=k)
