@@ -391,7 +391,10 @@ void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, 
   // algorithmic bytes: 8 links (12 reals), in and out per RHS, clover table, x per RHS
   double sb = 8 * link_site_bytes(LQ_F16) + 2.0 * nrhs * spinor_site_bytes(LQ_F16);
   if (epi != MR_EPI_NONE) sb += clover_site_bytes(LQ_F16);
-  if (epi == MR_EPI_SCHUR2 || epi == MR_EPI_UPDATE) sb += nrhs * spinor_site_bytes(LQ_F16);
+  if (epi == MR_EPI_SCHUR2 || epi == MR_EPI_UPDATE || epi == MR_EPI_SCHUR2_F32)
+    sb += nrhs * spinor_site_bytes(LQ_F16);
+  if (epi == MR_EPI_SCHUR2_F32)  // FP32 output in place of the FP16 one
+    sb += nrhs * (spinor_site_bytes(LQ_F32) - spinor_site_bytes(LQ_F16));
   if (epi == MR_EPI_UPDATE)  // no output; x, r read and written, p read
     sb += nrhs * (4 * spinor_site_bytes(LQ_F32) - spinor_site_bytes(LQ_F16)) +
           nrhs * spinor_site_bytes(LQ_F16);
@@ -402,6 +405,9 @@ void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, 
   if (epi == MR_EPI_UPDATE) {
     LQ_CHECK(dag && upd.st, LQ_EINVAL, "the fused update follows the adjoint Schur sweep");
     LQ_MR_LAUNCH(true, MR_EPI_UPDATE);
+  } else if (epi == MR_EPI_SCHUR2_F32) {
+    LQ_CHECK(dag && upd.r.d, LQ_EINVAL, "the FP32 output follows the adjoint Schur sweep");
+    LQ_MR_LAUNCH(true, MR_EPI_SCHUR2_F32);
   } else if (dag) {
     if (epi == MR_EPI_NONE) LQ_MR_LAUNCH(true, MR_EPI_NONE);
     else if (epi == MR_EPI_CLOVINV) LQ_MR_LAUNCH(true, MR_EPI_CLOVINV);
@@ -416,6 +422,19 @@ void mr_hop(lq_ctx* ctx, int p, int dag, int epi, const int* active, void* out, 
 }
 
 }  // namespace
+
+// q32 = Mhat^+ Mhat p, every RHS (block solvers): p and the work fields t
+// (odd) and q1 (even) FP16 multi-RHS fields, q32 an FP32 multi-RHS field
+// written unrounded by the last sweep
+void mrhs_normal(lq_ctx* ctx, void* q32, const void* p, void* t, void* q1, int nrhs) {
+  const Geo& g = ctx->mr_geo;
+  mr_hop(ctx, LQ_ODD, 0, MR_EPI_CLOVINV, nullptr, t, p, nullptr, nrhs, nullptr);
+  mr_hop(ctx, LQ_EVEN, 0, MR_EPI_SCHUR2, nullptr, q1, t, p, nrhs, nullptr);
+  mr_hop(ctx, LQ_ODD, 1, MR_EPI_CLOVINV, nullptr, t, q1, nullptr, nrhs, nullptr);
+  MRUpd out{};
+  out.r = mfield_at<P32>(q32, g.nblk, nrhs);
+  mr_hop(ctx, LQ_EVEN, 1, MR_EPI_SCHUR2_F32, nullptr, q1, t, q1, nrhs, nullptr, out);
+}
 
 void mrhs_pack(lq_ctx* ctx, void* dev, const double2* src_dev, int parity, int prec, int nrhs,
                int r) {

@@ -259,7 +259,13 @@ struct MRWork {
 };
 
 
-enum { MR_EPI_NONE = 0, MR_EPI_CLOVINV = 1, MR_EPI_SCHUR2 = 2, MR_EPI_UPDATE = 3 };
+enum {
+  MR_EPI_NONE = 0,
+  MR_EPI_CLOVINV = 1,
+  MR_EPI_SCHUR2 = 2,
+  MR_EPI_UPDATE = 3,
+  MR_EPI_SCHUR2_F32 = 4  // as SCHUR2, the result stored in the FP32 field upd.r
+};
 
 // Operands of the CG update fused into the second Schur sweep
 // (MR_EPI_UPDATE): x_r += alpha_r p_r and r_r -= alpha_r s_r with s the
@@ -292,6 +298,8 @@ constexpr int MR_SITES_PER_BLOCK = LQ_MR_SITES_PER_BLOCK;  // 4 waves, each ever
 // for the sites of parity p of all right-hand sides.  EPI_UPDATE forms
 // s = A x - k2 H in like EPI_SCHUR2 but, instead of storing it, applies the
 // CG update of `upd` and writes the partial |r_new|^2 per RHS.
+// EPI_SCHUR2_F32 forms A x - k2 H in like EPI_SCHUR2 and stores it in the
+// FP32 field upd.r (no FP16 rounding; the block solver's Q).
 // `active`: skip when 0.  links / clov: the FP16 site-major copies (clov:
 // the table of parity p).
 template <bool DAG, int EPI>
@@ -299,7 +307,8 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
     Geo g, int p, const int* __restrict__ active, MField<P16> out, MField<P16> in,
     MField<P16> x, const unsigned* __restrict__ links, const unsigned* __restrict__ clov,
     const int* __restrict__ nbr, float k2, double* __restrict__ part, MRUpd upd) {
-  constexpr bool AXPY = EPI == MR_EPI_SCHUR2 || EPI == MR_EPI_UPDATE;  // A x - k2 H in
+  constexpr bool AXPY =
+      EPI == MR_EPI_SCHUR2 || EPI == MR_EPI_UPDATE || EPI == MR_EPI_SCHUR2_F32;  // A x - k2 H in
   __shared__ double red[4][MR_MAX];
   if (active && !*active) return;
   const int lane = threadIdx.x & 63;
@@ -495,6 +504,16 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
         nsum += (double)r0.x * r0.x + (double)r0.y * r0.y + (double)r0.z * r0.z +
                 (double)r0.w * r0.w + (double)r1.x * r1.x + (double)r1.y * r1.y +
                 (double)r1.z * r1.z + (double)r1.w * r1.w;
+      }
+      continue;
+    }
+    if constexpr (EPI == MR_EPI_SCHUR2_F32) {
+      // the lane's colour of its RHS, 4 spins x (re, im), unrounded
+      if (bl) {
+        const int64_t e0 = (s * nrhs + li) * 12 + grp * 4;  // complex index
+        float4* op = reinterpret_cast<float4*>(upd.r.d + e0);
+        op[0] = make_float4(y[0], y[1], y[2], y[3]);
+        op[1] = make_float4(y[4], y[5], y[6], y[7]);
       }
       continue;
     }
