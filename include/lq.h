@@ -96,7 +96,16 @@ typedef struct {
   int fault_inject;      /* tests only: 1 = force the inner solve to stagnate */
   int profile;           /* 1: time every inner-iteration kernel with HIP events (no graph) */
   int batched;           /* 1: solve all nrhs (<= 16) together through the multi-RHS operator
-                            (CGNR, inner_prec F16): one operator application serves every RHS */
+                            (CGNR, inner_prec F16): one operator application serves every RHS,
+                            independent CG recurrences; 2: the same operator in block CG, one
+                            Krylov space shared by all RHS (O'Leary's block conjugate gradient,
+                            rank-revealing search block, reliable updates per RHS) */
+  int deflate;           /* LQ_FGMRES_NET: k > 0 deflated vectors (k < restart, at most 32)
+                            kept across restarts (FGMRES-DR, section 7 of the paper); restart
+                            then defaults to 70 */
+  const void* dev_xref;  /* optional reference solution(s) on the device (full-lattice FP64
+                            fields laid out as dev_x, nrhs of them): the report then gives
+                            ||x - xref|| / ||xref|| per right-hand side (ref_error) */
 } lq_solver_params;
 
 /* Kernels of one inner CG iteration, in launch order (report index). */
@@ -121,6 +130,7 @@ typedef struct {
   double kernel_ms[LQ_NK];      /* profile = 1: summed durations per iteration kernel */
   double kernel_bytes[LQ_NK];   /* algorithmic bytes of one launch of each kernel */
   int kernel_calls[LQ_NK];      /* profile = 1: launches timed per kernel */
+  double ref_error;        /* ||x - xref|| / ||xref|| when params->dev_xref is given, else -1 */
 } lq_solve_report;
 
 /* Context: owns device copies of the gauge field (12-real compressed, FP64,
@@ -190,6 +200,44 @@ lq_status lq_schur(lq_ctx* ctx, void* dev_out, const void* dev_in, void* dev_tmp
 lq_status lq_schur_noalloc(lq_ctx* ctx, void* dev_out, const void* dev_in, int dagger, int prec,
                            int nrhs);
 
+/* Measurement reference: copy `bytes` (a multiple of 16; both pointers
+ * 16-byte aligned, else LQ_EINVAL) from src to dst with 16-byte loads and
+ * stores per lane, asynchronously on `stream` (a hipStream_t, NULL =
+ * default).  Its rate, read plus write, is the achievable HBM bandwidth the
+ * hopping term is compared with; it needs no context. */
+lq_status lq_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Fused site-local lattice expressions (the data-parallel expressions of the
+ * QDP++ library that section 4 of the paper ports; its worked example is
+ * the SU(3) array product U_x = V_x W_x of section 3, eq. su3vecmul).  Each
+ * call is one kernel that reads every operand element once and writes the
+ * result once, whatever the length of the expression.  Arrays hold n site
+ * elements (complex 3x3 colour matrices, or 4 x 3 spinors) in the
+ * library's blocked device layout (lq_site_array_bytes bytes), FP64 or FP32;
+ * host arrays are element-major complex128 (matrix row-major; spinor
+ * spin-major).  The output may be one of the inputs (each element is read
+ * before it is written).  Asynchronous on `stream` (a hipStream_t) except
+ * the transfers, which synchronise it.  LQ_EINVAL on bad arguments.
+ * ------------------------------------------------------------------------ */
+enum { LQ_SITE_SU3 = 0, LQ_SITE_SPINOR = 1 };
+enum {
+  LQ_SU3_VW = 0,      /* U = V W (eq. su3vecmul) */
+  LQ_SU3_VWDAG = 1,   /* U = V W^dagger */
+  LQ_SU3_VDAGW = 2,   /* U = V^dagger W */
+  LQ_SU3_VWX = 3      /* U = V W X, one fused pass */
+};
+size_t lq_site_array_bytes(int64_t n, int kind, int prec);
+lq_status lq_site_array_to_device(void* dev, const double* host, int64_t n, int kind, int prec,
+                                  void* stream);
+lq_status lq_site_array_to_host(double* host, const void* dev, int64_t n, int kind, int prec,
+                                void* stream);
+lq_status lq_su3_mul(void* dev_u, const void* dev_v, const void* dev_w, const void* dev_x,
+                     int64_t n, int form, int prec, void* stream);
+/* out_x = U_x in_x (U^dagger when adjoint_u != 0) on every spin of each spinor */
+lq_status lq_su3_spinor_mul(void* dev_out, const void* dev_u, const void* dev_in, int64_t n,
+                            int adjoint_u, int prec, void* stream);
+
 /* Global reductions on a device field (FP64 accumulation, fixed tree order):
  * out[0] = sum |a|^2; dot: out[0] + i out[1] = sum conj(a) b. */
 lq_status lq_norm2(lq_ctx* ctx, double* out, const void* dev_a, int parity, int prec);
@@ -232,8 +280,14 @@ typedef struct {
                     number of times; at most 512 sites per block */
   int ncycles;   /* SAP cycles per application (0: 5) */
   int nmr;       /* MR steps per block solve (0: 4) */
-  int restart;   /* FGCR steps between FP64 restarts (0: 16, at most 64) */
+  int restart;   /* FGCR steps between FP64 restarts (0: 16, at most 64); with deflate > 0
+                    the Krylov dimension m of FGMRES-DR including the deflated vectors
+                    (0: 70, at most 128) */
   int maxiter;   /* FGCR steps in all (0: 2000) */
+  int deflate;   /* 0: FGCR.  k > 0: FGMRES with deflated restarting (section 7 of the
+                    paper): k harmonic Ritz vectors (k < m, at most 32) of the Arnoldi
+                    matrix are kept across each restart; the residual is recomputed in FP64
+                    at every restart */
 } lq_sap_params;
 
 /* dev_out = K dev_in on full-lattice FP32 fields (lq_field_bytes(ctx,
@@ -244,11 +298,13 @@ typedef struct {
 lq_status lq_sap_apply(lq_ctx* ctx, void* dev_out, const void* dev_in,
                        const lq_sap_params* params);
 
-/* Solve M x = b by SAP-preconditioned FGCR to ||b - M x|| <= tol ||b|| (FP64
- * true residual).  dev_b, dev_x: full-lattice FP64 fields as for
+/* Solve M x = b by SAP-preconditioned FGCR (or FGMRES-DR when
+ * params->deflate > 0) to ||b - M x|| <= tol ||b|| (FP64 true residual).  dev_b, dev_x: full-lattice FP64 fields as for
  * lq_solve_device (distinct; dev_x is overwritten).  report (may be NULL):
  * iterations = FGCR steps, reliable_updates = FP64 restarts, true_residual.
- * LQ_ENOCONV when maxiter steps do not reach tol. */
+ * LQ_ENOCONV when maxiter steps do not reach tol, or when restarts stop
+ * reducing the residual (five FGCR restarts, or three FGMRES-DR restarts, in
+ * a row without halving it). */
 lq_status lq_solve_sap(lq_ctx* ctx, void* dev_x, const void* dev_b, double kappa, double csw,
                        double tol, const lq_sap_params* params, lq_solve_report* report);
 
@@ -311,10 +367,24 @@ lq_status lq_net_loss_grad(lq_net* net, const void* dev_b, const void* dev_x, in
 lq_status lq_net_adam_step(lq_net* net, double lr, double beta1, double beta2, double eps);
 
 /* epochs of Adam (beta = 0.9, 0.999; eps = 1e-8) over the pairs in batches of
- * `batch` drawn by a seeded permutation per epoch; loss_history (may be
- * NULL) receives the mean loss of each epoch. */
+ * `batch` drawn by a random permutation per epoch; loss_history (may be
+ * NULL) receives the mean loss of each epoch.  The permutations come from a
+ * generator the net keeps: seed != 0 restarts it from that seed, seed = 0
+ * continues from its current state (after lq_net_load: the saved one). */
 lq_status lq_net_train(lq_net* net, const void* dev_b, const void* dev_x, int npairs, int epochs,
                        int batch, double lr, unsigned seed, double* loss_history);
+
+/* Checkpoint of the training state: the FP32 weights, both Adam moment
+ * arrays, the Adam step count and the shuffle generator's state, in a file
+ * that starts with one line of JSON (format "lq-net-checkpoint", version 1,
+ * layers, adam_step, shuffle_state, bytes_per_array) followed by the three
+ * arrays (float32 (re, im) pairs, [layers][9][4][4], little endian).  Loading
+ * restores them exactly (training continued after lq_net_load with seed 0
+ * repeats uninterrupted training step for step) and clears the stored
+ * gradient.  LQ_EINVAL on an unreadable, malformed or truncated file, or one
+ * of another layer count. */
+lq_status lq_net_save(lq_net* net, const char* path);
+lq_status lq_net_load(lq_net* net, const char* path);
 
 /* lq_solve with a learned-preconditioner solver: params->solver =
  * LQ_FGMRES_NET (FGMRES(restart) on Mhat, right preconditioner N_e) or

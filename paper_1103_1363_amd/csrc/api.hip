@@ -184,6 +184,8 @@ void lq_destroy(lq_ctx* ctx) {
   lq::free_mrhs_tables(ctx);
   lq::free_clover(ctx);
   lq::sap_destroy(ctx->sap);
+  lq::free_krylov(ctx);
+  lq::free_block_work(ctx);
   for (int p = 0; p < 3; ++p)
     if (ctx->gauge[p]) (void)hipFree(ctx->gauge[p]);
   if (ctx->staging) (void)hipFree(ctx->staging);
@@ -415,8 +417,11 @@ lq_status lq_solve_sap(lq_ctx* ctx, void* dev_x, const void* dev_b, double kappa
     ctx->cur = ctx->sstream;
     if (!ctx->clov.valid || ctx->clov.kappa != kappa || ctx->clov.csw != csw)
       lq::build_clover(ctx, kappa, csw);
-    const bool ok = lq::solve_sap(ctx, dev_x, dev_b, tol, *params, report);
-    LQ_CHECK(ok, LQ_ENOCONV, "SAP-FGCR did not reach the tolerance");
+    const bool dr = params->deflate > 0;
+    const bool ok = dr ? lq::solve_sap_dr(ctx, dev_x, dev_b, tol, *params, report)
+                       : lq::solve_sap(ctx, dev_x, dev_b, tol, *params, report);
+    LQ_CHECK(ok, LQ_ENOCONV,
+             dr ? "SAP-FGMRES-DR did not reach the tolerance" : "SAP-FGCR did not reach the tolerance");
   });
 }
 
@@ -503,6 +508,16 @@ lq_status lq_net_train(lq_net* net, const void* dev_b, const void* dev_x, int np
     lq::net_train(net->impl, dev_b, dev_x, npairs, epochs, batch, lr, seed, loss_history);
     LQ_HIP(hipStreamSynchronize(net->ctx->cur));
   });
+}
+
+lq_status lq_net_save(lq_net* net, const char* path) {
+  if (!net) return LQ_EINVAL;
+  return guarded(net->ctx, [&] { lq::net_save(net->impl, path); });
+}
+
+lq_status lq_net_load(lq_net* net, const char* path) {
+  if (!net) return LQ_EINVAL;
+  return guarded(net->ctx, [&] { lq::net_load(net->impl, path); });
 }
 
 lq_status lq_solve_net(lq_ctx* ctx, lq_net* net, double* host_x, const double* host_b, int nrhs,

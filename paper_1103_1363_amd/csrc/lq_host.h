@@ -4,6 +4,8 @@
 // kernels).
 #pragma once
 
+#include <functional>
+
 #include "lq_internal.h"
 
 namespace lq {
@@ -28,6 +30,8 @@ struct MRWork;  // batched multi-RHS solver work space (mrhs.hip)
 struct Net;     // learned preconditioner (net.hip)
 struct Ensemble;  // uneven batch of independent solves (ensemble.hip)
 struct Sap;       // SAP preconditioner state (sap.hip)
+struct KrylovWork;  // deflated FGMRES work space (krylov.hip)
+struct BlockWork;   // block CG work space (solver.hip)
 
 }  // namespace lq
 
@@ -57,6 +61,8 @@ struct lq_ctx {
   void* mr_clov[2] = {nullptr, nullptr};  // A_ee (even sites), A_oo^-1 (odd sites)
   bool mr_links_ok = false, mr_clov_ok = false;
   lq::Sap* sap = nullptr;   // SAP preconditioner state (lazy)
+  lq::KrylovWork* kwork = nullptr;  // deflated FGMRES work space (lazy)
+  lq::BlockWork* bwork = nullptr;   // block CG work space (lazy)
   std::string err;
   double bytes = 0.0;       // algorithmic bytes of every kernel launched so far
 };
@@ -91,6 +97,8 @@ void build_clover(lq_ctx* ctx, double kappa, double csw);
 void sap_apply(lq_ctx* ctx, void* out, const void* in, const lq_sap_params& q);
 bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_params& q,
                lq_solve_report* rep);
+bool solve_sap_dr(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_params& q,
+                  lq_solve_report* rep);  // FGMRES-DR (q.deflate > 0)
 void sap_destroy(Sap* sp);
 void free_clover(lq_ctx* ctx);
 
@@ -98,6 +106,7 @@ void free_clover(lq_ctx* ctx);
 // device (with that device current); the Schur operator that uses it
 void noalloc_init(int device);
 void schur_noalloc(lq_ctx* ctx, void* out, const void* in, int dagger, int prec, int nrhs);
+
 
 // blas.hip
 void norm2(lq_ctx* ctx, double* out_host, const void* a, int prec);
@@ -110,6 +119,7 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
            int nrhs, double kappa, double csw, double tol, const lq_solver_params* params,
            lq_solve_report* report, Net* net = nullptr);
 void free_work(lq_ctx* ctx);
+void free_block_work(lq_ctx* ctx);
 // Pieces of one solve, for the uneven batch (ensemble.hip): the work fields
 // of inner precision `inner` (allocated on first use); right-hand side setup
 // from a full-lattice FP64 device field (bhat, x = 0; returns |b|^2);
@@ -123,6 +133,29 @@ struct SolveFields {
 struct SolveTally {
   int iterations = 0, reliable = 0, fallback = 0, dslash = 0;
 };
+
+// krylov.hip: FGMRES with deflated restarting on FP32 fields of n complex
+// entries (one parity: halves = 1; a full field, even half then odd half:
+// halves = 2), FP64 residual and solution.  The callbacks apply the
+// preconditioner z = K v and the operator w = A z (FP32 fields), and
+// recompute r64 = b - A x64 in FP64 returning |r64|^2; they count their own
+// operator sweeps.
+struct KrylovSpace {
+  int64_t n = 0;
+  int halves = 1;
+  int64_t vh = 0;  // sites per parity (the rest of each half is padding)
+  void* x64 = nullptr;
+  void* r64 = nullptr;
+  std::function<void(void*, const void*)> precond, op;
+  std::function<double()> residual64;
+};
+// Returns true when |r64| <= target; false on maxiter (breakdown = false) or
+// on a breakdown or three restarts without halving the residual
+// (breakdown = true).  Counts iterations (preconditioned steps) and
+// restarts (as reliable updates) in t.
+bool fgmres_dr(lq_ctx* ctx, const KrylovSpace& S, int m, int k, double target, int maxiter,
+               SolveTally& t, bool& breakdown);
+void free_krylov(lq_ctx* ctx);
 SolveFields solve_fields(lq_ctx* ctx, int inner);
 double solve_begin(lq_ctx* ctx, void* dev_x, const void* dev_b, double* bhat_norm);
 bool solve_more(lq_ctx* ctx, int inner, double target, int maxiter, int check_every,
@@ -139,6 +172,7 @@ void mrhs_unpack(lq_ctx* ctx, double2* dst_dev, const void* dev, int parity, int
                  int r);
 void mrhs_dslash(lq_ctx* ctx, void* out, const void* in, int out_parity, int dagger, int nrhs);
 void mrhs_schur(lq_ctx* ctx, void* out, const void* in, void* tmp, int dagger, int nrhs);
+void mrhs_normal(lq_ctx* ctx, void* q32, const void* p, void* t, void* q1, int nrhs);
 MRWork* mrhs_work(lq_ctx* ctx, int nrhs);
 void free_mrhs_work(lq_ctx* ctx);
 void mrhs_tables(lq_ctx* ctx, bool clover);  // build the FP16 operator copies if stale
@@ -160,6 +194,8 @@ double net_loss_grad(Net* n, const void* b, const void* x, int npairs);
 void net_adam(Net* n, double lr, double b1, double b2, double eps);
 void net_train(Net* n, const void* b, const void* x, int npairs, int epochs, int batch, double lr,
                unsigned seed, double* hist);
+void net_save(Net* n, const char* path);
+void net_load(Net* n, const char* path);
 // complex BLAS on one-parity fields (elementwise over complex entries)
 void caxpy_f32(lq_ctx* ctx, void* y, double cr, double ci, const void* x);        // y += c x
 void caxpy_64_32(lq_ctx* ctx, void* y64, double cr, double ci, const void* x32);  // y += c x

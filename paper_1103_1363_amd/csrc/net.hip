@@ -27,6 +27,11 @@
 #include <cstring>
 #include <vector>
 
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
 #include "dslash_core.h"
 #include "lq_internal.h"
 #include "reduce.h"
@@ -52,6 +57,7 @@ struct Net {
   void* fbuf[2] = {nullptr, nullptr};  // FP16 full fields of the fast path (lazy)
   unsigned* wh = nullptr;   // the applied weight set as FP16 pairs [L][9][16][2]
   int64_t step = 0;
+  uint64_t rng = 0x9e3779b97f4a7c15ull;  // shuffle generator of the training batches (seed 0)
   bool adj_ok = false;
 };
 
@@ -1122,7 +1128,10 @@ void net_train(Net* n, const void* b, const void* x, int npairs, int epochs, int
   const size_t hb = parity_field_bytes(ctx->geo.nblk, LQ_F32);
   std::vector<int> perm(npairs);
   for (int i = 0; i < npairs; ++i) perm[i] = i;
-  uint64_t st = 0x9e3779b97f4a7c15ull ^ seed;
+  // seed 0 continues the generator where the last training (or the
+  // checkpoint it was loaded from) left it
+  if (seed != 0) n->rng = 0x9e3779b97f4a7c15ull ^ seed;
+  uint64_t& st = n->rng;
   auto rnd = [&st]() {  // splitmix64
     st += 0x9e3779b97f4a7c15ull;
     uint64_t z = st;
@@ -1132,6 +1141,9 @@ void net_train(Net* n, const void* b, const void* x, int npairs, int epochs, int
   };
   net_zero_grad(n);
   for (int e = 0; e < epochs; ++e) {
+    // each epoch's order depends on the generator state alone (a
+    // checkpoint then resumes it exactly)
+    for (int i = 0; i < npairs; ++i) perm[i] = i;
     for (int i = npairs - 1; i > 0; --i) std::swap(perm[i], perm[(int)(rnd() % (uint64_t)(i + 1))]);
     double tot = 0.0;
     for (int s0 = 0; s0 < npairs; s0 += batch) {
@@ -1148,6 +1160,84 @@ void net_train(Net* n, const void* b, const void* x, int npairs, int epochs, int
     }
     if (hist) hist[e] = tot / npairs;
   }
+}
+
+// Checkpoint: one line of JSON (format, version, layers, Adam step, shuffle
+// generator state, byte counts), then the FP32 weights and the two Adam
+// moment arrays as stored on the device ([L][9][16] (re, im) each), so that
+// training resumed from it continues exactly as if it had not stopped.
+void net_save(Net* n, const char* path) {
+  LQ_CHECK(path && *path, LQ_EINVAL, "no checkpoint path");
+  const size_t cnt = (size_t)n->L * NET_W;
+  std::vector<float2> w(cnt), m1(cnt), m2(cnt);
+  LQ_HIP(hipStreamSynchronize(n->ctx->cur));
+  LQ_HIP(hipMemcpy(w.data(), n->w, cnt * sizeof(float2), hipMemcpyDeviceToHost));
+  LQ_HIP(hipMemcpy(m1.data(), n->m1, cnt * sizeof(float2), hipMemcpyDeviceToHost));
+  LQ_HIP(hipMemcpy(m2.data(), n->m2, cnt * sizeof(float2), hipMemcpyDeviceToHost));
+  char head[512];
+  std::snprintf(head, sizeof head,
+                "{\"format\": \"lq-net-checkpoint\", \"version\": 1, \"layers\": %d, "
+                "\"adam_step\": %lld, \"shuffle_state\": \"%016llx\", \"arrays\": "
+                "[\"weights\", \"adam_m\", \"adam_v\"], \"bytes_per_array\": %zu, "
+                "\"dtype\": \"float32 (re, im) pairs, little endian\"}\n",
+                n->L, (long long)n->step, (unsigned long long)n->rng, cnt * sizeof(float2));
+  FILE* f = std::fopen(path, "wb");
+  LQ_CHECK(f != nullptr, LQ_EINVAL, std::string("cannot write ") + path);
+  bool ok = std::fputs(head, f) >= 0;
+  for (const auto* v : {&w, &m1, &m2})
+    ok = ok && std::fwrite(v->data(), sizeof(float2), cnt, f) == cnt;
+  ok = (std::fclose(f) == 0) && ok;
+  LQ_CHECK(ok, LQ_EINVAL, std::string("write failed: ") + path);
+}
+
+namespace {
+// the value after "key": in a one-line JSON object (numbers and strings)
+std::string json_field(const std::string& j, const std::string& key) {
+  const size_t k = j.find("\"" + key + "\"");
+  if (k == std::string::npos) return "";
+  size_t c = j.find(':', k);
+  if (c == std::string::npos) return "";
+  ++c;
+  while (c < j.size() && (j[c] == ' ' || j[c] == '"')) ++c;
+  size_t e = c;
+  while (e < j.size() && j[e] != ',' && j[e] != '"' && j[e] != '}') ++e;
+  return j.substr(c, e - c);
+}
+}  // namespace
+
+void net_load(Net* n, const char* path) {
+  LQ_CHECK(path && *path, LQ_EINVAL, "no checkpoint path");
+  FILE* f = std::fopen(path, "rb");
+  LQ_CHECK(f != nullptr, LQ_EINVAL, std::string("cannot read ") + path);
+  std::string head;
+  for (int c; (c = std::fgetc(f)) != EOF && c != '\n' && head.size() < 4096;) head.push_back((char)c);
+  const size_t cnt = (size_t)n->L * NET_W;
+  std::vector<float2> w(cnt), m1(cnt), m2(cnt);
+  bool ok = json_field(head, "format") == "lq-net-checkpoint" && json_field(head, "version") == "1";
+  const std::string layers = json_field(head, "layers"), step = json_field(head, "adam_step"),
+                    rng = json_field(head, "shuffle_state"),
+                    bytes = json_field(head, "bytes_per_array");
+  if (!ok || layers.empty() || step.empty() || rng.empty() || bytes.empty()) {
+    std::fclose(f);
+    throw Error(LQ_EINVAL, std::string("not an lq net checkpoint: ") + path);
+  }
+  if (std::atoi(layers.c_str()) != n->L || std::strtoull(bytes.c_str(), nullptr, 10) !=
+                                               cnt * sizeof(float2)) {
+    std::fclose(f);
+    throw Error(LQ_EINVAL, "checkpoint has another number of layers");
+  }
+  for (auto* v : {&w, &m1, &m2}) ok = ok && std::fread(v->data(), sizeof(float2), cnt, f) == cnt;
+  std::fclose(f);
+  LQ_CHECK(ok, LQ_EINVAL, std::string("checkpoint truncated: ") + path);
+  for (const float2& z : w)
+    LQ_CHECK(std::isfinite(z.x) && std::isfinite(z.y), LQ_EINVAL, "non-finite weight in checkpoint");
+  LQ_HIP(hipMemcpy(n->w, w.data(), cnt * sizeof(float2), hipMemcpyHostToDevice));
+  LQ_HIP(hipMemcpy(n->m1, m1.data(), cnt * sizeof(float2), hipMemcpyHostToDevice));
+  LQ_HIP(hipMemcpy(n->m2, m2.data(), cnt * sizeof(float2), hipMemcpyHostToDevice));
+  LQ_HIP(hipMemset(n->grad, 0, cnt * sizeof(double2)));
+  n->step = std::strtoll(step.c_str(), nullptr, 10);
+  n->rng = std::strtoull(rng.c_str(), nullptr, 16);
+  n->adj_ok = false;
 }
 
 void caxpy_f32(lq_ctx* ctx, void* y, double cr, double ci, const void* x) {

@@ -19,7 +19,9 @@
 #include <cstring>
 
 #include "bicgstab_kernels.h"
+#include "blockcg_kernels.h"
 #include "mrhs_kernels.h"
+#include "small_dense.h"
 #include "solver_kernels.h"
 
 namespace lq {
@@ -258,6 +260,22 @@ double schur_residual(lq_ctx* ctx, Work* w, SolveStats& ss) {
   axpby64(ctx, w->r64, 1.0, w->bhat, -1.0, w->te);
   ss.dslash += 2;
   return nrm2(ctx, w->r64);
+}
+
+// ||x - xref|| / ||xref|| of two full-lattice FP64 fields (even half, odd
+// half), in the work space's FP64 scratch fields.
+double ref_error(lq_ctx* ctx, Work* w, const void* x, const void* xref) {
+  const size_t hb = parity_field_bytes(w->nblk, LQ_F64);
+  const char* xc = reinterpret_cast<const char*>(x);
+  const char* rc = reinterpret_cast<const char*>(xref);
+  double d2 = 0.0, r2 = 0.0;
+  for (int h = 0; h < 2; ++h) {
+    void* tmp = h ? w->to : w->te;
+    axpby64(ctx, tmp, 1.0, xc + h * hb, -1.0, rc + h * hb);
+    d2 += nrm2(ctx, tmp);
+    r2 += nrm2(ctx, rc + h * hb);
+  }
+  return r2 > 0.0 ? std::sqrt(d2 / r2) : (d2 > 0.0 ? INFINITY : 0.0);
 }
 
 // Normal residual of the restart: r = Mhat^+ r64 in the vector precision and
@@ -795,14 +813,45 @@ bool fcg_net(lq_ctx* ctx, Work* w, Net* net, double target, int maxiter, SolveSt
   }
 }
 
+// FGMRES with deflated restarting (krylov.hip) on Mhat with N_e on the
+// right: FP32 even fields, restarts from the FP64 Schur residual.
+bool fgmres_dr_net(lq_ctx* ctx, Work* w, Net* net, double target, int maxiter, int m, int k,
+                   SolveStats& ss, bool& fb) {
+  const size_t f32 = parity_field_bytes(ctx->geo.nblk, LQ_F32);
+  void* to32 = f32_buf(w->nx, 1, f32);
+  const int L = net_layers(net);
+  KrylovSpace S;
+  S.n = ctx->geo.nblk * SB * 12;
+  S.halves = 1;
+  S.vh = ctx->geo.vh;
+  S.x64 = w->x;
+  S.r64 = w->r64;
+  S.precond = [&](void* z, const void* v) {
+    net_apply_even_fast(net, z, v, false);
+    ss.dslash += 2 * L;
+  };
+  S.op = [&](void* o, const void* z) {
+    schur(ctx, o, z, to32, 0, LQ_F32);
+    ss.dslash += 2;
+  };
+  S.residual64 = [&]() { return schur_residual(ctx, w, ss); };
+  SolveTally t;
+  t.iterations = ss.iterations;
+  const bool conv = fgmres_dr(ctx, S, m, k, target, maxiter, t, fb);
+  ss.iterations = t.iterations;
+  ss.reliable += t.reliable;
+  return conv;
+}
+
 bool run_inner(lq_ctx* ctx, Work* w, int solver, int inner, double target, double delta,
                int maxiter, int check_every, bool use_graph, int fault_inject, SolveStats& ss,
-               bool& fb, Prof* pf, Net* net, int restart) {
+               bool& fb, Prof* pf, Net* net, int restart, int deflate) {
   if (solver == LQ_FGMRES_NET || solver == LQ_FCG_NET) {
     // the plain mixed CG takes over where the flexible solver gave up
-    const bool conv = solver == LQ_FGMRES_NET
-                          ? fgmres_net(ctx, w, net, target, maxiter, restart, ss, fb)
-                          : fcg_net(ctx, w, net, target, maxiter, ss, fb);
+    const bool conv =
+        solver == LQ_FCG_NET ? fcg_net(ctx, w, net, target, maxiter, ss, fb)
+        : deflate > 0        ? fgmres_dr_net(ctx, w, net, target, maxiter, restart, deflate, ss, fb)
+                             : fgmres_net(ctx, w, net, target, maxiter, restart, ss, fb);
     if (conv) return true;
     fb = false;
     ss.fallback = 1;
@@ -1159,9 +1208,424 @@ void solve_batched(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_
       rep.schur_residual = bhn[r] > 0.0 ? std::sqrt(schur2[r]) / bhn[r] : 0.0;
       rep.seconds = std::chrono::duration<double>(t1 - t0).count();
       rep.bytes = ctx->bytes - bytes0;  // whole batch
+      rep.ref_error = p.dev_xref ? ref_error(ctx, w, mw->x64[r],
+                                             reinterpret_cast<const char*>(p.dev_xref) + r * fb)
+                                 : -1.0;
     }
   }
   if (!ok) throw Error(LQ_ENOCONV, "a right-hand side of the batch did not reach the tolerance");
+}
+
+// ------------------------------------------------------------ block CG
+// Block CG (O'Leary) for the nrhs right-hand sides of a batch on the normal
+// equations Mhat^+ Mhat X = Mhat^+ Bhat: one block Krylov space shared by all
+// of them, in the breakdown-free form that keeps the search block P
+// orthonormal and drops directions that became dependent (or belong to
+// solved right-hand sides).  An iteration:
+//   Q = Mhat^+ Mhat P           (the multi-RHS operator, FP16 on the matrix cores)
+//   alpha = (P^H Q)^-1 P^H R,   X += P alpha,  R -= Q alpha
+//   beta = -(P^H Q)^-1 Q^H R,   W = R + P beta,  P = W T
+// with T = V Lambda^-1/2 from W^H W = V Lambda V^H (eigenvalues below 1e-10
+// of the largest dropped).  X and R are FP32 multi-RHS fields, P and Q FP16.
+// Reliable updates per right-hand side, as in the batched CG: when its
+// recursive normal residual fell by delta since its last update, or below
+// its target, X_j is added to the FP64 solution, the FP64 Schur residual is
+// recomputed and R_j replaced by the FP32 normal residual of it (a solved
+// right-hand side gets R_j = 0); Q^H R is then recomputed for beta.
+}  // namespace
+
+struct BlockWork {
+  int nrhs = 0;
+  void *q1 = nullptr, *qb = nullptr, *wv = nullptr;  // FP16 even, FP32 even (Q), FP32 even (W)
+  double2* part = nullptr;   // [BCG_GRID][2][16][16]
+  double2* res = nullptr;    // [2][16][16]
+  double2* hres = nullptr;   // pinned
+  float2* coef = nullptr;    // [16][16]
+  float2* hcoef = nullptr;   // pinned
+};
+
+void free_block_work(lq_ctx* ctx) {
+  BlockWork* bw = ctx->bwork;
+  if (!bw) return;
+  for (void* q : {bw->q1, bw->qb, bw->wv, (void*)bw->part, (void*)bw->res, (void*)bw->coef})
+    if (q) (void)hipFree(q);
+  if (bw->hres) (void)hipHostFree(bw->hres);
+  if (bw->hcoef) (void)hipHostFree(bw->hcoef);
+  delete bw;
+  ctx->bwork = nullptr;
+}
+
+namespace {
+
+BlockWork* block_work(lq_ctx* ctx, int nrhs) {
+  BlockWork* bw = ctx->bwork;
+  if (bw && bw->nrhs != nrhs) {
+    free_block_work(ctx);
+    bw = nullptr;
+  }
+  if (!bw) {
+    bw = new BlockWork();
+    ctx->bwork = bw;
+    bw->nrhs = nrhs;
+    const size_t f16 = mrhs_field_bytes(ctx->geo.nblk, LQ_F16, nrhs);
+    const size_t f32 = mrhs_field_bytes(ctx->geo.nblk, LQ_F32, nrhs);
+    bw->q1 = dalloc(f16);
+    bw->qb = dalloc(f32);
+    bw->wv = dalloc(f32);
+    bw->part = reinterpret_cast<double2*>(dalloc(sizeof(double2) * BCG_GRID * 2 * 256));
+    bw->res = reinterpret_cast<double2*>(dalloc(sizeof(double2) * 2 * 256));
+    bw->coef = reinterpret_cast<float2*>(dalloc(sizeof(float2) * 256));
+    LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&bw->hres), sizeof(double2) * 2 * 256));
+    LQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&bw->hcoef), sizeof(float2) * 256));
+  }
+  return bw;
+}
+
+// The launches of one block-CG stage for the padded width KM.
+template <int KM>
+struct BlockOps {
+  lq_ctx* ctx;
+  MRWork* mw;
+  BlockWork* bw;
+  int K;
+  MField<P16> f16(void* d) const { return mfield_at<P16>(d, ctx->mr_geo.nblk, K); }
+  MField<P32> f32(void* d) const { return mfield_at<P32>(d, ctx->mr_geo.nblk, K); }
+  // the two K x K matrices of a Gram launch, summed, to the host: [m][i][j]
+  void fetch(int nm) {
+    const int nent = nm * KM * KM;
+    hipLaunchKernelGGL(bcg_sum_kernel, dim3(nent), dim3(256), 0, ctx->cur, bw->part, BCG_GRID,
+                       nent, bw->res);
+    LQ_HIP(hipGetLastError());
+    LQ_HIP(hipMemcpyAsync(bw->hres, bw->res, sizeof(double2) * nent, hipMemcpyDeviceToHost,
+                          ctx->cur));
+    LQ_HIP(hipStreamSynchronize(ctx->cur));
+  }
+  void upload(const std::vector<dense::cplx>& m) {  // K x K -> [KM][KM] FP32
+    LQ_HIP(hipStreamSynchronize(ctx->cur));
+    for (int i = 0; i < KM; ++i)
+      for (int j = 0; j < KM; ++j) {
+        const dense::cplx z = (i < K && j < K) ? m[(size_t)i * K + j] : dense::cplx(0.0);
+        bw->hcoef[i * KM + j] = make_float2((float)z.real(), (float)z.imag());
+      }
+    LQ_HIP(hipMemcpyAsync(bw->coef, bw->hcoef, sizeof(float2) * KM * KM, hipMemcpyHostToDevice,
+                          ctx->cur));
+  }
+  dense::cplx h(int m, int i, int j) const {
+    const double2 v = bw->hres[(m * KM + i) * KM + j];
+    return {v.x, v.y};
+  }
+  double site_bytes(double n16, double n32) const {
+    return K * (n16 * spinor_site_bytes(LQ_F16) + n32 * spinor_site_bytes(LQ_F32));
+  }
+  void gram_pq(void* p16, void* q32, void* r32) {  // G0 = P^H Q, G1 = P^H R
+    hipLaunchKernelGGL((bcg_gram_kernel<KM, P16, P32>), dim3(BCG_GRID), dim3(BCG_THREADS), 0,
+                       ctx->cur, ctx->mr_geo, f16(p16), f32(q32), f32(r32), bw->part);
+    LQ_HIP(hipGetLastError());
+    ctx->bytes += site_bytes(1, 2) * (double)ctx->geo.vh;
+    fetch(2);
+  }
+  void gram_qr(void* q32, void* r32) {  // G0 = Q^H Q, G1 = Q^H R
+    hipLaunchKernelGGL((bcg_gram_kernel<KM, P32, P32>), dim3(BCG_GRID), dim3(BCG_THREADS), 0,
+                       ctx->cur, ctx->mr_geo, f32(q32), f32(q32), f32(r32), bw->part);
+    LQ_HIP(hipGetLastError());
+    ctx->bytes += site_bytes(0, 2) * (double)ctx->geo.vh;
+    fetch(2);
+  }
+  void update() {  // coef = alpha
+    hipLaunchKernelGGL(bcg_update_kernel<KM>, dim3(BCG_GRID), dim3(BCG_THREADS), 0, ctx->cur,
+                       ctx->mr_geo, f16(mw->p), f32(bw->qb), f32(mw->x), f32(mw->r), bw->coef,
+                       bw->part);
+    LQ_HIP(hipGetLastError());
+    ctx->bytes += site_bytes(1, 5) * (double)ctx->geo.vh;
+    fetch(2);
+  }
+  void dir(bool with_p) {  // coef = beta (W = R when with_p is false)
+    hipLaunchKernelGGL(bcg_dir_kernel<KM>, dim3(BCG_GRID), dim3(BCG_THREADS), 0, ctx->cur,
+                       ctx->mr_geo, f16(mw->p), f32(mw->r), f32(bw->wv), bw->coef, (int)with_p,
+                       bw->part);
+    LQ_HIP(hipGetLastError());
+    ctx->bytes += site_bytes(with_p ? 1 : 0, 2) * (double)ctx->geo.vh;
+    fetch(1);
+  }
+  void orth() {  // coef = T
+    hipLaunchKernelGGL(bcg_orth_kernel<KM>, dim3(BCG_GRID), dim3(BCG_THREADS), 0, ctx->cur,
+                       ctx->mr_geo, f32(bw->wv), f16(mw->p), bw->coef);
+    LQ_HIP(hipGetLastError());
+    ctx->bytes += site_bytes(1, 1) * (double)ctx->geo.vh;
+  }
+};
+
+// T (K x K, columns past the returned rank zero) with W T orthonormal, from
+// G = W^H W; rank 0 when W vanishes.
+int block_orth_factor(int K, const std::vector<dense::cplx>& G, std::vector<dense::cplx>& T) {
+  std::vector<dense::cplx> a = G, v;
+  std::vector<double> lam;
+  dense::hermitian_eig(K, a, lam, v);
+  T.assign((size_t)K * K, 0.0);
+  const double top = lam.empty() ? 0.0 : lam.back();
+  if (!(top > 0.0) || !std::isfinite(top)) return 0;
+  int rank = 0;
+  for (int e = K - 1; e >= 0; --e) {  // largest first
+    if (!(lam[e] > 1e-10 * top)) break;
+    const double sc = 1.0 / std::sqrt(lam[e]);
+    for (int i = 0; i < K; ++i) T[(size_t)i * K + rank] = v[(size_t)i * K + e] * sc;
+    ++rank;
+  }
+  return rank;
+}
+
+// x = G_rr^-1 Y on the leading rank x rank block (rows past the rank zero);
+// false if singular
+bool block_solve(int K, int rank, const std::vector<dense::cplx>& G,
+                 const std::vector<dense::cplx>& Y, std::vector<dense::cplx>& X) {
+  X.assign((size_t)K * K, 0.0);
+  for (int j = 0; j < K; ++j) {
+    std::vector<dense::cplx> a((size_t)rank * rank), b(rank);
+    for (int r = 0; r < rank; ++r) {
+      for (int c = 0; c < rank; ++c) a[(size_t)r * rank + c] = G[(size_t)r * K + c];
+      b[r] = Y[(size_t)r * K + j];
+    }
+    if (rank > 0 && !dense::solve(rank, a, b)) return false;
+    for (int r = 0; r < rank; ++r) X[(size_t)r * K + j] = b[r];
+  }
+  return true;
+}
+
+template <int KM>
+bool block_iterate(lq_ctx* ctx, Work* w, MRWork* mw, BlockWork* bw, int nrhs,
+                   const std::vector<double>& bhn, std::vector<int>& done, double frac, double tol,
+                   double delta, int maxiter, SolveStats& ss) {
+  BlockOps<KM> op{ctx, mw, bw, nrhs};
+  const int K = nrhs;
+  std::vector<double> rr(K, 0.0), rr_max(K, 0.0), target2(K, 0.0);
+  // start: X = 0, R_j = the FP32 normal residual of the FP64 residual
+  auto refresh = [&](int j, bool first) -> void {
+    if (!first) mrhs_single_from_slot(ctx, mw, mw->x, LQ_F32, mw->x64[j], j, 1.0, 1.0);
+    mrhs_slot_from_single(ctx, mw, mw->x, LQ_F32, w->r64, j, 0.0, 0.0);
+    w->x = mw->x64[j];
+    w->bhat = mw->bhat[j];
+    const double t2 = schur_residual(ctx, w, ss);
+    const double target = frac * tol * bhn[j];
+    if (done[j] || t2 <= target * target) {
+      done[j] = 1;
+      mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->r64, j, 0.0, 0.0);
+      rr[j] = 0.0;
+      return;
+    }
+    const double rn = normal_residual32(ctx, w, ss);
+    mrhs_slot_from_single(ctx, mw, mw->r, LQ_F32, w->r[LQ_F16], j, 1.0, 0.0, LQ_F32);
+    rr[j] = rr_max[j] = rn;
+    target2[j] = target * target * rn / t2 * 0.25;
+  };
+  for (int j = 0; j < K; ++j) refresh(j, true);
+  auto all_done = [&] {
+    for (int j = 0; j < K; ++j)
+      if (!done[j]) return false;
+    return true;
+  };
+  if (all_done()) return true;
+  // P = orth(R): W = R (beta = 0), then T from W^H W
+  std::vector<dense::cplx> G((size_t)K * K), Y((size_t)K * K), Z, T;
+  op.upload(std::vector<dense::cplx>((size_t)K * K, 0.0));
+  op.dir(false);
+  for (int i = 0; i < K; ++i)
+    for (int j = 0; j < K; ++j) G[(size_t)i * K + j] = op.h(0, i, j);
+  int rank = block_orth_factor(K, G, T);
+  op.upload(T);
+  op.orth();
+  int stall_ref_iter = ss.iterations;
+  double stall_ref = *std::max_element(rr.begin(), rr.end());
+  while (rank > 0) {
+    if (ss.iterations >= maxiter) return false;
+    mrhs_normal(ctx, bw->qb, mw->p, mw->t, bw->q1, K);
+    ss.dslash += 4;  // (mr_hop counts the sweeps' bytes)
+    op.gram_pq(mw->p, bw->qb, mw->r);
+    std::vector<dense::cplx> PQ((size_t)K * K), PR((size_t)K * K), alpha;
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j) {
+        PQ[(size_t)i * K + j] = op.h(0, i, j);
+        PR[(size_t)i * K + j] = op.h(1, i, j);
+      }
+    if (!block_solve(K, rank, PQ, PR, alpha)) return false;
+    op.upload(alpha);
+    op.update();
+    ss.iterations += 1;
+    std::vector<dense::cplx> QR((size_t)K * K);
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j) QR[(size_t)i * K + j] = op.h(0, i, j);
+    bool replaced = false;
+    for (int j = 0; j < K; ++j) {
+      if (done[j]) continue;
+      rr[j] = op.h(1, j, j).real();
+      if (!std::isfinite(rr[j])) return false;
+      if (rr[j] < delta * delta * rr_max[j] || rr[j] <= target2[j]) {
+        refresh(j, false);
+        ss.reliable += 1;
+        replaced = true;
+      }
+    }
+    if (all_done()) return true;
+    if (replaced) {  // Q^H R with the replaced columns
+      op.gram_qr(bw->qb, mw->r);
+      for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j) QR[(size_t)i * K + j] = op.h(1, i, j);
+    }
+    // stagnation: the largest normal residual must quarter within 300 iterations
+    const double worst = *std::max_element(rr.begin(), rr.end());
+    if (worst <= 0.25 * stall_ref) {
+      stall_ref = worst;
+      stall_ref_iter = ss.iterations;
+    } else if (ss.iterations - stall_ref_iter >= 300) {
+      return false;
+    }
+    std::vector<dense::cplx> beta;
+    for (auto& z : QR) z = -z;
+    if (!block_solve(K, rank, PQ, QR, beta)) return false;
+    op.upload(beta);
+    op.dir(true);
+    for (int i = 0; i < K; ++i)
+      for (int j = 0; j < K; ++j) G[(size_t)i * K + j] = op.h(0, i, j);
+    rank = block_orth_factor(K, G, T);
+    op.upload(T);
+    op.orth();
+  }
+  // the search block vanished: every remaining direction is solved to
+  // rounding; one last refresh decides
+  for (int j = 0; j < K; ++j)
+    if (!done[j]) refresh(j, false);
+  return all_done();
+}
+
+void solve_block(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x,
+                 const void* dev_b, int nrhs, double tol, const lq_solver_params& p,
+                 lq_solve_report* report) {
+  LQ_CHECK(nrhs >= 1 && nrhs <= MR_MAX, LQ_EINVAL, "block CG takes 1..16 right-hand sides");
+  LQ_CHECK(p.solver == LQ_CGNR, LQ_EINVAL, "block CG runs on the normal equations (LQ_CGNR)");
+  auto t0 = std::chrono::steady_clock::now();
+  const double bytes0 = ctx->bytes;
+  Work* w = work(ctx, LQ_F16);
+  work(ctx, LQ_F64);
+  MRWork* mw = mrhs_work(ctx, nrhs);
+  BlockWork* bw = block_work(ctx, nrhs);
+  mrhs_tables(ctx, true);
+  const int64_t nb = ctx->geo.nblk;
+  const int64_t nsite = ctx->V;
+  const size_t hb = (size_t)nsite * 12 * 16;
+  const size_t fb = 2 * parity_field_bytes(nb, LQ_F64);
+  const double kappa = ctx->clov.kappa;
+  const int maxiter = p.maxiter > 0 ? p.maxiter : 20000;
+  const double delta = p.delta > 0.0 ? p.delta : 0.1;
+  void* bhat_own = w->bhat;
+  void* x_own = w->x;
+  void* b_own = w->b;
+  std::vector<double> b2(nrhs), bhn(nrhs), res2(nrhs, 0.0), schur2(nrhs, 0.0);
+  std::vector<int> done(nrhs, 0);
+  SolveStats ss;
+  for (int r = 0; r < nrhs; ++r) {
+    if (host_b) {
+      double2* stg = reinterpret_cast<double2*>(staging(ctx, hb));
+      LQ_HIP(hipMemcpyAsync(stg, host_b + (size_t)r * nsite * 24, hb, hipMemcpyHostToDevice,
+                            ctx->cur));
+      pack_spinor(ctx, mw->b64[r], stg, LQ_F64, LQ_FULL);
+    } else {
+      LQ_HIP(hipMemcpyAsync(mw->b64[r], reinterpret_cast<const char*>(dev_b) + r * fb, fb,
+                            hipMemcpyDeviceToDevice, ctx->cur));
+    }
+    w->b = mw->b64[r];
+    w->x = mw->x64[r];
+    w->bhat = mw->bhat[r];
+    b2[r] = nrm2(ctx, w->b) + nrm2(ctx, odd_half(w->b, nb));
+    clover_apply(ctx, w->to, odd_half(w->b, nb), LQ_ODD, 1, LQ_F64);
+    dslash(ctx, w->te, w->to, LQ_EVEN, 0, LQ_F64);
+    axpby64(ctx, w->bhat, 1.0, w->b, kappa, w->te);
+    bhn[r] = std::sqrt(nrm2(ctx, w->bhat));
+    zero<P64>(ctx, w->x);
+    zero<P64>(ctx, odd_half(w->x, nb));
+    if (b2[r] == 0.0) done[r] = 1;
+  }
+  double frac = 0.5;
+  for (int round = 0; round < 4; ++round) {
+    const int KM = nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : nrhs <= 12 ? 12 : 16;
+    bool conv = false;
+    switch (KM) {
+      case 4: conv = block_iterate<4>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss); break;
+      case 8: conv = block_iterate<8>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss); break;
+      case 12: conv = block_iterate<12>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss); break;
+      default: conv = block_iterate<16>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss);
+    }
+    if (!conv) {  // finish the unsolved right-hand sides with plain FP64 CG
+      ss.fallback = 1;
+      for (int r = 0; r < nrhs; ++r) {
+        if (done[r]) continue;
+        mrhs_single_from_slot(ctx, mw, mw->x, LQ_F32, mw->x64[r], r, 1.0, 1.0);
+        w->b = mw->b64[r];
+        w->x = mw->x64[r];
+        w->bhat = mw->bhat[r];
+        SolveStats f_ss;
+        bool fb = false;
+        run_cg(ctx, w, LQ_F64, frac * tol * bhn[r], 0.0, maxiter, 8, true, 0, f_ss, fb, nullptr);
+        ss.iterations += f_ss.iterations;
+        ss.dslash += f_ss.dslash + 4 * f_ss.iterations;
+        done[r] = 1;
+      }
+    }
+    bool all_ok = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (b2[r] == 0.0) continue;
+      w->b = mw->b64[r];
+      w->x = mw->x64[r];
+      w->bhat = mw->bhat[r];
+      res2[r] = reconstruct_and_residual(ctx, w, ss);
+      if (res2[r] > tol * tol * b2[r]) {
+        all_ok = false;
+        done[r] = 0;
+      }
+    }
+    if (all_ok) break;
+    frac *= 0.5;
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    w->b = mw->b64[r];
+    w->x = mw->x64[r];
+    w->bhat = mw->bhat[r];
+    if (host_x) {
+      double2* stg = reinterpret_cast<double2*>(staging(ctx, hb));
+      unpack_spinor(ctx, stg, w->x, LQ_F64, LQ_FULL);
+      LQ_HIP(hipMemcpyAsync(host_x + (size_t)r * nsite * 24, stg, hb, hipMemcpyDeviceToHost,
+                            ctx->cur));
+      LQ_HIP(hipStreamSynchronize(ctx->cur));
+    } else {
+      LQ_HIP(hipMemcpyAsync(reinterpret_cast<char*>(dev_x) + r * fb, w->x, fb,
+                            hipMemcpyDeviceToDevice, ctx->cur));
+    }
+    schur2[r] = b2[r] == 0.0 ? 0.0 : schur_residual(ctx, w, ss);
+  }
+  LQ_HIP(hipStreamSynchronize(ctx->cur));
+  w->bhat = bhat_own;
+  w->x = x_own;
+  w->b = b_own;
+  auto t1 = std::chrono::steady_clock::now();
+  bool ok = true;
+  for (int r = 0; r < nrhs; ++r) {
+    const bool conv = b2[r] == 0.0 || res2[r] <= tol * tol * b2[r];
+    ok = ok && conv;
+    if (report) {
+      lq_solve_report& rep = report[r];
+      std::memset(&rep, 0, sizeof(rep));
+      rep.iterations = ss.iterations;
+      rep.reliable_updates = ss.reliable;
+      rep.fallback = ss.fallback;
+      rep.dslash_calls = ss.dslash;
+      rep.true_residual = b2[r] > 0.0 ? std::sqrt(res2[r] / b2[r]) : 0.0;
+      rep.schur_residual = bhn[r] > 0.0 ? std::sqrt(schur2[r]) / bhn[r] : 0.0;
+      rep.seconds = std::chrono::duration<double>(t1 - t0).count();
+      rep.bytes = ctx->bytes - bytes0;
+      rep.ref_error = p.dev_xref ? ref_error(ctx, w, mw->x64[r],
+                                             reinterpret_cast<const char*>(p.dev_xref) + r * fb)
+                                 : -1.0;
+    }
+  }
+  if (!ok) throw Error(LQ_ENOCONV, "a right-hand side of the block solve did not reach the tolerance");
 }
 
 }  // namespace
@@ -1181,8 +1645,11 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
   LQ_CHECK(!net_solver || net, LQ_EINVAL,
            "learned-preconditioner solvers take a net (lq_solve_net)");
   LQ_CHECK(!net || net_ctx(net) == ctx, LQ_EINVAL, "the net belongs to another context");
-  const int restart = p.restart > 0 ? p.restart : 32;
+  const int restart = p.restart > 0 ? p.restart : (p.deflate > 0 ? 70 : 32);
   LQ_CHECK(restart <= 128, LQ_EINVAL, "restart length above 128");
+  LQ_CHECK(p.deflate >= 0 && (p.deflate == 0 || (p.solver == LQ_FGMRES_NET &&
+                                                  p.deflate < restart && p.deflate <= 32)),
+           LQ_EINVAL, "deflate: 1..min(restart-1, 32) deflated vectors, with LQ_FGMRES_NET only");
   const int maxiter = p.maxiter > 0 ? p.maxiter : 20000;
   const double delta = inner == LQ_F64 ? 0.0 : (p.delta > 0.0 ? p.delta : 0.1);
   const int check_every = p.check_every > 0 ? p.check_every : 8;
@@ -1193,6 +1660,11 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
   ctx->cur = ctx->sstream;
   if (!ctx->clov.valid || ctx->clov.kappa != kappa || ctx->clov.csw != csw)
     build_clover(ctx, kappa, csw);
+  if (p.batched == 2) {
+    LQ_CHECK(inner == LQ_F16, LQ_EINVAL, "block CG runs its inner iteration in FP16");
+    solve_block(ctx, host_x, host_b, dev_x, dev_b, nrhs, tol, p, report);
+    return;
+  }
   if (p.batched && nrhs > 1) {
     LQ_CHECK(inner == LQ_F16, LQ_EINVAL, "batched solves run their inner iteration in FP16");
     solve_batched(ctx, host_x, host_b, dev_x, dev_b, nrhs, tol, p, report);
@@ -1263,7 +1735,7 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
                                  use_graph, 0, inner_ss, fb, prof)
                         : run_inner(ctx, w, p.solver, inner, frac * tol * bhat_norm, delta, left,
                                     check_every, use_graph, p.fault_inject, inner_ss, fb, prof,
-                                    net, restart);
+                                    net, restart, p.deflate);
         ss.iterations += inner_ss.iterations;
         ss.reliable += inner_ss.reliable;
         // the flexible solvers count their own operator applications
@@ -1307,6 +1779,10 @@ void solve(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x, const
       r.schur_residual = bhat_norm > 0.0 ? std::sqrt(schur2) / bhat_norm : 0.0;
       r.seconds = std::chrono::duration<double>(t1 - t0).count();
       r.bytes = ctx->bytes - bytes0;
+      r.ref_error = p.dev_xref ? ref_error(ctx, w, w->x,
+                                           reinterpret_cast<const char*>(p.dev_xref) +
+                                               (size_t)rhs * 2 * parity_field_bytes(w->nblk, LQ_F64))
+                               : -1.0;
       for (int k = 0; k < LQ_NK; ++k) {
         r.kernel_bytes[k] = kb[k] * (double)ctx->geo.vh;
         r.kernel_ms[k] = prof ? prof->ms[k] : 0.0;

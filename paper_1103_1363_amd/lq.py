@@ -36,7 +36,7 @@ class SolverParams(ct.Structure):
     _fields_ = [("solver", ct.c_int), ("inner_prec", ct.c_int), ("maxiter", ct.c_int),
                 ("delta", ct.c_double), ("restart", ct.c_int), ("check_every", ct.c_int),
                 ("use_graph", ct.c_int), ("fault_inject", ct.c_int), ("profile", ct.c_int),
-                ("batched", ct.c_int)]
+                ("batched", ct.c_int), ("deflate", ct.c_int), ("dev_xref", ct.c_void_p)]
 
 
 class SolveReport(ct.Structure):
@@ -45,7 +45,7 @@ class SolveReport(ct.Structure):
                 ("true_residual", ct.c_double), ("schur_residual", ct.c_double),
                 ("seconds", ct.c_double), ("bytes", ct.c_double),
                 ("kernel_ms", ct.c_double * 5), ("kernel_bytes", ct.c_double * 5),
-                ("kernel_calls", ct.c_int * 5)]
+                ("kernel_calls", ct.c_int * 5), ("ref_error", ct.c_double)]
 
     def as_dict(self):
         d = {}
@@ -57,7 +57,7 @@ class SolveReport(ct.Structure):
 
 class SapParams(ct.Structure):
     _fields_ = [("block", ct.c_int * 4), ("ncycles", ct.c_int), ("nmr", ct.c_int),
-                ("restart", ct.c_int), ("maxiter", ct.c_int)]
+                ("restart", ct.c_int), ("maxiter", ct.c_int), ("deflate", ct.c_int)]
 
 
 class EnsembleReport(ct.Structure):
@@ -107,6 +107,17 @@ def lib():
         L.lq_clover_apply.argtypes = [vp, vp, vp, ip, ip, ip, ip]
         L.lq_schur.argtypes = [vp, vp, vp, vp, ip, ip, ip]
         L.lq_schur_noalloc.argtypes = [vp, vp, vp, ip, ip, ip]
+        L.lq_stream_copy.argtypes = [vp, vp, ct.c_size_t, vp]
+        L.lq_stream_copy.restype = ip
+        L.lq_site_array_bytes.argtypes = [ct.c_int64, ip, ip]
+        L.lq_site_array_bytes.restype = ct.c_size_t
+        L.lq_site_array_to_device.argtypes = [vp, dp, ct.c_int64, ip, ip, vp]
+        L.lq_site_array_to_host.argtypes = [dp, vp, ct.c_int64, ip, ip, vp]
+        L.lq_su3_mul.argtypes = [vp, vp, vp, vp, ct.c_int64, ip, ip, vp]
+        L.lq_su3_spinor_mul.argtypes = [vp, vp, vp, ct.c_int64, ip, ip, vp]
+        for name in ("lq_site_array_to_device", "lq_site_array_to_host", "lq_su3_mul",
+                     "lq_su3_spinor_mul"):
+            getattr(L, name).restype = ip
         L.lq_norm2.argtypes = [vp, dp, vp, ip, ip]
         L.lq_dot.argtypes = [vp, dp, vp, vp, ip, ip]
         L.lq_solve.argtypes = [vp, dp, dp, ip, ct.c_double, ct.c_double, ct.c_double,
@@ -123,6 +134,8 @@ def lib():
         L.lq_net_loss_grad.argtypes = [vp, vp, vp, ip, dp, dp]
         L.lq_net_adam_step.argtypes = [vp, ct.c_double, ct.c_double, ct.c_double, ct.c_double]
         L.lq_net_train.argtypes = [vp, vp, vp, ip, ip, ip, ct.c_double, ct.c_uint, dp]
+        L.lq_net_save.argtypes = [vp, ct.c_char_p]
+        L.lq_net_load.argtypes = [vp, ct.c_char_p]
         L.lq_solve_net.argtypes = [vp, vp, dp, dp, ip, ct.c_double, ct.c_double, ct.c_double,
                                    ct.POINTER(SolverParams), ct.POINTER(SolveReport)]
         L.lq_sap_apply.argtypes = [vp, vp, vp, ct.POINTER(SapParams)]
@@ -145,7 +158,8 @@ def lib():
                      "lq_norm2", "lq_dot", "lq_solve", "lq_solve_device", "lq_sap_apply",
                      "lq_solve_sap", "lq_net_create",
                      "lq_net_set_weights", "lq_net_get_weights", "lq_net_init_neumann", "lq_net_apply",
-                     "lq_net_loss_grad", "lq_net_adam_step", "lq_net_train", "lq_solve_net"):
+                     "lq_net_loss_grad", "lq_net_adam_step", "lq_net_train", "lq_solve_net",
+                     "lq_net_save", "lq_net_load"):
             getattr(L, name).restype = ip
         _lib = L
     return _lib
@@ -178,6 +192,7 @@ class Report:
     kernel_ms: list
     kernel_bytes: list
     kernel_calls: list
+    ref_error: float = -1.0
 
 
 class Lattice:
@@ -287,7 +302,8 @@ class Lattice:
               delta=0.0, restart=0, check_every=0, use_graph=0, fault_inject=0,
               profile=0, batched=0, raise_on_noconv=True):
         """Solve M x = b on the full lattice; b has shape (nrhs?, V-sites..., 4, 3).
-        batched=1 runs all right-hand sides through the multi-RHS operator."""
+        batched=1 runs all right-hand sides through the multi-RHS operator as
+        independent CG recurrences, batched=2 as one block CG."""
         b = np.ascontiguousarray(b, dtype=np.complex128)
         nrhs = b.size // (self.volume * 12)
         assert nrhs * self.volume * 12 == b.size
@@ -305,10 +321,12 @@ class Lattice:
     def solve_device(self, dev_x, dev_b, kappa, csw, tol=1e-10, nrhs=1, solver=CGNR,
                      inner_prec=F64, maxiter=0, delta=0.0, restart=0, check_every=0,
                      use_graph=0, fault_inject=0, profile=0, batched=0,
-                     raise_on_noconv=True):
-        """Solve with device-resident full-lattice FP64 fields (see lq_solve_device)."""
+                     raise_on_noconv=True, xref=None):
+        """Solve with device-resident full-lattice FP64 fields (see lq_solve_device);
+        xref: optional device reference solution(s), reported as ref_error."""
         p = SolverParams(solver, inner_prec, maxiter, delta, restart, check_every, use_graph,
-                         fault_inject, profile, batched)
+                         fault_inject, profile, batched, 0,
+                         xref.data_ptr() if xref is not None else None)
         reps = (SolveReport * nrhs)()
         rc = self._L.lq_solve_device(self._h, ct.c_void_p(dev_x.data_ptr()),
                                      ct.c_void_p(dev_b.data_ptr()), nrhs, float(kappa),
@@ -321,9 +339,9 @@ class Lattice:
 
     # -- SAP preconditioner and FGCR ------------------------------------
     @staticmethod
-    def _sap_params(block, ncycles, nmr, restart=0, maxiter=0):
+    def _sap_params(block, ncycles, nmr, restart=0, maxiter=0, deflate=0):
         return SapParams((ct.c_int * 4)(*[int(b) for b in block]), int(ncycles), int(nmr),
-                         int(restart), int(maxiter))
+                         int(restart), int(maxiter), int(deflate))
 
     def sap_apply(self, dev_out, dev_in, block, ncycles=0, nmr=0):
         """dev_out = K dev_in on full-lattice FP32 fields (see lq_sap_apply)."""
@@ -332,9 +350,11 @@ class Lattice:
                                          ct.c_void_p(dev_in.data_ptr()), ct.byref(p)))
 
     def solve_sap_device(self, dev_x, dev_b, kappa, csw, tol=1e-10, block=(4, 4, 4, 4),
-                         ncycles=0, nmr=0, restart=0, maxiter=0, raise_on_noconv=True):
-        """SAP-preconditioned FGCR on full-lattice FP64 device fields (see lq_solve_sap)."""
-        p = self._sap_params(block, ncycles, nmr, restart, maxiter)
+                         ncycles=0, nmr=0, restart=0, maxiter=0, raise_on_noconv=True,
+                         deflate=0):
+        """SAP-preconditioned FGCR, or FGMRES-DR with `deflate` deflated vectors, on
+        full-lattice FP64 device fields (see lq_solve_sap)."""
+        p = self._sap_params(block, ncycles, nmr, restart, maxiter, deflate)
         rep = SolveReport()
         rc = self._L.lq_solve_sap(self._h, ct.c_void_p(dev_x.data_ptr()),
                                   ct.c_void_p(dev_b.data_ptr()), float(kappa), float(csw),
@@ -415,15 +435,22 @@ class Net:
                                              _dptr(hist)))
         return hist
 
+    def save(self, path):
+        """Checkpoint weights, Adam moments and step, shuffle state (lq_net_save)."""
+        self.lat._check(self._L.lq_net_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        self.lat._check(self._L.lq_net_load(self._h, str(path).encode()))
+
     def solve(self, b, kappa, csw, tol=1e-10, solver=FGMRES_NET, maxiter=0, restart=0,
-              raise_on_noconv=True):
+              raise_on_noconv=True, deflate=0):
         """Solve M x = b (full lattice, host arrays) with a flexible solver
-        preconditioned by this net."""
+        preconditioned by this net (FGMRES-DR when deflate > 0)."""
         b = np.ascontiguousarray(b, dtype=np.complex128)
         nrhs = b.size // (self.lat.volume * 12)
         assert nrhs * self.lat.volume * 12 == b.size
         x = np.zeros_like(b)
-        p = SolverParams(solver, F32, maxiter, 0.0, restart, 0, 0, 0, 0, 0)
+        p = SolverParams(solver, F32, maxiter, 0.0, restart, 0, 0, 0, 0, 0, deflate)
         reps = (SolveReport * nrhs)()
         rc = self._L.lq_solve_net(self.lat._h, self._h, _dptr(x.view(np.float64)),
                                   _dptr(b.view(np.float64)), nrhs, float(kappa), float(csw),
@@ -490,3 +517,56 @@ class Ensemble:
         if rc != 0 and (rc != -4 or raise_on_noconv):
             self._check(rc)
         return reports, er.as_dict()
+
+
+# ---------------------------------------------------------------- fused site expressions
+SITE_SU3, SITE_SPINOR = 0, 1
+SU3_VW, SU3_VWDAG, SU3_VDAGW, SU3_VWX = 0, 1, 2, 3
+
+
+def _stream():
+    return ct.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _expr_check(rc, what):
+    if rc != 0:
+        raise LQError(rc, what)
+
+
+def site_array_bytes(n, kind, prec):
+    return int(lib().lq_site_array_bytes(int(n), kind, prec))
+
+
+def site_array_to_device(host, kind, prec):
+    """Host (n, 3, 3) matrices or (n, 4, 3) spinors, complex128 -> device array."""
+    host = np.ascontiguousarray(host, dtype=np.complex128)
+    n = host.shape[0]
+    torch = _torch()
+    dev = torch.empty(site_array_bytes(n, kind, prec), dtype=torch.uint8, device="cuda")
+    _expr_check(lib().lq_site_array_to_device(ct.c_void_p(dev.data_ptr()),
+                                              _dptr(host.view(np.float64)), n, kind, prec,
+                                              _stream()), "lq_site_array_to_device")
+    return dev
+
+
+def site_array_to_host(dev, n, kind, prec):
+    shape = (n, 3, 3) if kind == SITE_SU3 else (n, 4, 3)
+    out = np.empty(shape, dtype=np.complex128)
+    _expr_check(lib().lq_site_array_to_host(_dptr(out.view(np.float64)),
+                                            ct.c_void_p(dev.data_ptr()), n, kind, prec,
+                                            _stream()), "lq_site_array_to_host")
+    return out
+
+
+def su3_mul(out, v, w, n, form=SU3_VW, prec=F64, x=None):
+    """out = V W (or the form's product) on n matrices; one fused kernel."""
+    _expr_check(lib().lq_su3_mul(ct.c_void_p(out.data_ptr()), ct.c_void_p(v.data_ptr()),
+                                 ct.c_void_p(w.data_ptr()),
+                                 ct.c_void_p(x.data_ptr() if x is not None else 0), int(n),
+                                 form, prec, _stream()), "lq_su3_mul")
+
+
+def su3_spinor_mul(out, u, psi, n, adjoint=False, prec=F64):
+    _expr_check(lib().lq_su3_spinor_mul(ct.c_void_p(out.data_ptr()), ct.c_void_p(u.data_ptr()),
+                                        ct.c_void_p(psi.data_ptr()), int(n), int(adjoint), prec,
+                                        _stream()), "lq_su3_spinor_mul")

@@ -282,3 +282,60 @@ def test_training_gain(lq):
     # counts with FP16 arithmetic inside the net vary by a couple
     assert its["trained"] * 1.5 < its["identity"]
     assert its["trained"] <= its["neumann"] + 3
+
+
+@pytest.mark.parametrize("m,k", [(16, 4), (24, 8)])
+def test_net_fgmres_dr(lq, m, k):
+    """FGMRES with deflated restarts and the net (Neumann start) on the
+    right: the solution meets the tolerance by the oracle's residual without
+    falling back."""
+    dims, tol = (8, 8, 8, 8), 1e-10
+    say(f"net FGMRES-DR m={m} k={k}")
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 1)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 23)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    net = lq.Net(lat, 4)
+    net.set_weights(onet.neumann_weights(KAPPA, 4))
+    x, rep = net.solve(b, KAPPA, CSW, tol, solver=lq.FGMRES_NET, restart=m, deflate=k)
+    res = oracle_residual(u, KAPPA, CSW, x, b)
+    say(f"  iterations={rep[0].iterations} restarts={rep[0].reliable_updates} "
+        f"fallback={rep[0].fallback} res={res:.2e}")
+    assert res <= tol
+    assert rep[0].fallback == 0
+
+
+def test_checkpoint_resume_matches_uninterrupted_training(lq, tmp_path):
+    """Four epochs in one go against two epochs, a checkpoint, a fresh net
+    loaded from it, and two more epochs continuing the shuffle generator:
+    the weights agree bit for bit, and so does the loss history."""
+    dims = (4, 4, 4, 4)
+    u, _, _, _ = case(dims, "smooth", 1)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    b, x = even_fields(dims, 6, 30), even_fields(dims, 6, 31)
+    db, dx = lat.to_device(b, lq.EVEN, lq.F32), lat.to_device(x, lq.EVEN, lq.F32)
+    w0 = onet.neumann_weights(KAPPA, 3)
+    full = lq.Net(lat, 3)
+    full.set_weights(w0)
+    h_full = full.train(db, dx, 6, epochs=4, batch=2, lr=5e-3, seed=5)
+    part = lq.Net(lat, 3)
+    part.set_weights(w0)
+    h1 = part.train(db, dx, 6, epochs=2, batch=2, lr=5e-3, seed=5)
+    path = tmp_path / "net.ckpt"
+    part.save(path)
+    head = open(path, "rb").readline().decode()
+    assert '"format": "lq-net-checkpoint"' in head and '"layers": 3' in head
+    resumed = lq.Net(lat, 3)
+    resumed.load(path)
+    h2 = resumed.train(db, dx, 6, epochs=2, batch=2, lr=5e-3, seed=0)
+    assert np.array_equal(resumed.get_weights(), full.get_weights())
+    assert np.array_equal(np.concatenate([h1, h2]), h_full)
+    # a net of another depth, and a damaged file, are refused
+    with pytest.raises(lq.LQError):
+        lq.Net(lat, 2).load(path)
+    data = open(path, "rb").read()
+    bad = tmp_path / "bad.ckpt"
+    open(bad, "wb").write(data[: len(data) // 2])
+    with pytest.raises(lq.LQError):
+        lq.Net(lat, 3).load(bad)

@@ -247,3 +247,32 @@ def test_full_size_batched_point_sources(lq):
     say(f"  largest sampled site residual {worst:.2e} (bound {tol:.2e})")
     assert worst <= 1.01 * tol
 
+
+
+@pytest.mark.parametrize("batched", [0, 1])
+def test_reference_error_in_report(lq, batched):
+    """With a reference solution on the device the report gives
+    ||x - xref|| / ||xref|| per right-hand side; it equals the same norm
+    taken on the host, and the mixed solves agree with the FP64 CG to about
+    the condition number times the tolerance."""
+    dims, kappa, csw, tol = (8, 4, 4, 8), 0.135, 1.0, 1e-10
+    say(f"reference error batched={batched}")
+    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 7)
+    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 7, nrhs=2)
+    lat = lq.Lattice(dims)
+    lat.upload_gauge(u)
+    db = lat.to_device(b, lq.FULL, lq.F64)
+    dref = lat.new_field(lq.FULL, lq.F64, 2)
+    lat.solve_device(dref, db, kappa, csw, 1e-12, nrhs=2, inner_prec=lq.F64)
+    dx = lat.new_field(lq.FULL, lq.F64, 2)
+    reps = lat.solve_device(dx, db, kappa, csw, tol, nrhs=2, inner_prec=lq.F16,
+                            batched=batched, xref=dref)
+    x = lat.to_host(dx, lq.FULL, lq.F64, 2)
+    xr = lat.to_host(dref, lq.FULL, lq.F64, 2)
+    for r in range(2):
+        host = np.linalg.norm(x[r] - xr[r]) / np.linalg.norm(xr[r])
+        say(f"  rhs {r}: ref_error {reps[r].ref_error:.3e} host {host:.3e}")
+        assert abs(reps[r].ref_error - host) <= 1e-3 * host + 1e-16
+        assert reps[r].ref_error <= 1e-7
+    reps = lat.solve_device(dx, db, kappa, csw, tol, nrhs=2, inner_prec=lq.F16)
+    assert all(r.ref_error == -1.0 for r in reps)
