@@ -290,7 +290,7 @@ __global__ __launch_bounds__(BCG_THREADS) void bcg_orth_kernel(Geo g, MField<P32
       }
       const int64_t s = s0 + sl;
       p.norm[s * K + j] = m;
-      const float inv = m > 0.f ? 1.f / m : 0.f;
+      const float inv = scale_inv(m);
 #pragma unroll
       for (int c = 0; c < 12; ++c)
         p.d[(s * K + j) * 12 + c] = __floats2half2_rn(inv * v[c].x, inv * v[c].y);

@@ -55,6 +55,17 @@ __host__ __device__ inline int64_t link_idx(int64_t nblk, int p, int mu, int64_t
   return ((((int64_t)p * 4 + mu) * nblk + (s >> 6)) * 6 + c) * SB + (s & 63);
 }
 
+// Reciprocal of an FP16 field's per-site (or per-site, per-RHS) scale m, the
+// largest component magnitude: 0 when m is below the smallest normal FP32
+// number.  Such components are far below any rounding level of the solvers
+// (the fronts of point-source Krylov vectors reach it on large lattices) and
+// are stored as zero; 1 / m of a denormal m would overflow to infinity.
+__device__ __forceinline__ float scale_inv(float m) {
+  return m >= 1.17549435e-38f ? 1.f / m : 0.f;
+}
+__device__ __forceinline__ float scale_rcp(float m) {  // the same, hardware reciprocal
+  return m >= 1.17549435e-38f ? __builtin_amdgcn_rcpf(m) : 0.f;
+}
 
 // ---------------------------------------------------------------- complex
 template <class R>
@@ -233,7 +244,7 @@ __device__ __forceinline__ void store_spinor(const Field<P>& f, int64_t s,
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
     f.norm[s] = m;
-    float inv = m > 0.f ? 1.f / m : 0.f;
+    const float inv = scale_inv(m);
 #pragma unroll
     for (int c = 0; c < 12; ++c) st<P>(f.d, spin_idx(s, c), inv * v[c]);
   } else {

@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void mr_p_update(Geo g, const MRState* __restr
     }
 #pragma unroll
     for (int k = 0; k < 24; ++k) mx = fmaxf(mx, fabsf(o[k]));
-    const float inv = mx > 0.f ? 1.f / mx : 0.f;
+    const float inv = scale_inv(mx);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       mr_u4 wv;

@@ -450,7 +450,7 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
         xb[1] = mr_u2{xv[2], xv[3]};
       } else {
         // FP16 operand: the hop sum scaled by 1 / (largest neighbour scale)
-        const float cs = colmax > 0.f ? __builtin_amdgcn_rcpf(colmax) : 0.f;
+        const float cs = scale_rcp(colmax);
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
           xb[cb] = mr_u2{mr_pack(cs * acc[4 * cb], cs * acc[4 * cb + 1]),
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(MR_BLK) void mrhs_hop_kernel(
     mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
     mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
     if (bl) {
-      const float inv = mx > 0.f ? __builtin_amdgcn_rcpf(mx) : 0.f;
+      const float inv = scale_rcp(mx);
       mr_u4 o;
 #pragma unroll
       for (int k = 0; k < 4; ++k) o[k] = mr_pack(inv * y[2 * k], inv * y[2 * k + 1]);

@@ -256,7 +256,7 @@ __device__ __forceinline__ float load_h(const Field<P>& f, unsigned s, unsigned 
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(x[c].re), fabsf(x[c].im)));
-    const float inv = m > 0.f ? 1.f / m : 0.f;
+    const float inv = scale_inv(m);
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[c] = pack_h(inv * x[c].re, inv * x[c].im);
     return m;
@@ -273,7 +273,7 @@ __device__ __forceinline__ void store_h(const Field<P>& f, unsigned s, const C<f
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
     at32(f.norm, s) = m;
-    const float inv = m > 0.f ? 1.f / m : 0.f;
+    const float inv = scale_inv(m);
     unsigned* d = reinterpret_cast<unsigned*>(f.d);
 #pragma unroll
     for (int c = 0; c < 12; ++c) at32(d, b + 64u * c) = pack_h(inv * v[c].re, inv * v[c].im);
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(NET_MBLK) __attribute__((amdgpu_waves_per_eu(4))) v
   float cmax = 0.f;
 #pragma unroll
   for (int h = 0; h < 9; ++h) cmax = fmaxf(cmax, fabsf(c[h]));
-  const float rinv = cmax > 0.f ? 1.f / cmax : 0.f;
+  const float rinv = scale_inv(cmax);
   const int gg = lane >> 4, i = lane & 15;
   // D[4 P + q]: colours 2 P + (row / 8) of sites 16 q .. 16 q + 15
   nf4 D[8];

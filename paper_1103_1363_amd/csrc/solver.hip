@@ -1394,7 +1394,7 @@ bool block_solve(int K, int rank, const std::vector<dense::cplx>& G,
 template <int KM>
 bool block_iterate(lq_ctx* ctx, Work* w, MRWork* mw, BlockWork* bw, int nrhs,
                    const std::vector<double>& bhn, std::vector<int>& done, double frac, double tol,
-                   double delta, int maxiter, SolveStats& ss) {
+                   double delta, int maxiter, SolveStats& ss, bool& nonfinite) {
   BlockOps<KM> op{ctx, mw, bw, nrhs};
   const int K = nrhs;
   std::vector<double> rr(K, 0.0), rr_max(K, 0.0), target2(K, 0.0);
@@ -1457,7 +1457,10 @@ bool block_iterate(lq_ctx* ctx, Work* w, MRWork* mw, BlockWork* bw, int nrhs,
     for (int j = 0; j < K; ++j) {
       if (done[j]) continue;
       rr[j] = op.h(1, j, j).real();
-      if (!std::isfinite(rr[j])) return false;
+      if (!std::isfinite(rr[j])) {
+        nonfinite = true;
+        return false;
+      }
       if (rr[j] < delta * delta * rr_max[j] || rr[j] <= target2[j]) {
         refresh(j, false);
         ss.reliable += 1;
@@ -1546,18 +1549,20 @@ void solve_block(lq_ctx* ctx, double* host_x, const double* host_b, void* dev_x,
   double frac = 0.5;
   for (int round = 0; round < 4; ++round) {
     const int KM = nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : nrhs <= 12 ? 12 : 16;
-    bool conv = false;
+    bool conv = false, nonfinite = false;
     switch (KM) {
-      case 4: conv = block_iterate<4>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss); break;
-      case 8: conv = block_iterate<8>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss); break;
-      case 12: conv = block_iterate<12>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss); break;
-      default: conv = block_iterate<16>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss);
+      case 4: conv = block_iterate<4>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss, nonfinite); break;
+      case 8: conv = block_iterate<8>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss, nonfinite); break;
+      case 12: conv = block_iterate<12>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss, nonfinite); break;
+      default: conv = block_iterate<16>(ctx, w, mw, bw, nrhs, bhn, done, frac, tol, delta, maxiter, ss, nonfinite);
     }
     if (!conv) {  // finish the unsolved right-hand sides with plain FP64 CG
       ss.fallback = 1;
       for (int r = 0; r < nrhs; ++r) {
         if (done[r]) continue;
-        mrhs_single_from_slot(ctx, mw, mw->x, LQ_F32, mw->x64[r], r, 1.0, 1.0);
+        // the FP32 increment since the column's last reliable update, unless
+        // the iteration produced non-finite values (then restart from that update)
+        if (!nonfinite) mrhs_single_from_slot(ctx, mw, mw->x, LQ_F32, mw->x64[r], r, 1.0, 1.0);
         w->b = mw->b64[r];
         w->x = mw->x64[r];
         w->bhat = mw->bhat[r];

@@ -99,18 +99,29 @@ def pmc_counters(path, counter):
     return out
 
 
-COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_KERNELS = ("stream_copy_kernel", "__amd_rocclr_copyBuffer")
 COPY_BYTES = 1 << 30  # the benchmark's reference copy: 1 GiB read and 1 GiB written
+
+
+def copy_kernel(counts):
+    """Name of the reference copy among the profiled kernels: the library's
+    16-byte-per-lane streaming copy, else the runtime's copyBuffer."""
+    for want in COPY_KERNELS:
+        for name in counts:
+            if want in name:
+                return name
+    raise KeyError("no reference copy kernel in the counter file")
 
 
 def pmc_traffic(fetch_csv, write_csv, kernel=None):
     """HBM bytes per launch per kernel from FETCH_SIZE and WRITE_SIZE (KiB),
     each scaled so that the reference copy of COPY_BYTES reads and writes
-    exactly that many bytes (the largest copyBuffer dispatch is taken as it)."""
+    exactly that many bytes (the median dispatch of the copy kernel is taken
+    as it)."""
     fetch = pmc_counters(fetch_csv, "FETCH_SIZE")
     write = pmc_counters(write_csv, "WRITE_SIZE")
-    cf = COPY_BYTES / (max(fetch[COPY_KERNEL]) * 1024.0)
-    cw = COPY_BYTES / (max(write[COPY_KERNEL]) * 1024.0)
+    cf = COPY_BYTES / (statistics.median(fetch[copy_kernel(fetch)]) * 1024.0)
+    cw = COPY_BYTES / (statistics.median(write[copy_kernel(write)]) * 1024.0)
     rows = []
     for name in sorted(fetch):
         if kernel and kernel not in name:
