@@ -16,20 +16,29 @@ Printed (one JSON line):
                 timed with HIP events inside the library during one
                 profiled solve, priced against the 8 TB/s HBM peak;
   plain_fp64    the same solve with plain FP64 CG, for comparison;
-  dslash_gbs    stand-alone hopping-term sweeps per precision (HIP events);
+  dslash_gbs    stand-alone hopping-term sweeps per precision over three
+                rotated copies of the fields (HIP events per launch), beside the
+                library's 16-byte streaming copy (hbm_copy), the achievable HBM
+                bandwidth;
+  fused_expressions
+                the SU(3) array product of the paper's worked example and a
+                three-factor product fused into one pass against two passes;
   batched_12rhs the 12 spin-colour point sources of a propagator solved
                 together through the multi-RHS operator (FP16 on the matrix
-                cores), beside one point source solved alone (plain FP64 and
-                mixed FP16) scaled by 12;
+                cores) as independent recurrences and as one block CG, beside
+                one point source solved alone (plain FP64 and mixed FP16)
+                scaled by 12;
   learned_preconditioner
-                a 4-layer gauge-covariant net trained on the GPU on
+                a 4-layer gauge-covariant net trained on the GPU on 2000
                 (source, solution) pairs the solver generated on a 16^3x32
-                field, then used on the benchmark's 32^3x64 field in flexible
-                CG and FGMRES, beside the plain solves of the same system;
+                field (weights kept by held-out solve iterations), then used on
+                the benchmark's 32^3x64 field in flexible CG, FGMRES and
+                FGMRES-DR, beside its Neumann start;
   uneven_batch  eight lattices of different volumes and kappas solved as one
                 batch, beside the same solves one after another;
   sap_fgcr      the paper's own solver on the benchmark system: FGCR with the
-                SAP preconditioner (FP32 block MR, FP64 restarts), and one SAP
+                SAP preconditioner (FP32 block MR, FP64 restarts), the same
+                preconditioner in FGMRES with deflated restarting, and one SAP
                 application alone;
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample.
 
@@ -57,82 +66,6 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def dslash_rates(lq, lat, torch, b_full, nrep=50):
-    """Stand-alone even-odd hopping sweeps H_eo on the 32^3x64 field per
-    precision, timed with torch events on the stream the library launches on."""
-    out = {}
-    vh = lat.volume // 2
-    for name, prec in (("f64", lq.F64), ("f32", lq.F32), ("f16", lq.F16)):
-        full = lat.to_device(b_full, lq.FULL, prec)
-        din = full[lat.field_bytes(lq.EVEN, prec):]  # odd half of the full field
-        dout = lat.new_field(lq.EVEN, prec)
-        for _ in range(5):
-            lat.dslash(dout, din, lq.EVEN, False, prec)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(nrep):
-            lat.dslash(dout, din, lq.EVEN, False, prec)
-        b.record()
-        torch.cuda.synchronize()
-        us = a.elapsed_time(b) * 1e3 / nrep
-        per_site = {"f64": 1152, "f32": 576, "f16": 296}[name]
-        gbs = per_site * vh / (us * 1e-6) / 1e9
-        out[name] = {"us": round(us, 2), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / 8000, 3),
-                     "GFLOP/s": round(1320 * vh / (us * 1e-6) / 1e9, 1)}
-        del full, din, dout
-    return out
-
-
-def copy_rate(torch, nbytes=1 << 30, nrep=20):
-    """A plain device-to-device copy of known size (1 GiB read + 1 GiB written):
-    the achievable HBM bandwidth on this machine, and the reference kernel that
-    scales the FETCH_SIZE / WRITE_SIZE counters."""
-    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(nrep):
-        dst.copy_(src)
-    b.record()
-    torch.cuda.synchronize()
-    s = a.elapsed_time(b) * 1e-3 / nrep
-    del src, dst
-    return {"bytes_per_copy": 2 * nbytes, "us": round(s * 1e6, 1),
-            "GB/s": round(2 * nbytes / s / 1e9, 1)}
-
-
-def mrhs_rate(lq, lat, torch, nrhs=12, nrep=30):
-    """Stand-alone multi-RHS hopping sweep H_eo on nrhs interleaved FP16
-    right-hand sides (algorithmic bytes: 8 links of 24 B plus 104 B of
-    spinor in and out per RHS and output site)."""
-    import numpy as np
-    vh = lat.volume // 2
-    rng = np.random.default_rng(7)
-    o = rng.standard_normal((nrhs, vh, 4, 3)) + 1j * rng.standard_normal((nrhs, vh, 4, 3))
-    din = lat.to_device(o, lq.ODD, lq.F16X)
-    dout = lat.new_field(lq.EVEN, lq.F16X, nrhs)
-    for _ in range(5):
-        lat.dslash(dout, din, lq.EVEN, False, lq.F16X, nrhs)
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(nrep):
-        lat.dslash(dout, din, lq.EVEN, False, lq.F16X, nrhs)
-    b.record()
-    torch.cuda.synchronize()
-    us = a.elapsed_time(b) * 1e3 / nrep
-    per_site = 8 * 24 + nrhs * 104
-    gbs = per_site * vh / (us * 1e-6) / 1e9
-    del din, dout
-    return {"nrhs": nrhs, "us": round(us, 2), "bytes_per_site": per_site, "GB/s": round(gbs, 1),
-            "frac_hbm": round(gbs / 8000, 3),
-            "GFLOP/s": round(1320 * nrhs * vh / (us * 1e-6) / 1e9, 1)}
-
-
 def batched_point_sources(lq, lat, torch, dims):
     """The 12 point sources at the origin solved as one batch, against one of
     them solved alone (plain FP64 CG and mixed FP16 CG) times 12."""
@@ -156,7 +89,18 @@ def batched_point_sources(lq, lat, torch, dims):
         torch.cuda.synchronize()
         single[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 2),
                         "iterations": r.iterations, "true_residual": r.true_residual}
+    lat.solve_device(dx, db, KAPPA, CSW, TOL, nrhs=12, inner_prec=lq.F16, batched=2)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rblk = lat.solve_device(dx, db, KAPPA, CSW, TOL, nrhs=12, inner_prec=lq.F16, batched=2)
+    torch.cuda.synchronize()
+    tblk = time.perf_counter() - t0
     out = {"rhs": 12, "sources": "point sources at the origin, one per (spin, colour)",
+           "block_cg": {"solve_ms": round(tblk * 1e3, 2), "iterations": rblk[0].iterations,
+                        "reliable_updates": rblk[0].reliable_updates,
+                        "fallback": rblk[0].fallback,
+                        "max_true_residual": max(r.true_residual for r in rblk),
+                        "operator_applications_vs_batched": None},
            "solve_ms": round(tb * 1e3, 2), "ms_per_rhs": round(tb * 1e3 / 12, 2),
            "iterations": reps[0].iterations, "reliable_updates": reps[0].reliable_updates,
            "fallback": reps[0].fallback,
@@ -164,6 +108,10 @@ def batched_point_sources(lq, lat, torch, dims):
            "one_source_alone": single,
            "speedup_vs_12x_plain_fp64": round(12 * single["plain_fp64"]["ms"] / (tb * 1e3), 3),
            "speedup_vs_12x_mixed_f16": round(12 * single["mixed_f16"]["ms"] / (tb * 1e3), 3)}
+    out["block_cg"]["operator_applications_vs_batched"] = round(
+        rblk[0].iterations / max(1, reps[0].iterations), 3)
+    out["block_cg"]["speedup_vs_12x_mixed_f16"] = round(
+        12 * single["mixed_f16"]["ms"] / (tblk * 1e3), 3)
     del db, dx, dx1
     return out
 
@@ -229,9 +177,14 @@ def uneven_batch(lq, torch):
 
 
 def learned_preconditioner(lq, lat, torch, db_bench, npairs, epochs):
-    """Train the net on pairs from a 16^3x32 field (its own gauge field and
-    sources), then solve the benchmark system (its source on the device,
-    db_bench) with it."""
+    """Train the net on (source, FP64 solution) pairs the solver generates on a
+    16^3x32 field (its own gauge field and sources), one epoch at a time.
+    After every epoch, flexible CG with the current weights solves a
+    held-out source on the training lattice; the weights with the fewest
+    iterations are kept, the Neumann start among the candidates, so the net
+    carried to the benchmark is never worse than its start on held-out data.
+    Then the benchmark system (its source on the device, db_bench) is solved
+    with the kept net, with its Neumann start, and with FGMRES-DR."""
     import numpy as np
     from gen import fields
     dt = (16, 16, 16, 32)
@@ -262,27 +215,55 @@ def learned_preconditioner(lq, lat, torch, db_bench, npairs, epochs):
     w0 = net.get_weights()
     l0, _ = net.loss_grad(db, dx, ntr)
     v0 = net.loss_grad(db[ntr * fb32:], dx[ntr * fb32:], nv)[0] if nv else None
-    t0 = time.perf_counter()
-    hist = net.train(db, dx, ntr, epochs=epochs, batch=8, lr=1e-3, seed=1)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    b_sel = fields.gaussian_spinor(dt, fields.SEED_TRAIN_SOURCE + 99999)  # held-out source
+
+    def sel_iterations(wts):  # resets the Adam state: callers restore it
+        net.set_weights(wts)
+        _, rep = net.solve(b_sel, KAPPA, CSW, TOL, solver=lq.FCG_NET)
+        return rep[0].iterations + (10 ** 6 if rep[0].fallback else 0)
+
+    best_w, best_it, best_epoch = w0, sel_iterations(w0), 0
+    sel = [best_it]
+    net.set_weights(w0)
+    hist = []
+    t_train = 0.0
+    for e in range(epochs):
+        t1 = time.perf_counter()
+        hist += list(net.train(db, dx, ntr, epochs=1, batch=8, lr=1e-3, seed=1 if e == 0 else 0))
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t1
+        w_e = net.get_weights()
+        # checkpoint the training state: selection solves leave the Adam state alone
+        ck = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"lq_net_{os.getpid()}.ckpt")
+        net.save(ck)
+        it = sel_iterations(w_e)
+        net.load(ck)
+        sel.append(it)
+        if it < best_it:
+            best_w, best_it, best_epoch = w_e, it, e + 1
     l1, _ = net.loss_grad(db, dx, ntr)
     v1 = net.loss_grad(db[ntr * fb32:], dx[ntr * fb32:], nv)[0] if nv else None
-    w = net.get_weights()
     del db, dx, dB, dX, net, tl
     bn = lq.Net(lat, 4)
     out = {"layers": 4, "train_lattice": list(dt), "pairs": npairs, "train_pairs": ntr,
            "epochs": epochs, "pair_generation_s": round(t_pairs, 2), "training_s": round(t_train, 2),
            "loss_train": [round(l0, 5), round(l1, 5)],
            "loss_valid": [round(v0, 5), round(v1, 5)] if nv else None,
-           "loss_history": [round(float(h), 5) for h in hist], "solves": {}}
+           "loss_history": [round(float(h), 5) for h in hist],
+           "selection": {"held_out_fcg_iterations_per_epoch": sel, "kept_epoch": best_epoch,
+                         "rule": "fewest flexible-CG iterations on a held-out 16^3x32 source; "
+                                 "epoch 0 = the Neumann start"},
+           "solves": {}}
     b_host = lat.to_host(db_bench, lq.FULL, lq.F64)
-    for name, wts, kind in (("fcg_trained", w, lq.FCG_NET), ("fcg_initial", w0, lq.FCG_NET),
-                            ("fgmres_trained", w, lq.FGMRES_NET)):
+    for name, wts, kind, kw in (("fcg_trained", best_w, lq.FCG_NET, {}),
+                                ("fcg_initial", w0, lq.FCG_NET, {}),
+                                ("fgmres_trained", best_w, lq.FGMRES_NET, {}),
+                                ("fgmres_dr_trained", best_w, lq.FGMRES_NET,
+                                 {"restart": 70, "deflate": 10})):
         bn.set_weights(wts)
-        t0 = time.perf_counter()
-        _, rep = bn.solve(b_host, KAPPA, CSW, TOL, solver=kind)
-        dt_s = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        _, rep = bn.solve(b_host, KAPPA, CSW, TOL, solver=kind, **kw)
+        dt_s = time.perf_counter() - t1
         out["solves"][name] = {"ms": round(dt_s * 1e3, 1), "iterations": rep[0].iterations,
                                "restarts": rep[0].reliable_updates, "fallback": rep[0].fallback,
                                "dslash_equivalents": rep[0].dslash_calls,
@@ -291,7 +272,7 @@ def learned_preconditioner(lq, lat, torch, db_bench, npairs, epochs):
     dn = lat.to_device(lat.to_host(db_bench[:lat.field_bytes(lq.EVEN, lq.F64)], lq.EVEN, lq.F64),
                        lq.EVEN, lq.F32)
     dy = lat.new_field(lq.EVEN, lq.F32)
-    bn.set_weights(w)
+    bn.set_weights(best_w)
     for _ in range(3):
         bn.apply(dy, dn, fp16=True)
     a = torch.cuda.Event(enable_timing=True)
@@ -327,18 +308,27 @@ def recorded_traffic(kernel):
     return None
 
 
-def sap_fgcr(lq, lat, torch, db, block, ncycles, nmr, restart):
+def sap_fgcr(lq, lat, torch, db, block, ncycles, nmr, restart, dr_m=70, dr_k=10):
     """The paper's own solver on the benchmark system: FGCR with the SAP
     preconditioner (FP32 block MR and inner FGCR, FP64 restarts), after one
-    warm-up solve; and one SAP application alone, with the algorithmic bytes
-    of its kernels (the library's own count)."""
+    warm-up solve; the same preconditioner in FGMRES with deflated
+    restarting (Krylov dimension dr_m including dr_k deflated vectors, the
+    paper's 70 and 10); and one SAP application alone, with the algorithmic
+    bytes of its kernels (the library's own count)."""
     dx = lat.new_field(lq.FULL, lq.F64)
     lat.solve_sap_device(dx, db, KAPPA, CSW, TOL, block, ncycles, nmr, restart)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rep = lat.solve_sap_device(dx, db, KAPPA, CSW, TOL, block, ncycles, nmr, restart)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
+    out = {"block": list(block), "ncycles": ncycles, "nmr": nmr}
+    for name, kw in (("fgcr", {"restart": restart}),
+                     ("fgmres_dr", {"restart": dr_m, "deflate": dr_k})):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = lat.solve_sap_device(dx, db, KAPPA, CSW, TOL, block, ncycles, nmr, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out[name] = {**kw, "ms": round(ms, 1), "steps": rep.iterations,
+                     "restarts": rep.reliable_updates, "true_residual": rep.true_residual,
+                     "GB/s": round(rep.bytes / (rep.seconds if rep.seconds > 0 else ms / 1e3)
+                                   / 1e9, 1)}
     e = lat.new_field(lq.FULL, lq.F32)
     y = lat.new_field(lq.FULL, lq.F32)
     e.copy_(lat.to_device(lat.to_host(db, lq.FULL, lq.F64), lq.FULL, lq.F32))
@@ -351,31 +341,116 @@ def sap_fgcr(lq, lat, torch, db, block, ncycles, nmr, restart):
         lat.sap_apply(y, e, block, ncycles, nmr)
     z.record()
     torch.cuda.synchronize()
-    apply_ms = a.elapsed_time(z) / 5
-    return {"block": list(block), "ncycles": ncycles, "nmr": nmr, "restart": restart,
-            "ms": round(ms, 1), "fgcr_steps": rep.iterations, "restarts": rep.reliable_updates,
-            "true_residual": rep.true_residual,
-            "GB/s": round(rep.bytes / (rep.seconds if rep.seconds > 0 else ms / 1e3) / 1e9, 1),
-            "sap_apply_ms": round(apply_ms, 3)}
+    out["sap_apply_ms"] = round(a.elapsed_time(z) / 5, 3)
+    return out
 
 
-def cpu_baseline(u, b, dims):
-    """The FP64 oracle on the host: one even-odd hopping sweep H_eo of the same
-    32^3x64 workload (a bounded sample of the solve, whose iterations each make
-    four such sweeps), priced with the same algorithmic byte count."""
-    from oracle import evenodd
-    from oracle import dirac
+def cpu_info():
+    model, cores = "unknown", os.cpu_count() or 1
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    return model, cores
+
+
+def cpu_baseline(u, b, dims, gpu_iters):
+    """The FP64 oracle (NumPy) on the host, timed on bounded samples of the
+    workloads (NumPy runs them on one thread: its element-wise and einsum
+    kernels do not spread over cores):
+      * one even-odd hopping sweep H_eo of the 32^3x64 benchmark field, priced
+        with the same 1152 algorithmic bytes per output site as the GPU sweep
+        (the value), and one of a 16^3x32 field;
+      * the whole 4^4 Wilson solve of the small configuration (even-odd CGNR
+        to 1e-10);
+      * one CGNR iteration on the 16^3x32 Schur operator (one application of
+        Mhat and one of Mhat^+; the vector updates are negligible beside
+        them), from which whole solves are extrapolated with the iteration
+        counts the GPU solves of this run needed (gpu_iters: name -> (sites
+        factor relative to 16^3x32, iterations)); each extrapolation says so."""
+    import numpy as np
+    from oracle import dirac, evenodd
+    from oracle import solvers
+    from gen import fields
+    model, ncpu = cpu_info()
     e, o = evenodd.split(b, dims)
     t0 = time.perf_counter()
-    full = evenodd.join(None, o, dims)
-    y = dirac.hop(u, full)
+    y = dirac.hop(u, evenodd.join(None, o, dims))
     evenodd.split(y, dims)
     dt = time.perf_counter() - t0
     vh = e.shape[0]
+    d16 = (16, 16, 16, 32)
+    vh16 = 16 * 16 * 16 * 32 // 2
+    u16 = fields.gauge_field(d16, "smooth", fields.SEED_GAUGE + 1)
+    b16 = fields.gaussian_spinor(d16, fields.SEED_SOURCE + 1)
+    t0 = time.perf_counter()
+    dirac.hop(u16, evenodd.join(None, evenodd.split(b16, d16)[1], d16))
+    dt16 = time.perf_counter() - t0
+    wc16 = evenodd.WilsonClover(u16, KAPPA, CSW)
+    bh16 = wc16.prepare_source(b16)
+    t0 = time.perf_counter()
+    z = wc16.schur(wc16.schur(bh16), dagger=True)
+    dit = time.perf_counter() - t0
+    del z
+    d4 = (4, 4, 4, 4)
+    u4 = fields.gauge_field(d4, "haar", fields.SEED_GAUGE)
+    b4 = fields.gaussian_spinor(d4, fields.SEED_SOURCE)
+    wc = evenodd.WilsonClover(u4, 0.12, 0.0)
+    t0 = time.perf_counter()
+    x4, info = solvers.solve_evenodd(wc, b4, tol=1e-10)
+    dt4 = time.perf_counter() - t0
+    extrap = {name: {"seconds": round(dit * f * it, 1), "iterations": it,
+                     "from": f"{f:g} x the 16^3x32 CGNR iteration x {it} iterations "
+                             "(the GPU plain FP64 solve's count)"}
+              for name, (f, it) in gpu_iters.items()}
     return {"value": round(1152 * vh / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "seconds": round(dt, 2),
+            "cpu_model": model, "host_cpus": ncpu, "seconds": round(dt, 2),
             "sample": "one FP64 even-odd hopping-term sweep (H_eo, 1152 algorithmic bytes per "
-                      "output site) of the 32^3x64 field by the NumPy oracle, single thread"}
+                      "output site) of the 32^3x64 field by the NumPy oracle, single thread",
+            "dslash_16x16x16x32": {"seconds": round(dt16, 3),
+                                   "GB/s": round(1152 * vh16 / dt16 / 1e9, 3)},
+            "cgnr_iteration_16x16x16x32": {"seconds": round(dit, 2),
+                                           "what": "Mhat then Mhat^+ on the 16^3x32 clover "
+                                                   "Schur operator"},
+            "solve_4x4x4x4_wilson": {"seconds": round(dt4, 3), "iterations": info.iterations,
+                                     "true_residual": info.true_residual},
+            "extrapolated_solves": extrap}
+
+
+def config_16(lq, torch):
+    """The 16^3x32 configuration (kappa 0.135, csw 1, smooth links, Gaussian
+    source): FP32 inner iteration with FP64 reliable updates against plain
+    FP64 CG.  Its fields (about 0.1 GB) stay in the 256 MB last-level cache,
+    so its rates are cache-resident, not HBM rates."""
+    from gen import fields
+    d16 = (16, 16, 16, 32)
+    u16 = fields.gauge_field(d16, "smooth", fields.SEED_GAUGE + 1)
+    b16 = fields.gaussian_spinor(d16, fields.SEED_SOURCE + 1)
+    lat = lq.Lattice(d16)
+    lat.upload_gauge(u16)
+    lat.set_clover(KAPPA, CSW)
+    db = lat.to_device(b16, lq.FULL, lq.F64)
+    dx = lat.new_field(lq.FULL, lq.F64)
+    out = {"lattice": list(d16), "note": "working set resident in the last-level cache"}
+    for name, prec in (("mixed_f32", lq.F32), ("mixed_f16", lq.F16), ("plain_fp64", lq.F64)):
+        lat.solve_device(dx, db, KAPPA, CSW, TOL, inner_prec=prec)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lat.solve_device(dx, db, KAPPA, CSW, TOL, inner_prec=prec)[0]
+        torch.cuda.synchronize()
+        out[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), "iterations": r.iterations,
+                     "reliable_updates": r.reliable_updates, "fallback": r.fallback,
+                     "true_residual": r.true_residual}
+    out["speedup_f32_vs_plain_fp64"] = round(out["plain_fp64"]["ms"] / out["mixed_f32"]["ms"], 3)
+    del lat, db, dx
+    return out
 
 
 def main():
@@ -391,8 +466,10 @@ def main():
     ap.add_argument("--no-net", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-sap", action="store_true")
-    ap.add_argument("--net-pairs", type=int, default=400)
+    ap.add_argument("--net-pairs", type=int, default=2000)
     ap.add_argument("--net-epochs", type=int, default=8)
+    ap.add_argument("--gauge-cache", default=None,
+                    help="an .npy file holding the benchmark gauge field (written if absent)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the library has no "
@@ -412,7 +489,12 @@ def main():
     dims = tuple(int(x) for x in a.dims.split(","))
     inner = {"f32": lq.F32, "f16": lq.F16}[a.inner]
     log(f"generating the {dims} smooth gauge field and source")
-    u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 2)
+    if a.gauge_cache and os.path.exists(a.gauge_cache):
+        u = np.load(a.gauge_cache)
+    else:
+        u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 2)
+        if a.gauge_cache:
+            np.save(a.gauge_cache, u)
     b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 2)
 
     lat = lq.Lattice(dims)
@@ -443,6 +525,9 @@ def main():
     result = {
         "metric": "Dslash GB/s & %HBM peak; solve time to 1e-10 residual, plain vs mixed/learned",
         "value": round(value, 1),
+        "value_is": "whole-solve algorithmic GB/s of the mixed FP16/FP64 solve (all its kernels' "
+                    "compulsory bytes / wall time); the stand-alone Dslash rates and their "
+                    "fractions of the 8 TB/s HBM peak are under dslash_gbs / dslash_frac_hbm",
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -526,10 +611,19 @@ def main():
                                   / 1e9, 1) if rprof.kernel_ms[i] > 0 else None}
         for i in range(5)}
 
-    log("stand-alone hopping-term sweeps")
-    result["dslash_gbs"] = dslash_rates(lq, lat, torch, b)
-    result["dslash_gbs"]["f16x12"] = mrhs_rate(lq, lat, torch, 12)
-    result["hbm_copy"] = copy_rate(torch)
+    log("stand-alone hopping-term sweeps (3 rotated copies) and the copy reference")
+    from paper_1103_1363_amd import sweep as _sweep
+    copy = _sweep.copy_kernel_rate(lq, torch)
+    result["hbm_copy"] = copy
+    lats = [lat] + _sweep.make_lattices(lq, dims, 2, u=u)
+    result["dslash_gbs"] = {p: _sweep.dslash_sweep(lq, lats, torch, p)
+                            for p in ("f64", "f32", "f16", "f16x12")}
+    for p, d in result["dslash_gbs"].items():
+        d["frac_of_copy"] = round(d["GB/s"] / copy["GB/s"], 3)
+    del lats
+    result["dslash_frac_hbm"] = {p: d["frac_hbm"] for p, d in result["dslash_gbs"].items()}
+    log("fused site expressions (SU(3) array products)")
+    result["fused_expressions"] = _sweep.su3_sweep(lq, torch, prec=0)
     if not a.no_batched:
         log("12 point sources: batched solve, and one source alone")
         result["batched_12rhs"] = batched_point_sources(lq, lat, torch, dims)
@@ -542,12 +636,23 @@ def main():
                                                                   a.net_epochs)
 
     if not a.no_sap:
-        log("SAP-preconditioned FGCR (blocks 8x4x4x4, 3 cycles of 6 MR steps, restart 48)")
+        log("SAP-preconditioned FGCR (blocks 8x4x4x4, 3 cycles of 6 MR steps, restart 48) "
+            "and SAP-FGMRES-DR (70, 10)")
         result["sap_fgcr"] = sap_fgcr(lq, lat, torch, db, (8, 4, 4, 4), 3, 6, 48)
+
+    log("16^3x32 configuration: FP32 inner iteration against plain FP64")
+    result["config_16x16x16x32"] = config_16(lq, torch)
 
     if not a.no_cpu_baseline:
         log("CPU baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(u, b, dims)
+        vol = dims[0] * dims[1] * dims[2] * dims[3] / (16 * 16 * 16 * 32)
+        its = {"16x16x16x32_plain": (1.0, result["config_16x16x16x32"]["plain_fp64"]["iterations"]),
+               "benchmark_plain": (vol, result["plain_fp64"]["iterations"])
+               if "plain_fp64" in result else None}
+        if "batched_12rhs" in result:
+            its["12_point_sources_plain"] = (
+                12 * vol, result["batched_12rhs"]["one_source_alone"]["plain_fp64"]["iterations"])
+        result["cpu_baseline"] = cpu_baseline(u, b, dims, {k: v for k, v in its.items() if v})
     print(json.dumps(result), flush=True)
 
 
