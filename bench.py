@@ -9,6 +9,9 @@ per-site FP32 scales by default, FP32 inner vectors, FP64 reliable updates,
 FP64 final residual).
 
 Printed (one JSON line):
+  autotune      the tile tuner's choice (lq_tune_tiles) for the single-RHS
+                numbering and the 12-RHS numbering, every candidate's time and
+                the spread; the benchmark's contexts use the chosen tiles;
   value         whole-solve throughput: algorithmic bytes of every kernel the
                 solve launched / wall time of the timed steps, in GB/s;
   ms_per_step   wall time per solve;
@@ -222,25 +225,39 @@ def learned_preconditioner(lq, lat, torch, db_bench, npairs, epochs):
         _, rep = net.solve(b_sel, KAPPA, CSW, TOL, solver=lq.FCG_NET)
         return rep[0].iterations + (10 ** 6 if rep[0].fallback else 0)
 
-    best_w, best_it, best_epoch = w0, sel_iterations(w0), 0
+    best_w, best_it, best_at = w0, sel_iterations(w0), "start"
     sel = [best_it]
     net.set_weights(w0)
     hist = []
     t_train = 0.0
+    # each epoch runs over the training pairs in `chunks` consecutive slices
+    # (one shuffled pass per slice), and the selection looks after each
+    chunks = 8
+    bounds = [ntr * c // chunks for c in range(chunks + 1)]
+    ck = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"lq_net_{os.getpid()}.ckpt")
     for e in range(epochs):
-        t1 = time.perf_counter()
-        hist += list(net.train(db, dx, ntr, epochs=1, batch=8, lr=1e-3, seed=1 if e == 0 else 0))
-        torch.cuda.synchronize()
-        t_train += time.perf_counter() - t1
-        w_e = net.get_weights()
-        # checkpoint the training state: selection solves leave the Adam state alone
-        ck = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"lq_net_{os.getpid()}.ckpt")
-        net.save(ck)
-        it = sel_iterations(w_e)
-        net.load(ck)
-        sel.append(it)
-        if it < best_it:
-            best_w, best_it, best_epoch = w_e, it, e + 1
+        ep_loss = []
+        for c in range(chunks):
+            lo, hi = bounds[c], bounds[c + 1]
+            if hi <= lo:
+                continue
+            t1 = time.perf_counter()
+            ep_loss += [float(h) * (hi - lo) for h in
+                        net.train(db[lo * fb32:], dx[lo * fb32:], hi - lo, epochs=1, batch=8,
+                                  lr=1e-3, seed=1 if e == 0 and c == 0 else 0)]
+            torch.cuda.synchronize()
+            t_train += time.perf_counter() - t1
+            w_e = net.get_weights()
+            # checkpoint the training state: selection solves leave the Adam state alone
+            net.save(ck)
+            it = sel_iterations(w_e)
+            net.load(ck)
+            sel.append(it)
+            if it < best_it:
+                best_w, best_it, best_at = w_e, it, f"epoch {e + 1}, slice {c + 1}"
+        hist.append(sum(ep_loss) / ntr)
+    if os.path.exists(ck):
+        os.remove(ck)
     l1, _ = net.loss_grad(db, dx, ntr)
     v1 = net.loss_grad(db[ntr * fb32:], dx[ntr * fb32:], nv)[0] if nv else None
     del db, dx, dB, dX, net, tl
@@ -250,9 +267,10 @@ def learned_preconditioner(lq, lat, torch, db_bench, npairs, epochs):
            "loss_train": [round(l0, 5), round(l1, 5)],
            "loss_valid": [round(v0, 5), round(v1, 5)] if nv else None,
            "loss_history": [round(float(h), 5) for h in hist],
-           "selection": {"held_out_fcg_iterations_per_epoch": sel, "kept_epoch": best_epoch,
-                         "rule": "fewest flexible-CG iterations on a held-out 16^3x32 source; "
-                                 "epoch 0 = the Neumann start"},
+           "selection": {"held_out_fcg_iterations": sel, "kept": best_at,
+                         "rule": f"fewest flexible-CG iterations on a held-out 16^3x32 source, "
+                                 f"checked at the start (the Neumann series) and after each "
+                                 f"1/{chunks} of every epoch"},
            "solves": {}}
     b_host = lat.to_host(db_bench, lq.FULL, lq.F64)
     for name, wts, kind, kw in (("fcg_trained", best_w, lq.FCG_NET, {}),
@@ -497,7 +515,14 @@ def main():
             np.save(a.gauge_cache, u)
     b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 2)
 
-    lat = lq.Lattice(dims)
+    log("tile tuner: the inner-precision Schur operator and the 12-RHS operator")
+    t_tune = time.perf_counter()
+    tune_one = lq.tune_tiles(dims, inner, 1)
+    tune_12 = lq.tune_tiles(dims, lq.F16X, 12)
+    t_tune = time.perf_counter() - t_tune
+    tiling = {"tile_sites": int(tune_one.target[tune_one.best]),
+              "mr_tile_sites": int(tune_12.target[tune_12.best])}
+    lat = lq.Lattice(dims, **tiling)
     lat.upload_gauge(u)
     lat.set_clover(KAPPA, CSW)
     db = lat.to_device(b, lq.FULL, lq.F64)
@@ -551,6 +576,18 @@ def main():
                   "seconds_inside_library": round(r0.seconds, 4),
                   "algorithmic_GB": round(r0.bytes / 1e9, 2)},
     }
+
+    def spread(rep):
+        us = [rep.us[i] for i in range(rep.ncand)]
+        return round(max(us) / min(us), 3)
+
+    result["autotune"] = {
+        "what": "largest tile (sites of one parity) of the single-RHS numbering, timed on the "
+                f"{a.inner} Schur operator, and of the 12-RHS numbering, timed on the 12-RHS "
+                "Schur operator; unit links on scratch contexts, 20 applications each",
+        "single_rhs": {**tune_one.as_dict(), "spread_slowest_over_fastest": spread(tune_one)},
+        "rhs12": {**tune_12.as_dict(), "spread_slowest_over_fastest": spread(tune_12)},
+        "seconds": round(t_tune, 2)}
 
     x_mixed = lat.to_host(dx, lq.FULL, lq.F64)
     if not a.no_plain:
@@ -615,7 +652,7 @@ def main():
     from paper_1103_1363_amd import sweep as _sweep
     copy = _sweep.copy_kernel_rate(lq, torch)
     result["hbm_copy"] = copy
-    lats = [lat] + _sweep.make_lattices(lq, dims, 2, u=u)
+    lats = [lat] + _sweep.make_lattices(lq, dims, 2, u=u, **tiling)
     result["dslash_gbs"] = {p: _sweep.dslash_sweep(lq, lats, torch, p)
                             for p in ("f64", "f32", "f16", "f16x12")}
     for p, d in result["dslash_gbs"].items():

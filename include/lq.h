@@ -200,6 +200,53 @@ lq_status lq_schur(lq_ctx* ctx, void* dev_out, const void* dev_in, void* dev_tmp
 lq_status lq_schur_noalloc(lq_ctx* ctx, void* dev_out, const void* dev_in, int dagger, int prec,
                            int nrhs);
 
+/* ------------------------------------------------------------------------
+ * Tiling and its tuner.  Each parity's sites are numbered inside 4-D tiles
+ * (every extent an even divisor of the lattice extent; the tile with the
+ * least surface per volume among those of at most `tile_sites` sites of one
+ * parity): within a tile the y, z and t neighbours of 64 consecutive sites
+ * are 64 consecutive sites, and the tile size sets how far a neighbour across
+ * it lies in memory.  The 12-RHS fields have their own, smaller tiles.
+ * Defaults: 65536 and 2048 sites (measured on MI355X at 32^3x64).
+ * ------------------------------------------------------------------------ */
+
+/* Change the largest tile of the single-RHS numbering (tile_sites) and of
+ * the multi-RHS numbering (mr_tile_sites); 0 keeps the current one, other
+ * values below 64 are LQ_EINVAL.  Only before the gauge field is uploaded
+ * and before any solver work space exists (else LQ_ESTATE): every field is
+ * laid out in this numbering. */
+lq_status lq_set_tiling(lq_ctx* ctx, int64_t tile_sites, int64_t mr_tile_sites);
+/* The tile extents in use (either pointer may be NULL). */
+lq_status lq_get_tiling(const lq_ctx* ctx, int tiles[4], int mr_tiles[4]);
+
+#define LQ_TUNE_MAX 8
+typedef struct {
+  int ncand;                        /* candidates measured (distinct tilings) */
+  int64_t target[LQ_TUNE_MAX];      /* their largest tile, sites of one parity */
+  int tiles[LQ_TUNE_MAX][4];        /* their tile extents */
+  double us[LQ_TUNE_MAX];           /* time of one Schur application (0: unknown) */
+  int best;                         /* index of the chosen candidate */
+  int from_cache;                   /* 1: the choice was read from the cache file */
+} lq_tune_report;
+
+/* Choose the tile for a lattice of `dims` (t_antiperiodic as lq_create):
+ * for prec LQ_F64 / LQ_F32 / LQ_F16 with nrhs = 1 the single-RHS tile
+ * (candidates 4096, 16384, 65536, 262144 sites and one tile for the whole
+ * lattice), for LQ_F16X with nrhs 1..16 the multi-RHS tile (512, 1024, 2048,
+ * 8192, 32768), candidates giving the same tiling measured once.  Each is
+ * timed on a scratch context with unit links and the clover term of
+ * kappa 0.135, csw 1 (the kernels' work does not depend on the values): 20
+ * applications of the Schur operator (lq_schur) after 3 warm-ups, on a
+ * stream of its own, HIP events around them.  The fastest is the choice.
+ * With cache_path (may be NULL) the choice is first looked up in that JSON
+ * file under the key "<arch>:<precision>:nrhs<n>:<dims>" and written there
+ * after a measurement (other keys are kept).  Apply it with lq_set_tiling
+ * on a new context.  Needs a GPU and several GB of free device memory for
+ * the scratch contexts.  Errors: lq_tune_last_error(). */
+lq_status lq_tune_tiles(const int dims[4], int t_antiperiodic, int prec, int nrhs,
+                        const char* cache_path, lq_tune_report* rep);
+const char* lq_tune_last_error(void);
+
 /* Measurement reference: copy `bytes` (a multiple of 16; both pointers
  * 16-byte aligned, else LQ_EINVAL) from src to dst with 16-byte loads and
  * stores per lane, asynchronously on `stream` (a hipStream_t, NULL =

@@ -165,12 +165,43 @@ void unpack_t(lq_ctx* ctx, double2* dst, const void* dev, int parity) {
 
 }  // namespace
 
+namespace {
+
+// unit links U_mu(x) = 1 in the host layout (the tile tuner's operator: the
+// kernels' work does not depend on the link values)
+__global__ void unit_links_kernel(double2* __restrict__ u, int64_t nlinks) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nlinks) return;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u[t * 9 + k] = make_double2(k % 4 == 0 ? 1.0 : 0.0, 0.0);
+}
+
+void compress_staged_gauge(lq_ctx* ctx, const double2* st);
+
+}  // namespace
+
 void upload_gauge(lq_ctx* ctx, const double* host_U) {
-  const Geo& g = ctx->geo;
   const int64_t nlinks = ctx->V * 4;
   const size_t host_bytes = (size_t)nlinks * 9 * 16;
   double2* st = reinterpret_cast<double2*>(staging(ctx, host_bytes));
   LQ_HIP(hipMemcpyAsync(st, host_U, host_bytes, hipMemcpyHostToDevice, ctx->cur));
+  compress_staged_gauge(ctx, st);
+}
+
+void upload_unit_gauge(lq_ctx* ctx) {
+  const int64_t nlinks = ctx->V * 4;
+  double2* st = reinterpret_cast<double2*>(staging(ctx, (size_t)nlinks * 9 * 16));
+  hipLaunchKernelGGL(unit_links_kernel, dim3(grid_for(nlinks, 256)), dim3(256), 0, ctx->cur, st,
+                     nlinks);
+  LQ_HIP(hipGetLastError());
+  compress_staged_gauge(ctx, st);
+}
+
+namespace {
+
+void compress_staged_gauge(lq_ctx* ctx, const double2* st) {
+  const Geo& g = ctx->geo;
+  const int64_t nlinks = ctx->V * 4;
   const int64_t ncomp = 2 * 4 * g.nblk * 6 * SB;
   for (int p = 0; p < 3; ++p) {
     if (!ctx->gauge[p]) {
@@ -205,6 +236,8 @@ void upload_gauge(lq_ctx* ctx, const double* host_U) {
   ctx->clov.valid = false;
   ctx->mr_links_ok = ctx->mr_clov_ok = false;
 }
+
+}  // namespace
 
 void pack_spinor(lq_ctx* ctx, void* dev, const double2* src, int prec, int parity) {
   switch (prec) {

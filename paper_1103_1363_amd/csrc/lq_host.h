@@ -79,6 +79,9 @@ void ensure_red(lq_ctx* ctx);
 
 // layout.hip
 void upload_gauge(lq_ctx* ctx, const double* host_U);
+void upload_unit_gauge(lq_ctx* ctx);  // U = 1 everywhere (timing only)
+int64_t tile_target();
+int64_t mr_tile_target();
 // parity: LQ_EVEN / LQ_ODD (host half field, dev one parity field) or
 // LQ_FULL (host full field, dev = even half then odd half)
 void pack_spinor(lq_ctx* ctx, void* dev, const double2* src_dev, int prec, int parity);

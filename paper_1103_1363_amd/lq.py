@@ -152,6 +152,15 @@ def lib():
                                         ct.POINTER(EnsembleReport)]
         for name in ("lq_ensemble_create", "lq_ensemble_tune", "lq_ensemble_solve"):
             getattr(L, name).restype = ip
+        L.lq_set_tiling.argtypes = [vp, ct.c_int64, ct.c_int64]
+        L.lq_set_tiling.restype = ip
+        L.lq_get_tiling.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
+        L.lq_get_tiling.restype = ip
+        L.lq_tune_tiles.argtypes = [ct.POINTER(ct.c_int), ip, ip, ip, ct.c_char_p,
+                                    ct.POINTER(TuneReport)]
+        L.lq_tune_tiles.restype = ip
+        L.lq_tune_last_error.argtypes = []
+        L.lq_tune_last_error.restype = ct.c_char_p
         for name in ("lq_upload_gauge", "lq_set_clover", "lq_spinor_to_device",
                      "lq_spinor_to_host", "lq_dslash", "lq_clover_apply", "lq_schur",
                      "lq_schur_noalloc",
@@ -195,10 +204,41 @@ class Report:
     ref_error: float = -1.0
 
 
-class Lattice:
-    """One lq context: lattice geometry, gauge field, clover term, solvers."""
+TUNE_MAX = 8
 
-    def __init__(self, dims, antiperiodic_t=True, stream=None):
+
+class TuneReport(ct.Structure):
+    _fields_ = [("ncand", ct.c_int), ("target", ct.c_int64 * TUNE_MAX),
+                ("tiles", (ct.c_int * 4) * TUNE_MAX), ("us", ct.c_double * TUNE_MAX),
+                ("best", ct.c_int), ("from_cache", ct.c_int)]
+
+    def as_dict(self):
+        n = self.ncand
+        return {"candidates": [{"max_tile_sites": int(self.target[i]),
+                                "tile": list(self.tiles[i]), "us": round(self.us[i], 2)}
+                               for i in range(n)],
+                "chosen": int(self.target[self.best]), "from_cache": bool(self.from_cache)}
+
+
+def tune_tiles(dims, prec, nrhs=1, cache_path=None, antiperiodic_t=True):
+    """lq_tune_tiles: the fastest tile for `dims` at `prec` (LQ_F16X with nrhs
+    for the multi-RHS numbering), and every candidate's time."""
+    L = lib()
+    arr = (ct.c_int * 4)(*[int(d) for d in dims])
+    rep = TuneReport()
+    rc = L.lq_tune_tiles(arr, int(bool(antiperiodic_t)), int(prec), int(nrhs),
+                         str(cache_path).encode() if cache_path else None, ct.byref(rep))
+    if rc != 0:
+        raise LQError(rc, L.lq_tune_last_error().decode())
+    return rep
+
+
+class Lattice:
+    """One lq context: lattice geometry, gauge field, clover term, solvers.
+    tile_sites / mr_tile_sites (0: the library's default) set the tiling
+    (lq_set_tiling) before anything is laid out."""
+
+    def __init__(self, dims, antiperiodic_t=True, stream=None, tile_sites=0, mr_tile_sites=0):
         self._L = lib()
         self.dims = tuple(int(d) for d in dims)
         arr = (ct.c_int * 4)(*self.dims)
@@ -209,6 +249,16 @@ class Lattice:
             raise LQError(rc, self._L.lq_last_error(None).decode())
         self._h = h
         self.volume = int(self._L.lq_volume(h))
+        if tile_sites or mr_tile_sites:
+            self.set_tiling(tile_sites, mr_tile_sites)
+
+    def set_tiling(self, tile_sites=0, mr_tile_sites=0):
+        self._check(self._L.lq_set_tiling(self._h, int(tile_sites), int(mr_tile_sites)))
+
+    def tiling(self):
+        a, b = (ct.c_int * 4)(), (ct.c_int * 4)()
+        self._check(self._L.lq_get_tiling(self._h, a, b))
+        return list(a), list(b)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -154,16 +154,16 @@ def su3_sweep(lq, torch, n=1 << 23, prec=0, reps=20):
     return out
 
 
-def make_lattices(lq, dims, copies, seed=1100, u=None):
+def make_lattices(lq, dims, copies, seed=1100, u=None, tile_sites=0, mr_tile_sites=0):
     """`copies` contexts, each with its own device copy of one smooth gauge
     field (distinct buffers are what the rotation needs; the values may
-    repeat)."""
+    repeat), in the given tiling (0: the library's default)."""
     from gen import fields
     if u is None:
         u = fields.gauge_field(dims, "smooth", seed)
     lats = []
     for _ in range(copies):
-        lat = lq.Lattice(dims)
+        lat = lq.Lattice(dims, tile_sites=tile_sites, mr_tile_sites=mr_tile_sites)
         lat.upload_gauge(u)
         lats.append(lat)
     return lats

@@ -18,7 +18,7 @@ import pytest
 from gen import fields
 from oracle import dirac, evenodd
 from oracle import net as onet
-from tests.gpu_common import PREC_NAME, TOL, case, rel, say
+from tests.gpu_common import PREC_NAME, TOL, case, log_errors, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_operator_parity_tiled(lq, monkeypatch, dims, prec):
             ref = wc.hop_block(src, out_par, dagger=dag)
             dout = lat.new_field(out_par, prec)
             lat.dslash(dout, lat.to_device(src, 1 - out_par, prec), out_par, dag, prec)
-            err = rel(lat.to_host(dout, out_par, prec), ref)
+            err = log_errors(f"H out parity {out_par} dagger {int(dag)}", lat.to_host(dout, out_par, prec), ref)
             assert err <= TOL[prec], ("dslash", out_par, dag, err)
     ref = wc.clover_half(o, evenodd.ODD, inverse=True)
     dout = lat.new_field(evenodd.ODD, prec)
@@ -74,7 +74,7 @@ def test_operator_parity_tiled(lq, monkeypatch, dims, prec):
     tmp = lat.new_field(evenodd.ODD, prec)
     for dag in (False, True):
         lat.schur(dout, din, tmp, dag, prec)
-        err = rel(lat.to_host(dout, evenodd.EVEN, prec), wc.schur(e, dagger=dag))
+        err = log_errors(f"Schur dagger {int(dag)}", lat.to_host(dout, evenodd.EVEN, prec), wc.schur(e, dagger=dag))
         assert err <= TOL[prec], ("schur", dag, err)
 
 
@@ -144,3 +144,68 @@ def test_net_fp16_ragged_and_extent_two(lq, dims):
     for adj in (False, True):
         err = net_case(lq, lat, u, dims, True, adj)
         assert err <= 5e-3, (adj, err)
+
+
+def test_set_tiling_through_the_abi(lq):
+    """lq_set_tiling: 64-site tiles of both numberings, set through the C ABI,
+    give the oracle's Schur operator (single-RHS FP64 and FP16, and 3 RHS in
+    the multi-RHS form); the extents in use are reported; once the gauge
+    field is uploaded the tiling is fixed (LQ_ESTATE)."""
+    dims = (12, 6, 4, 8)
+    say(f"set_tiling dims={dims}")
+    u, psi, e, o = case(dims, "smooth", 5)
+    lat = lq.Lattice(dims, tile_sites=64, mr_tile_sites=64)
+    tiles, mr = lat.tiling()
+    say(f"  tiles {tiles}, multi-RHS tiles {mr}")
+    assert np.prod(tiles) // 2 <= 64 and np.prod(mr) // 2 <= 64
+    assert all(d % t == 0 and t % 2 == 0 for d, t in zip(dims, tiles))
+    lat.upload_gauge(u)
+    lat.set_clover(KAPPA, CSW)
+    wc = evenodd.WilsonClover(u, KAPPA, CSW)
+    for prec in (0, 2):
+        din = lat.to_device(e, evenodd.EVEN, prec)
+        dout = lat.new_field(evenodd.EVEN, prec)
+        tmp = lat.new_field(evenodd.ODD, prec)
+        lat.schur(dout, din, tmp, False, prec)
+        err = log_errors(f"Schur {PREC_NAME[prec]}", lat.to_host(dout, evenodd.EVEN, prec),
+                         wc.schur(e))
+        assert err <= TOL[prec]
+    g = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 91, nrhs=3)
+    es = np.stack([evenodd.split(g[r], dims)[0] for r in range(3)])
+    din = lat.to_device(es, evenodd.EVEN, lq.F16X)
+    dout = lat.new_field(evenodd.EVEN, lq.F16X, 3)
+    tmp = lat.new_field(evenodd.ODD, lq.F16X, 3)
+    lat.schur(dout, din, tmp, False, lq.F16X, 3)
+    got = lat.to_host(dout, evenodd.EVEN, lq.F16X, 3)
+    for r in range(3):
+        assert log_errors(f"multi-RHS Schur rhs {r}", got[r], wc.schur(es[r])) <= TOL[2]
+    with pytest.raises(lq.LQError) as ei:
+        lat.set_tiling(4096, 0)
+    assert ei.value.code == -5
+
+
+def test_tune_tiles_and_cache(lq, tmp_path):
+    """lq_tune_tiles on 16^3x32: every distinct candidate is timed and the
+    fastest chosen; the choice is written to the cache file and read back
+    from it; the single-RHS and the multi-RHS choice live side by side in
+    the file; a context created with the choices uses those tiles."""
+    dims = (16, 16, 16, 32)
+    path = tmp_path / "tiles.json"
+    say(f"tune tiles dims={dims}")
+    r1 = lq.tune_tiles(dims, 2, 1, path)
+    say(f"  single-RHS FP16: {r1.as_dict()}")
+    assert 2 <= r1.ncand <= lq.TUNE_MAX and not r1.from_cache
+    us = [r1.us[i] for i in range(r1.ncand)]
+    assert min(us) > 0 and r1.us[r1.best] == min(us)
+    r2 = lq.tune_tiles(dims, 2, 1, path)
+    assert r2.from_cache and r2.best == r1.best
+    r3 = lq.tune_tiles(dims, lq.F16X, 12, path)
+    say(f"  12-RHS: {r3.as_dict()}")
+    assert r3.ncand >= 2 and not r3.from_cache
+    text = open(path).read()
+    assert ":f16:nrhs1:16x16x16x32" in text and ":f16x:nrhs12:16x16x16x32" in text
+    lat = lq.Lattice(dims, tile_sites=r1.target[r1.best], mr_tile_sites=r3.target[r3.best])
+    tiles, mr = lat.tiling()
+    assert tiles == list(r1.tiles[r1.best]) and mr == list(r3.tiles[r3.best])
+    with pytest.raises(lq.LQError):
+        lq.tune_tiles(dims, lq.F16X, 17)

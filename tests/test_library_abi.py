@@ -97,3 +97,18 @@ def test_sap_calls_reject_missing_context():
     buf = ctypes.create_string_buffer(64)
     assert lib.lq_sap_apply(None, buf, buf, params) == -1
     assert lib.lq_solve_sap(None, buf, buf, 0.13, 1.0, 1e-10, params, None) == -1
+
+
+def test_tune_tiles_rejects_bad_arguments_on_the_host():
+    """The tile tuner checks its precision and right-hand-side count before
+    touching the device."""
+    lib = _lib()
+    lib.lq_tune_tiles.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, ctypes.c_char_p, ctypes.c_void_p]
+    lib.lq_tune_tiles.restype = ctypes.c_int
+    lib.lq_tune_last_error.restype = ctypes.c_char_p
+    dims = (ctypes.c_int * 4)(8, 8, 8, 8)
+    assert lib.lq_tune_tiles(dims, 1, 7, 1, None, None) == -1
+    assert b"nrhs" in lib.lq_tune_last_error()
+    assert lib.lq_tune_tiles(dims, 1, 2, 2, None, None) == -1
+    assert lib.lq_tune_tiles(None, 1, 2, 1, None, None) == -1
