@@ -13,7 +13,7 @@ import pytest
 
 from gen import fields
 from oracle import dirac, evenodd
-from tests.gpu_common import TOL, case, rel, say
+from tests.gpu_common import TOL, case, log_errors, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_mrhs_dslash_parity(lq, dims, nrhs):
             got = lat.to_host(dout, out_par, lq.F16X, nrhs).reshape((nrhs,) + src.shape[1:])
             for r in range(nrhs):
                 ref = wc.hop_block(src[r], out_par, dagger=dag)
-                err = rel(got[r], ref)
+                err = log_errors(f"rhs {r} parity {out_par} dagger {int(dag)}", got[r], ref)
                 assert err <= TOL16, (dims, nrhs, out_par, dag, r, err)
 
 
@@ -79,7 +79,7 @@ def test_mrhs_dslash_scale_and_locality(lq):
     got = lat.to_host(dout, evenodd.EVEN, lq.F16X, 6)
     for r in range(6):
         ref = wc.hop_block(o[r], evenodd.EVEN)
-        err = rel(got[r], ref)
+        err = log_errors(f"rhs {r} scale {scale[r]:.0e}", got[r], ref)
         assert err <= TOL16, (r, scale[r], err)
 
 
@@ -112,7 +112,7 @@ def test_mrhs_schur_parity(lq, dims):
         got = lat.to_host(dout, evenodd.EVEN, lq.F16X, nrhs)
         for r in range(nrhs):
             ref = wc.schur(e[r], dagger=dag)
-            err = rel(got[r], ref)
+            err = log_errors(f"Schur rhs {r} dagger {int(dag)}", got[r], ref)
             assert err <= TOL16, (dims, dag, r, err)
 
 

@@ -15,7 +15,7 @@ import pytest
 from gen import fields
 from oracle import dirac, evenodd
 from oracle import net as onet
-from tests.gpu_common import case, rel, say
+from tests.gpu_common import case, log_errors, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,7 @@ def test_net_forward_parity(lq, dims, init):
     net.apply(dy, dx)
     got = lat.to_host(dy, lq.EVEN, lq.F32)
     ref = onet.apply_even(u, w, x, dims)
-    err = rel(got, ref)
+    err = log_errors("net FP32 forward", got, ref)
     assert err <= 2e-5, err
 
 
@@ -85,7 +85,7 @@ def test_net_forward_fp16(lq, dims, layers):
             acts = onet.forward(u, w, evenodd.join(x, None, dims))
             ref = evenodd.split(onet.backward(u, w, acts, evenodd.join(x, None, dims))[1],
                                 dims)[0]
-        err = rel(got, ref)
+        err = log_errors(f"net FP16 adjoint {int(adj)}", got, ref)
         assert err <= 5e-3, (adj, err)
 
 
@@ -247,10 +247,14 @@ def make_pairs(lq, lat, u, dims, n, seed):
 
 
 def test_training_gain(lq):
-    """Train from the Neumann initialisation on pairs the solver generated:
-    the loss falls, and on a fresh source FGMRES with the trained net needs
-    far fewer iterations than without a net (identity weights) and no more
-    than with its initial weights."""
+    """Train from the Neumann initialisation on pairs the solver generated,
+    keeping after every epoch the weights that need the fewest flexible-CG
+    iterations on a held-out source (the Neumann start counts as epoch 0;
+    the benchmark's rule).  The loss falls; on a fresh source the kept net
+    needs far fewer iterations than no net (identity weights) and strictly
+    fewer than its Neumann start (on this 8^4 system the first epochs of
+    training help; longer training raises the count again while the loss
+    keeps falling, which is what the selection guards against)."""
     dims = (8, 8, 8, 8)
     u = fields.gauge_field(dims, "smooth", fields.SEED_TRAIN_FIELD)
     lat = lq.Lattice(dims)
@@ -258,30 +262,41 @@ def test_training_gain(lq):
     say("training pairs")
     bs, xs = make_pairs(lq, lat, u, dims, 32, 40)
     db, dx = lat.to_device(bs, lq.EVEN, lq.F32), lat.to_device(xs, lq.EVEN, lq.F32)
+    held = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 42)
+    fresh = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 41)
+    probe = lq.Net(lat, 4)
+
+    def iterations(w, b):
+        probe.set_weights(w)
+        x, rep = probe.solve(b, KAPPA, CSW, 1e-10, solver=lq.FCG_NET)
+        assert oracle_residual(u, KAPPA, CSW, x, b) <= 1e-10
+        assert rep[0].fallback == 0
+        return rep[0].iterations
+
     net = lq.Net(lat, 4)
     w0 = onet.neumann_weights(KAPPA, 4)
     net.set_weights(w0)
     l0, _ = net.loss_grad(db, dx, 32)
-    hist = net.train(db, dx, 32, epochs=30, batch=4, lr=2e-3, seed=1)
+    kept, kept_its = w0, iterations(w0, held)
+    per_epoch = [kept_its]
+    for e in range(6):
+        net.train(db, dx, 32, epochs=5, batch=4, lr=2e-3, seed=1 if e == 0 else 0)
+        w = net.get_weights()
+        its = iterations(w, held)
+        per_epoch.append(its)
+        if its < kept_its:
+            kept, kept_its = w, its
     l1, _ = net.loss_grad(db, dx, 32)
-    say(f"  loss {l0:.4f} -> {l1:.4f}; epochs {hist[0]:.4f} .. {hist[-1]:.4f}")
+    say(f"  loss {l0:.4f} -> {l1:.4f}; held-out iterations per 5 epochs {per_epoch}")
     assert l1 < 0.8 * l0
-    b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 41)
-    its = {}
-    for name, w in (("trained", net.get_weights()), ("neumann", w0),
-                    ("identity", np.concatenate([np.eye(4)[None, None].repeat(4, 0),
-                                                 np.zeros((4, 8, 4, 4))], axis=1))):
-        tnet = lq.Net(lat, 4)
-        tnet.set_weights(w)
-        x, rep = tnet.solve(b, KAPPA, CSW, 1e-10, solver=lq.FGMRES_NET)
-        assert oracle_residual(u, KAPPA, CSW, x, b) <= 1e-10
-        its[name] = rep[0].iterations
-    say(f"  FGMRES iterations {its}")
-    # the gain over the solver without the net is large; relative to its
-    # Neumann start a linear net of this size gains little, and iteration
-    # counts with FP16 arithmetic inside the net vary by a couple
-    assert its["trained"] * 1.5 < its["identity"]
-    assert its["trained"] <= its["neumann"] + 3
+    assert kept_its <= per_epoch[0]
+    identity = np.concatenate([np.eye(4)[None, None].repeat(4, 0), np.zeros((4, 8, 4, 4))], axis=1)
+    its = {"kept": iterations(kept, fresh), "neumann": iterations(w0, fresh),
+           "identity": iterations(identity, fresh)}
+    say(f"  fresh-source flexible-CG iterations {its}")
+    assert its["kept"] * 1.5 < its["identity"]
+    assert kept is not w0
+    assert its["kept"] < its["neumann"]
 
 
 @pytest.mark.parametrize("m,k", [(16, 4), (24, 8)])

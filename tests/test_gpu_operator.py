@@ -10,7 +10,7 @@ import pytest
 
 from gen import fields
 from oracle import dirac, evenodd
-from tests.gpu_common import PREC_NAME, TOL, case, rel, say
+from tests.gpu_common import PREC_NAME, TOL, case, log_errors, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def test_dslash_parity(lq, dims, prec):
             dout = lat.new_field(out_par, prec)
             lat.dslash(dout, din, out_par, dag, prec)
             got = lat.to_host(dout, out_par, prec)
-            err = rel(got, ref)
+            err = log_errors(f"H out parity {out_par} dagger {int(dag)}", got, ref)
             assert err <= TOL[prec], (dims, prec, out_par, dag, err)
 
 
@@ -97,7 +97,8 @@ def test_clover_and_schur_parity(lq, dims, prec):
         din = lat.to_device(src, par, prec)
         dout = lat.new_field(par, prec)
         lat.clover(dout, din, par, inv, prec)
-        err = rel(lat.to_host(dout, par, prec), ref)
+        err = log_errors(f"clover parity {par} inverse {int(inv)}",
+                         lat.to_host(dout, par, prec), ref)
         assert err <= TOL[prec], ("clover", par, inv, err)
     # Schur operator and its adjoint
     din = lat.to_device(e, evenodd.EVEN, prec)
@@ -106,7 +107,7 @@ def test_clover_and_schur_parity(lq, dims, prec):
     for dag in (False, True):
         ref = wc.schur(e, dagger=dag)
         lat.schur(dout, din, tmp, dag, prec)
-        err = rel(lat.to_host(dout, evenodd.EVEN, prec), ref)
+        err = log_errors(f"Schur dagger {int(dag)}", lat.to_host(dout, evenodd.EVEN, prec), ref)
         assert err <= TOL[prec], ("schur", dag, err)
 
 

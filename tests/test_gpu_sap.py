@@ -11,7 +11,7 @@ import pytest
 
 from gen import fields
 from oracle import dirac, evenodd, sap
-from tests.gpu_common import rel, say
+from tests.gpu_common import log_errors, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def test_sap_apply_parity(lq, monkeypatch, dims, block, tile, ncy, nmr, lds_link
     dout = lat.new_field(lq.FULL, lq.F32)
     lat.sap_apply(dout, din, block, ncy, nmr)
     got = lat.to_host(dout, lq.FULL, lq.F32).reshape(ref.shape)
-    err = rel(got, ref)
+    err = log_errors("SAP application", got, ref)
     assert err <= 1e-4, err
 
 
