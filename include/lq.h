@@ -335,6 +335,13 @@ typedef struct {
                     paper): k harmonic Ritz vectors (k < m, at most 32) of the Arnoldi
                     matrix are kept across each restart; the residual is recomputed in FP64
                     at every restart */
+  int block_fp16; /* 0: the block solves apply the operator with FP32 links (copied to
+                     LDS) and FP32 clover blocks (read from HBM at every MR step).  1: with
+                     FP16 links and clover blocks, staged in LDS beside the FP32 residual
+                     once per block (arithmetic FP32); LQ_EINVAL when they do not fit
+                     (at most 512 sites per block as always; 8x4x4x4 fits).  The
+                     preconditioner then differs from the FP32 one by the FP16 rounding of
+                     the operator, which the flexible outer solver absorbs */
 } lq_sap_params;
 
 /* dev_out = K dev_in on full-lattice FP32 fields (lq_field_bytes(ctx,

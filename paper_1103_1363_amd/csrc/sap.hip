@@ -35,6 +35,8 @@ namespace lq {
 struct Sap {
   void* a32[2] = {nullptr, nullptr};  // FP32 clover blocks A of each parity
   uint64_t clov_gen = 0;               // clover build they were copied from (0: none)
+  void* a16[2] = {nullptr, nullptr};  // FP16 copies (block solves with block_fp16)
+  uint64_t clov_gen16 = 0;
   void* r = nullptr;    // residual (FP32 full field)
   void* tmp = nullptr;  // FP32 full field
   std::vector<void*> z, w;                 // FGCR directions (FP32 full fields)
@@ -300,6 +302,239 @@ __global__ __launch_bounds__(SAP_MAXV) void sap_mr_kernel(Geo g, SapBlocks sb, i
   }
 }
 
+// ---- block solves with FP16 operator data staged in LDS
+// The block's residual (FP32), its clover blocks A (FP16, 36 half2 per site,
+// the library's slot order) and its interior forward links (FP16, rows 0
+// and 1; links that leave the block are never used) all sit in LDS, so the
+// MR steps read no global memory: per site and colour pass the clover and
+// the links cross HBM once instead of once per step.  Arithmetic is FP32.
+// Interior forward links of direction mu are numbered over the box with
+// extent B[mu] - 1 in mu (x fastest), directions one after another, and
+// stored component-major: entry c of link i at L16[c * nl + i].
+
+struct SapLinks16 {
+  int base[4];  // first link of each direction
+  int nl;       // interior forward links of the block
+};
+
+inline SapLinks16 sap_links16(const SapBlocks& sb) {
+  SapLinks16 k;
+  int n = 0;
+  for (int mu = 0; mu < 4; ++mu) {
+    k.base[mu] = n;
+    n += sb.vb / sb.B[mu] * (sb.B[mu] - 1);
+  }
+  k.nl = n;
+  return k;
+}
+
+// Index of the interior forward link of direction mu at block coordinates l
+// (l[mu] < B[mu] - 1).
+__device__ __forceinline__ int sap_link16_idx(const SapBlocks& sb, const SapLinks16& k, int mu,
+                                              const int l[4]) {
+  int e[4] = {sb.B[0], sb.B[1], sb.B[2], sb.B[3]};
+  e[mu] -= 1;
+  return k.base[mu] + l[0] + e[0] * (l[1] + e[1] * (l[2] + e[2] * l[3]));
+}
+
+__device__ __forceinline__ C<float> h2c(unsigned w) {
+  const float2 f = __half22float2(__builtin_bit_cast(__half2, w));
+  return C<float>{f.x, f.y};
+}
+
+// Rows 0 and 1 of link i from the FP16 LDS copy, row 2 rebuilt (FP32).
+__device__ __forceinline__ void lds_link16(const unsigned* L, int nl, int i, C<float> u[9]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) u[c] = h2c(L[c * nl + i]);
+  u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+  u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+  u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+}
+
+template <int MU>
+__device__ __forceinline__ void block_hops16(const float2* rho, const unsigned* L, int nl, int vb,
+                                             int t, int stride, int fi, int bi, C<float> acc[12]) {
+  if (fi >= 0) {
+    C<float> v[12], h[6], u[9], w[6];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 e = rho[c * vb + t + stride];
+      v[c] = C<float>{e.x, e.y};
+    }
+    project<MU, 1>(v, h);
+    lds_link16(L, nl, fi, u);
+    link_mul<false>(u, h, w);
+    reconstruct_add<MU, 1>(acc, w);
+  }
+  if (bi >= 0) {
+    C<float> v[12], h[6], u[9], w[6];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 e = rho[c * vb + t - stride];
+      v[c] = C<float>{e.x, e.y};
+    }
+    project<MU, -1>(v, h);
+    lds_link16(L, nl, bi, u);
+    link_mul<true>(u, h, w);
+    reconstruct_add<MU, -1>(acc, w);
+  }
+}
+
+// y = A x for the site's clover blocks from the FP16 LDS copy [36][vb].
+__device__ __forceinline__ void lds_clover16(const unsigned* A, int vb, int t, const C<float> x[12],
+                                             C<float> y[12]) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    C<float> m[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) m[k] = h2c(A[(18 * b + k) * vb + t]);
+    const C<float>* xb = x + 6 * b;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      const float d = (r & 1) ? m[r >> 1].im : m[r >> 1].re;
+      C<float> a = d * xb[r];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        if (c == r) continue;
+        if (r < c)
+          a = a + m[3 + tri_idx(r, c)] * xb[c];
+        else
+          a = a + cmul_conj(m[3 + tri_idx(c, r)], xb[c]);
+      }
+      y[6 * b + r] = a;
+    }
+  }
+}
+
+// As sap_mr_kernel, with the operator from FP16 links and clover staged in
+// LDS (dynamic LDS: residual [12][vb] float2, clover [36][vb] half2, links
+// [6][nl] half2).
+__global__ __launch_bounds__(SAP_MAXV) void sap_mr16_kernel(
+    Geo g, SapBlocks sb, SapLinks16 lk, int colour, int nmr, float kappa, Field<P32> r0,
+    Field<P32> r1, Field<P32> psi0, Field<P32> psi1, const __half2* __restrict__ gauge16,
+    const __half2* __restrict__ a0, const __half2* __restrict__ a1) {
+  extern __shared__ float2 rho[];
+  __shared__ double tot[3];
+  __shared__ double sh[3][16];
+  const int t = threadIdx.x;
+  const bool on = t < sb.vb;
+  const int tt = on ? t : 0;
+  const int half = sb.NB[0] >> 1;
+  int j = blockIdx.x;
+  const int jx = j % half;
+  j /= half;
+  const int by = j % sb.NB[1];
+  j /= sb.NB[1];
+  const int bz = j % sb.NB[2];
+  const int bt = j / sb.NB[2];
+  const int bx = 2 * jx + ((by + bz + bt + colour) & 1);
+  int l[4];
+  {
+    int q = tt;
+    l[0] = q % sb.B[0];
+    q /= sb.B[0];
+    l[1] = q % sb.B[1];
+    q /= sb.B[1];
+    l[2] = q % sb.B[2];
+    l[3] = q / sb.B[2];
+  }
+  int x[4] = {bx * sb.B[0] + l[0], by * sb.B[1] + l[1], bz * sb.B[2] + l[2], bt * sb.B[3] + l[3]};
+  const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+  const int64_t s = cb_index(g, x);
+  const int stride[4] = {1, sb.B[0], sb.B[0] * sb.B[1], sb.B[0] * sb.B[1] * sb.B[2]};
+  // interior link of each direction at this site (forward) and at the
+  // backward neighbour (whose forward link it is); -1 where a hop leaves
+  int fi[4], bi[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    fi[mu] = (on && l[mu] + 1 < sb.B[mu]) ? sap_link16_idx(sb, lk, mu, l) : -1;
+    int lb[4] = {l[0], l[1], l[2], l[3]};
+    lb[mu] -= 1;
+    bi[mu] = (on && l[mu] > 0) ? sap_link16_idx(sb, lk, mu, lb) : -1;
+  }
+  Field<P32> rf, pf;
+  rf.d = p ? r1.d : r0.d;
+  rf.norm = nullptr;
+  pf.d = p ? psi1.d : psi0.d;
+  pf.norm = nullptr;
+  const unsigned* acl = reinterpret_cast<const unsigned*>(p ? a1 : a0);
+  unsigned* A16 = reinterpret_cast<unsigned*>(rho + 12 * sb.vb);
+  unsigned* L16 = A16 + 36 * sb.vb;
+  if (on) {
+#pragma unroll
+    for (int k = 0; k < 36; ++k) A16[k * sb.vb + t] = acl[clov_idx(s, k)];
+    const unsigned* gl = reinterpret_cast<const unsigned*>(gauge16);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+      if (fi[mu] >= 0)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) L16[c * lk.nl + fi[mu]] = gl[link_idx(g.nblk, p, mu, s, c)];
+  }
+  C<float> rt[12], del[12];
+  if (on) load_spinor<P32>(rf, s, rt);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    if (!on) rt[c] = C<float>{0.f, 0.f};
+    del[c] = C<float>{0.f, 0.f};
+    if (on) rho[c * sb.vb + t] = make_float2(rt[c].re, rt[c].im);
+  }
+  for (int it = 0; it < nmr; ++it) {
+    __syncthreads();
+    C<float> q[12];
+    double v[3] = {0.0, 0.0, 0.0};
+    if (on) {
+      C<float> acc[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[c] = C<float>{0.f, 0.f};
+      block_hops16<0>(rho, L16, lk.nl, sb.vb, t, stride[0], fi[0], bi[0], acc);
+      block_hops16<1>(rho, L16, lk.nl, sb.vb, t, stride[1], fi[1], bi[1], acc);
+      block_hops16<2>(rho, L16, lk.nl, sb.vb, t, stride[2], fi[2], bi[2], acc);
+      block_hops16<3>(rho, L16, lk.nl, sb.vb, t, stride[3], fi[3], bi[3], acc);
+      lds_clover16(A16, sb.vb, t, rt, q);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        q[c] = q[c] - kappa * acc[c];
+        v[0] += (double)q[c].re * rt[c].re + (double)q[c].im * rt[c].im;  // <q, rho>
+        v[1] += (double)q[c].re * rt[c].im - (double)q[c].im * rt[c].re;
+        v[2] += (double)q[c].re * q[c].re + (double)q[c].im * q[c].im;    // <q, q>
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) q[c] = C<float>{0.f, 0.f};
+    }
+    block_sum<3>(v, sh);  // (its barriers also end every read of rho above)
+    if (t == 0) {
+      tot[0] = v[0];
+      tot[1] = v[1];
+      tot[2] = v[2];
+    }
+    __syncthreads();
+    const double qq = tot[2];
+    const C<float> al = qq > 0.0 ? C<float>{(float)(tot[0] / qq), (float)(tot[1] / qq)}
+                                 : C<float>{0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      del[c] = del[c] + al * rt[c];
+      rt[c] = rt[c] - al * q[c];
+      if (on) rho[c * sb.vb + t] = make_float2(rt[c].re, rt[c].im);
+    }
+  }
+  if (on) {
+    C<float> o[12];
+    load_spinor<P32>(pf, s, o);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] = o[c] + del[c];
+    store_spinor<P32>(pf, s, o);
+  }
+}
+
+// FP64 clover blocks -> FP16
+__global__ void sap_a16_kernel(const double2* __restrict__ in, __half2* __restrict__ out,
+                               int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = __floats2half2_rn((float)in[i].x, (float)in[i].y);
+}
+
 // FP64 clover blocks -> FP32
 __global__ void sap_a32_kernel(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -479,6 +714,21 @@ Sap* sap_state(lq_ctx* ctx) {
   return sp;
 }
 
+// The FP16 clover copies for block_fp16, rebuilt with every clover build.
+void sap_a16(lq_ctx* ctx, Sap* sp) {
+  const int64_t ncl = ctx->geo.nblk * SB * 36;
+  if (!sp->a16[0])
+    for (int p = 0; p < 2; ++p) LQ_HIP(hipMalloc(&sp->a16[p], (size_t)ncl * sizeof(__half2)));
+  if (sp->clov_gen16 != ctx->clov.gen) {
+    for (int p = 0; p < 2; ++p)
+      hipLaunchKernelGGL(sap_a16_kernel, dim3(grid_for(ncl, 256)), dim3(256), 0, ctx->cur,
+                         reinterpret_cast<const double2*>(ctx->clov.a64[p]),
+                         reinterpret_cast<__half2*>(sp->a16[p]), ncl);
+    LQ_HIP(hipGetLastError());
+    sp->clov_gen16 = ctx->clov.gen;
+  }
+}
+
 // out = M in (SUB: out = eta - M in) on full fields of precision P
 template <class P, bool SUB>
 void full_m(lq_ctx* ctx, void* out, const void* eta, const void* in) {
@@ -578,6 +828,7 @@ SapBlocks blocks_of(const lq_ctx* ctx, const lq_sap_params& q) {
     sb.vb *= b;
   }
   LQ_CHECK(sb.vb <= SAP_MAXV, LQ_EINVAL, "a block holds at most 512 sites");
+  LQ_CHECK(q.block_fp16 == 0 || q.block_fp16 == 1, LQ_EINVAL, "block_fp16 is 0 or 1");
   return sb;
 }
 
@@ -598,12 +849,38 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
   const bool cache = lds_cached + 4096 <= (size_t)maxlds && !(env && env[0] == '0');
   const int threads = (sb.vb + 63) / 64 * 64;
   const int nblk_colour = sb.NB[0] * sb.NB[1] * sb.NB[2] * sb.NB[3] / 2;
+  const SapLinks16 lk = sap_links16(sb);
+  const size_t lds16 = lds + (size_t)sb.vb * 36 * 4 + (size_t)lk.nl * 6 * 4;
+  if (q.block_fp16) {
+    LQ_CHECK(lds16 + 1024 <= (size_t)maxlds, LQ_EINVAL,
+             "block too large to stage its FP16 clover and links in LDS (block_fp16 = 0 "
+             "streams them)");
+    LQ_CHECK(ctx->gauge[LQ_F16], LQ_ESTATE, "no FP16 gauge field");
+    sap_a16(ctx, sp);
+  }
   fill_zero(ctx, out, f32);
   LQ_HIP(hipMemcpyAsync(sp->r, in, f32, hipMemcpyDeviceToDevice, ctx->cur));
   const auto* gauge = reinterpret_cast<const float2*>(ctx->gauge[LQ_F32]);
   const Geo& g = ctx->geo;
   for (int cy = 0; cy < ncy; ++cy)
     for (int c = 0; c < 2; ++c) {
+      if (q.block_fp16) {
+        hipLaunchKernelGGL(sap_mr16_kernel, dim3(nblk_colour), dim3(threads), lds16, ctx->cur, g,
+                           sb, lk, c, nmr, (float)ctx->clov.kappa, half_of<P32>(sp->r, ctx, 0),
+                           half_of<P32>(sp->r, ctx, 1), half_of<P32>(out, ctx, 0),
+                           half_of<P32>(out, ctx, 1),
+                           reinterpret_cast<const __half2*>(ctx->gauge[LQ_F16]),
+                           reinterpret_cast<const __half2*>(sp->a16[0]),
+                           reinterpret_cast<const __half2*>(sp->a16[1]));
+        LQ_HIP(hipGetLastError());
+        // per site of the colour: its FP16 clover blocks and interior links
+        // once, the residual read and the solution read and written once
+        ctx->bytes += ctx->V / 2.0 * (clover_site_bytes(LQ_F16) +
+                                      (double)lk.nl / sb.vb * link_site_bytes(LQ_F16) +
+                                      3 * spinor_site_bytes(LQ_F32));
+        full_m<P32, true>(ctx, sp->r, in, out);
+        continue;
+      }
       if (cache)
         hipLaunchKernelGGL(sap_mr_kernel<true>, dim3(nblk_colour), dim3(threads), lds_cached,
                            ctx->cur, g, sb, c, nmr, (float)ctx->clov.kappa,
@@ -634,7 +911,8 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
 
 void sap_destroy(Sap* sp) {
   if (!sp) return;
-  for (void* p : {sp->a32[0], sp->a32[1], sp->r, sp->tmp, sp->xc, sp->r64, (void*)sp->part,
+  for (void* p : {sp->a32[0], sp->a32[1], sp->a16[0], sp->a16[1], sp->r, sp->tmp, sp->xc,
+                  sp->r64, (void*)sp->part,
                   (void*)sp->wdev, (void*)sp->zdev, (void*)sp->mres, (void*)sp->mpart,
                   (void*)sp->coef})
     if (p) (void)hipFree(p);
