@@ -42,8 +42,9 @@ Printed (one JSON line):
   sap_fgcr      the paper's own solver on the benchmark system: FGCR with the
                 SAP preconditioner (FP32 block MR, FP64 restarts), the same
                 preconditioner in FGMRES with deflated restarting, both again
-                with the block solves' operator in FP16 staged in LDS, and one
-                SAP application alone in either form;
+                with the block solves' operator in FP16 staged in LDS, and with
+                MR on the even-odd reduced block operator, and one SAP
+                application alone in each form;
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample.
 
 roofline.traffic is the HBM traffic per launch of the roofline kernel from
@@ -341,7 +342,11 @@ def sap_fgcr(lq, lat, torch, db, block, ncycles, nmr, restart, dr_m=70, dr_k=10)
                      ("fgmres_dr", {"restart": dr_m, "deflate": dr_k}),
                      ("fgcr_fp16_blocks", {"restart": restart, "block_fp16": True}),
                      ("fgmres_dr_fp16_blocks", {"restart": dr_m, "deflate": dr_k,
-                                                "block_fp16": True})):
+                                                "block_fp16": True}),
+                     ("fgcr_fp16_eo_blocks", {"restart": restart, "block_fp16": True,
+                                              "block_eo": True}),
+                     ("fgmres_dr_fp16_eo_blocks", {"restart": dr_m, "deflate": dr_k,
+                                                   "block_fp16": True, "block_eo": True})):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rep = lat.solve_sap_device(dx, db, KAPPA, CSW, TOL, block, ncycles, nmr, **kw)
@@ -354,14 +359,16 @@ def sap_fgcr(lq, lat, torch, db, block, ncycles, nmr, restart, dr_m=70, dr_k=10)
     e = lat.new_field(lq.FULL, lq.F32)
     y = lat.new_field(lq.FULL, lq.F32)
     e.copy_(lat.to_device(lat.to_host(db, lq.FULL, lq.F64), lq.FULL, lq.F32))
-    for name, fp16 in (("sap_apply_ms", False), ("sap_apply_fp16_blocks_ms", True)):
-        lat.sap_apply(y, e, block, ncycles, nmr, block_fp16=fp16)
+    for name, fp16, eo in (("sap_apply_ms", False, False),
+                           ("sap_apply_fp16_blocks_ms", True, False),
+                           ("sap_apply_fp16_eo_blocks_ms", True, True)):
+        lat.sap_apply(y, e, block, ncycles, nmr, block_fp16=fp16, block_eo=eo)
         a = torch.cuda.Event(enable_timing=True)
         z = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         a.record()
         for _ in range(5):
-            lat.sap_apply(y, e, block, ncycles, nmr, block_fp16=fp16)
+            lat.sap_apply(y, e, block, ncycles, nmr, block_fp16=fp16, block_eo=eo)
         z.record()
         torch.cuda.synchronize()
         out[name] = round(a.elapsed_time(z) / 5, 3)

@@ -342,6 +342,12 @@ typedef struct {
                      (at most 512 sites per block as always; 8x4x4x4 fits).  The
                      preconditioner then differs from the FP32 one by the FP16 rounding of
                      the operator, which the flexible outer solver absorbs */
+  int block_eo;   /* 1 (with block_fp16 = 1 and an even x extent of the blocks): MR on the
+                     even-odd reduced block operator A_ee - kappa^2 H_eo A_oo^-1 H_oe
+                     (block-restricted hopping term) from the source r_e + kappa H_eo
+                     A_oo^-1 r_o, then d_o = A_oo^-1 (r_o + kappa H_oe d_e): the block
+                     solve the paper's performance model counts (section 5, eq.
+                     sapmodel).  0: MR on the block operator itself */
 } lq_sap_params;
 
 /* dev_out = K dev_in on full-lattice FP32 fields (lq_field_bytes(ctx,

@@ -528,6 +528,247 @@ __global__ __launch_bounds__(SAP_MAXV) void sap_mr16_kernel(
   }
 }
 
+// ---- even-odd reduced block solves (the refinement eq. sapmodel counts)
+// The block system M_b d = r splits into the block's even and odd sites
+// (global parity); MR runs on the Schur operator
+//   Mhat_b d_e = A_ee d_e - kappa^2 H_eo^b A_oo^-1 H_oe^b d_e
+// (H^b: the hopping term restricted to the block, Dirichlet) with source
+// r_e + kappa H_eo^b A_oo^-1 r_o, from d_e = 0, and then
+//   d_o = A_oo^-1 (r_o + kappa H_oe^b d_e).
+// One thread holds the pair of block sites (2 i, 2 i + 1), x neighbours of
+// opposite parity (the x extent of a block is even): it works on the odd
+// one in the first half of an MR step (t_o = A_oo^-1 H_oe^b rho_e) and on the
+// even one in the second (q_e = A_ee rho_e - kappa^2 H_eo^b t_o), so every
+// lane is busy in both.  LDS: rho_e and t_o by pair [12][vb / 2] (FP32),
+// the clover table of each site by block site [36][vb] (FP16: A_ee at even
+// sites, A_oo^-1 at odd ones), the interior links as in sap_mr16_kernel.
+
+struct EoSite {
+  int t;          // block-local site index
+  int l[4];       // block-local coordinates
+  int64_t s;      // checkerboard index of its parity
+  int fi[4], bi[4];  // interior link of the forward hop / of the backward neighbour (-1: none)
+  int nf[4], nb[4];  // pair index of the forward / backward neighbour (-1: outside the block)
+};
+
+__device__ __forceinline__ EoSite eo_site(const Geo& g, const SapBlocks& sb, const SapLinks16& lk,
+                                          const int org[4], int t, bool on) {
+  EoSite e;
+  e.t = t;
+  int q = t;
+  e.l[0] = q % sb.B[0];
+  q /= sb.B[0];
+  e.l[1] = q % sb.B[1];
+  q /= sb.B[1];
+  e.l[2] = q % sb.B[2];
+  e.l[3] = q / sb.B[2];
+  int x[4];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) x[mu] = org[mu] + e.l[mu];
+  e.s = cb_index(g, x);
+  const int stride[4] = {1, sb.B[0], sb.B[0] * sb.B[1], sb.B[0] * sb.B[1] * sb.B[2]};
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const bool f = on && e.l[mu] + 1 < sb.B[mu], b = on && e.l[mu] > 0;
+    e.fi[mu] = f ? sap_link16_idx(sb, lk, mu, e.l) : -1;
+    int lb[4] = {e.l[0], e.l[1], e.l[2], e.l[3]};
+    lb[mu] -= 1;
+    e.bi[mu] = b ? sap_link16_idx(sb, lk, mu, lb) : -1;
+    e.nf[mu] = f ? (t + stride[mu]) >> 1 : -1;
+    e.nb[mu] = b ? (t - stride[mu]) >> 1 : -1;
+  }
+  return e;
+}
+
+// acc += H^b v at site e, v of the other parity stored by pair [12][hb]
+template <int MU>
+__device__ __forceinline__ void eo_hops(const float2* v, int hb, const unsigned* L, int nl,
+                                        const EoSite& e, C<float> acc[12]) {
+  if (e.nf[MU] >= 0) {
+    C<float> w12[12], h[6], u[9], w[6];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 z = v[c * hb + e.nf[MU]];
+      w12[c] = C<float>{z.x, z.y};
+    }
+    project<MU, 1>(w12, h);
+    lds_link16(L, nl, e.fi[MU], u);
+    link_mul<false>(u, h, w);
+    reconstruct_add<MU, 1>(acc, w);
+  }
+  if (e.nb[MU] >= 0) {
+    C<float> w12[12], h[6], u[9], w[6];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const float2 z = v[c * hb + e.nb[MU]];
+      w12[c] = C<float>{z.x, z.y};
+    }
+    project<MU, -1>(w12, h);
+    lds_link16(L, nl, e.bi[MU], u);
+    link_mul<true>(u, h, w);
+    reconstruct_add<MU, -1>(acc, w);
+  }
+}
+
+__device__ __forceinline__ void eo_hop_all(const float2* v, int hb, const unsigned* L, int nl,
+                                           const EoSite& e, C<float> acc[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = C<float>{0.f, 0.f};
+  eo_hops<0>(v, hb, L, nl, e, acc);
+  eo_hops<1>(v, hb, L, nl, e, acc);
+  eo_hops<2>(v, hb, L, nl, e, acc);
+  eo_hops<3>(v, hb, L, nl, e, acc);
+}
+
+__device__ __forceinline__ void eo_store(float2* v, int hb, int i, const C<float> x[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c * hb + i] = make_float2(x[c].re, x[c].im);
+}
+
+__global__ __launch_bounds__(SAP_MAXV / 2) void sap_mr16eo_kernel(
+    Geo g, SapBlocks sb, SapLinks16 lk, int colour, int nmr, float kappa, Field<P32> r0,
+    Field<P32> r1, Field<P32> psi0, Field<P32> psi1, const __half2* __restrict__ gauge16,
+    const __half2* __restrict__ aee16, const __half2* __restrict__ aooinv16) {
+  extern __shared__ float2 sm[];
+  __shared__ double tot[3];
+  __shared__ double sh[3][16];
+  const int hb = sb.vb >> 1;
+  float2* RE = sm;             // [12][hb] rho_e, at the end d_e
+  float2* TO = sm + 12 * hb;   // [12][hb] t_o
+  unsigned* A16 = reinterpret_cast<unsigned*>(sm + 24 * hb);  // [36][vb]
+  unsigned* L16 = A16 + 36 * sb.vb;                            // [6][nl]
+  const int i = threadIdx.x;
+  const bool on = i < hb;
+  const int ii = on ? i : 0;
+  const int half = sb.NB[0] >> 1;
+  int j = blockIdx.x;
+  const int jx = j % half;
+  j /= half;
+  const int by = j % sb.NB[1];
+  j /= sb.NB[1];
+  const int bz = j % sb.NB[2];
+  const int bt = j / sb.NB[2];
+  const int bx = 2 * jx + ((by + bz + bt + colour) & 1);
+  const int org[4] = {bx * sb.B[0], by * sb.B[1], bz * sb.B[2], bt * sb.B[3]};
+  // the pair (2 i, 2 i + 1): which of the two is even
+  const EoSite a = eo_site(g, sb, lk, org, 2 * ii, on);
+  const int pa = (org[0] + org[1] + org[2] + org[3] + a.l[0] + a.l[1] + a.l[2] + a.l[3]) & 1;
+  const EoSite E = eo_site(g, sb, lk, org, 2 * ii + pa, on);
+  const EoSite O = eo_site(g, sb, lk, org, 2 * ii + 1 - pa, on);
+  Field<P32> fe, fo, pe, po;
+  fe.d = r0.d;
+  fo.d = r1.d;
+  pe.d = psi0.d;
+  po.d = psi1.d;
+  fe.norm = fo.norm = pe.norm = po.norm = nullptr;
+  if (on) {
+    const unsigned* ae = reinterpret_cast<const unsigned*>(aee16);
+    const unsigned* ao = reinterpret_cast<const unsigned*>(aooinv16);
+#pragma unroll
+    for (int k = 0; k < 36; ++k) {
+      A16[k * sb.vb + E.t] = ae[clov_idx(E.s, k)];
+      A16[k * sb.vb + O.t] = ao[clov_idx(O.s, k)];
+    }
+    const unsigned* gl = reinterpret_cast<const unsigned*>(gauge16);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      if (E.fi[mu] >= 0)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) L16[c * lk.nl + E.fi[mu]] = gl[link_idx(g.nblk, 0, mu, E.s, c)];
+      if (O.fi[mu] >= 0)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) L16[c * lk.nl + O.fi[mu]] = gl[link_idx(g.nblk, 1, mu, O.s, c)];
+    }
+  }
+  C<float> ro[12], rho[12], del[12], w[12], acc[12];
+  if (on) {
+    load_spinor<P32>(fo, O.s, ro);
+    load_spinor<P32>(fe, E.s, rho);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) ro[c] = rho[c] = C<float>{0.f, 0.f};
+  }
+  __syncthreads();  // clover and links staged
+  // source: rho_e = r_e + kappa H_eo^b A_oo^-1 r_o
+  if (on) {
+    lds_clover16(A16, sb.vb, O.t, ro, w);
+    eo_store(TO, hb, i, w);
+  }
+  __syncthreads();
+  if (on) {
+    eo_hop_all(TO, hb, L16, lk.nl, E, acc);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rho[c] = rho[c] + kappa * acc[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) del[c] = C<float>{0.f, 0.f};
+  __syncthreads();  // every read of TO above is done
+  if (on) eo_store(RE, hb, i, rho);
+  const float k2 = kappa * kappa;
+  for (int it = 0; it < nmr; ++it) {
+    __syncthreads();
+    // odd half: t_o = A_oo^-1 H_oe^b rho_e
+    if (on) {
+      eo_hop_all(RE, hb, L16, lk.nl, O, acc);
+      lds_clover16(A16, sb.vb, O.t, acc, w);
+      eo_store(TO, hb, i, w);
+    }
+    __syncthreads();
+    // even half: q_e = A_ee rho_e - kappa^2 H_eo^b t_o
+    double v[3] = {0.0, 0.0, 0.0};
+    C<float> q[12];
+    if (on) {
+      eo_hop_all(TO, hb, L16, lk.nl, E, acc);
+      lds_clover16(A16, sb.vb, E.t, rho, q);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        q[c] = q[c] - k2 * acc[c];
+        v[0] += (double)q[c].re * rho[c].re + (double)q[c].im * rho[c].im;  // <q, rho>
+        v[1] += (double)q[c].re * rho[c].im - (double)q[c].im * rho[c].re;
+        v[2] += (double)q[c].re * q[c].re + (double)q[c].im * q[c].im;      // <q, q>
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) q[c] = C<float>{0.f, 0.f};
+    }
+    block_sum<3>(v, sh);  // (its barriers also end every read of RE and TO above)
+    if (threadIdx.x == 0) {
+      tot[0] = v[0];
+      tot[1] = v[1];
+      tot[2] = v[2];
+    }
+    __syncthreads();
+    const double qq = tot[2];
+    const C<float> al = qq > 0.0 ? C<float>{(float)(tot[0] / qq), (float)(tot[1] / qq)}
+                                 : C<float>{0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      del[c] = del[c] + al * rho[c];
+      rho[c] = rho[c] - al * q[c];
+    }
+    if (on) eo_store(RE, hb, i, rho);
+  }
+  // d_o = A_oo^-1 (r_o + kappa H_oe^b d_e)
+  __syncthreads();
+  if (on) eo_store(RE, hb, i, del);
+  __syncthreads();
+  if (on) {
+    eo_hop_all(RE, hb, L16, lk.nl, O, acc);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = ro[c] + kappa * acc[c];
+    lds_clover16(A16, sb.vb, O.t, acc, w);
+    C<float> o[12];
+    load_spinor<P32>(pe, E.s, o);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] = o[c] + del[c];
+    store_spinor<P32>(pe, E.s, o);
+    load_spinor<P32>(po, O.s, o);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] = o[c] + w[c];
+    store_spinor<P32>(po, O.s, o);
+  }
+}
+
 // FP64 clover blocks -> FP16
 __global__ void sap_a16_kernel(const double2* __restrict__ in, __half2* __restrict__ out,
                                int64_t n) {
@@ -829,6 +1070,7 @@ SapBlocks blocks_of(const lq_ctx* ctx, const lq_sap_params& q) {
   }
   LQ_CHECK(sb.vb <= SAP_MAXV, LQ_EINVAL, "a block holds at most 512 sites");
   LQ_CHECK(q.block_fp16 == 0 || q.block_fp16 == 1, LQ_EINVAL, "block_fp16 is 0 or 1");
+  LQ_CHECK(q.block_eo == 0 || q.block_eo == 1, LQ_EINVAL, "block_eo is 0 or 1");
   return sb;
 }
 
@@ -851,6 +1093,13 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
   const int nblk_colour = sb.NB[0] * sb.NB[1] * sb.NB[2] * sb.NB[3] / 2;
   const SapLinks16 lk = sap_links16(sb);
   const size_t lds16 = lds + (size_t)sb.vb * 36 * 4 + (size_t)lk.nl * 6 * 4;
+  if (q.block_eo) {
+    LQ_CHECK(q.block_fp16, LQ_EINVAL, "the even-odd block solver runs on the FP16 staged "
+                                      "operator (block_fp16 = 1)");
+    LQ_CHECK(sb.B[0] % 2 == 0, LQ_EINVAL, "the even-odd block solver needs an even x extent");
+    LQ_CHECK(ctx->clov.a_ee[LQ_F16] && ctx->clov.ainv_oo[LQ_F16], LQ_ESTATE,
+             "no FP16 clover tables");
+  }
   if (q.block_fp16) {
     LQ_CHECK(lds16 + 1024 <= (size_t)maxlds, LQ_EINVAL,
              "block too large to stage its FP16 clover and links in LDS (block_fp16 = 0 "
@@ -864,6 +1113,21 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
   const Geo& g = ctx->geo;
   for (int cy = 0; cy < ncy; ++cy)
     for (int c = 0; c < 2; ++c) {
+      if (q.block_fp16 && q.block_eo) {
+        hipLaunchKernelGGL(sap_mr16eo_kernel, dim3(nblk_colour), dim3((sb.vb / 2 + 63) / 64 * 64),
+                           lds16, ctx->cur, g, sb, lk, c, nmr, (float)ctx->clov.kappa,
+                           half_of<P32>(sp->r, ctx, 0), half_of<P32>(sp->r, ctx, 1),
+                           half_of<P32>(out, ctx, 0), half_of<P32>(out, ctx, 1),
+                           reinterpret_cast<const __half2*>(ctx->gauge[LQ_F16]),
+                           reinterpret_cast<const __half2*>(ctx->clov.a_ee[LQ_F16]),
+                           reinterpret_cast<const __half2*>(ctx->clov.ainv_oo[LQ_F16]));
+        LQ_HIP(hipGetLastError());
+        ctx->bytes += ctx->V / 2.0 * (clover_site_bytes(LQ_F16) +
+                                      (double)lk.nl / sb.vb * link_site_bytes(LQ_F16) +
+                                      3 * spinor_site_bytes(LQ_F32));
+        full_m<P32, true>(ctx, sp->r, in, out);
+        continue;
+      }
       if (q.block_fp16) {
         hipLaunchKernelGGL(sap_mr16_kernel, dim3(nblk_colour), dim3(threads), lds16, ctx->cur, g,
                            sb, lk, c, nmr, (float)ctx->clov.kappa, half_of<P32>(sp->r, ctx, 0),

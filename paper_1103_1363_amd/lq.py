@@ -58,7 +58,7 @@ class SolveReport(ct.Structure):
 class SapParams(ct.Structure):
     _fields_ = [("block", ct.c_int * 4), ("ncycles", ct.c_int), ("nmr", ct.c_int),
                 ("restart", ct.c_int), ("maxiter", ct.c_int), ("deflate", ct.c_int),
-                ("block_fp16", ct.c_int)]
+                ("block_fp16", ct.c_int), ("block_eo", ct.c_int)]
 
 
 class EnsembleReport(ct.Structure):
@@ -390,22 +390,26 @@ class Lattice:
 
     # -- SAP preconditioner and FGCR ------------------------------------
     @staticmethod
-    def _sap_params(block, ncycles, nmr, restart=0, maxiter=0, deflate=0, block_fp16=0):
+    def _sap_params(block, ncycles, nmr, restart=0, maxiter=0, deflate=0, block_fp16=0,
+                    block_eo=0):
         return SapParams((ct.c_int * 4)(*[int(b) for b in block]), int(ncycles), int(nmr),
-                         int(restart), int(maxiter), int(deflate), int(bool(block_fp16)))
+                         int(restart), int(maxiter), int(deflate), int(bool(block_fp16)),
+                         int(bool(block_eo)))
 
-    def sap_apply(self, dev_out, dev_in, block, ncycles=0, nmr=0, block_fp16=False):
+    def sap_apply(self, dev_out, dev_in, block, ncycles=0, nmr=0, block_fp16=False,
+                  block_eo=False):
         """dev_out = K dev_in on full-lattice FP32 fields (see lq_sap_apply)."""
-        p = self._sap_params(block, ncycles, nmr, block_fp16=block_fp16)
+        p = self._sap_params(block, ncycles, nmr, block_fp16=block_fp16, block_eo=block_eo)
         self._check(self._L.lq_sap_apply(self._h, ct.c_void_p(dev_out.data_ptr()),
                                          ct.c_void_p(dev_in.data_ptr()), ct.byref(p)))
 
     def solve_sap_device(self, dev_x, dev_b, kappa, csw, tol=1e-10, block=(4, 4, 4, 4),
                          ncycles=0, nmr=0, restart=0, maxiter=0, raise_on_noconv=True,
-                         deflate=0, block_fp16=False):
+                         deflate=0, block_fp16=False, block_eo=False):
         """SAP-preconditioned FGCR, or FGMRES-DR with `deflate` deflated vectors, on
         full-lattice FP64 device fields (see lq_solve_sap)."""
-        p = self._sap_params(block, ncycles, nmr, restart, maxiter, deflate, block_fp16)
+        p = self._sap_params(block, ncycles, nmr, restart, maxiter, deflate, block_fp16,
+                             block_eo)
         rep = SolveReport()
         rc = self._L.lq_solve_sap(self._h, ct.c_void_p(dev_x.data_ptr()),
                                   ct.c_void_p(dev_b.data_ptr()), float(kappa), float(csw),

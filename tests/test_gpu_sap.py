@@ -34,51 +34,60 @@ CASES = [
 
 @pytest.mark.parametrize("dims,block,tile", CASES)
 @pytest.mark.parametrize("ncy,nmr", [(1, 1), (2, 4)])
-@pytest.mark.parametrize("kernel", ["lds_links", "hbm_links", "fp16_staged"])
+@pytest.mark.parametrize("kernel", ["lds_links", "hbm_links", "fp16_staged", "fp16_eo"])
 def test_sap_apply_parity(lq, monkeypatch, dims, block, tile, ncy, nmr, kernel):
-    """All three block kernels: FP32 links copied to LDS once, or read from
-    HBM at every MR step (LQ_SAP_LDS_LINKS=0); or FP16 links and clover
-    staged in LDS (block_fp16), whose operator carries the FP16 rounding of
-    its links and clover entries (a few 1e-4 relative): bound 5e-3, the
-    FP16 operator's bound, instead of 1e-4."""
+    """All four block kernels: FP32 links copied to LDS once, or read from
+    HBM at every MR step (LQ_SAP_LDS_LINKS=0); FP16 links and clover staged
+    in LDS (block_fp16), whose operator carries the FP16 rounding of its
+    links and clover entries (a few 1e-4 relative): bound 5e-3, the FP16
+    operator's bound, instead of 1e-4; and the same with MR on the even-odd
+    reduced block operator (block_eo), against the oracle's even-odd block
+    solver.  The even-odd form needs an even x extent of the blocks and
+    refuses others."""
     say(f"sap apply dims={dims} block={block} tile={tile} ncy={ncy} nmr={nmr} kernel={kernel}")
     if tile:
         monkeypatch.setenv("LQ_TILE_SITES", tile)
     monkeypatch.setenv("LQ_SAP_LDS_LINKS", "0" if kernel == "hbm_links" else "1")
-    fp16 = kernel == "fp16_staged"
+    fp16 = kernel in ("fp16_staged", "fp16_eo")
+    eo = kernel == "fp16_eo"
     u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 31)
     eta = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 31)
     lat = lq.Lattice(dims)
     lat.upload_gauge(u)
     lat.set_clover(KAPPA, CSW)
     wc = evenodd.WilsonClover(u, KAPPA, CSW)
-    ref = sap.sap(wc.M, eta, dims, block, ncy, nmr)
     din = lat.to_device(eta, lq.FULL, lq.F32)
     dout = lat.new_field(lq.FULL, lq.F32)
-    lat.sap_apply(dout, din, block, ncy, nmr, block_fp16=fp16)
+    if eo and block[0] % 2:
+        with pytest.raises(lq.LQError):
+            lat.sap_apply(dout, din, block, ncy, nmr, block_fp16=True, block_eo=True)
+        return
+    ref = sap.sap(wc.M, eta, dims, block, ncy, nmr, wc=wc if eo else None)
+    lat.sap_apply(dout, din, block, ncy, nmr, block_fp16=fp16, block_eo=eo)
     got = lat.to_host(dout, lq.FULL, lq.F32).reshape(ref.shape)
     err = log_errors("SAP application", got, ref)
     assert err <= (5e-3 if fp16 else 1e-4), err
 
 
 @pytest.mark.parametrize("dims,block", [((8, 8, 8, 8), (4, 4, 4, 4)), ((8, 4, 4, 8), (2, 2, 2, 2))])
-@pytest.mark.parametrize("fp16", [False, True])
-def test_solve_sap(lq, dims, block, fp16):
-    say(f"sap-fgcr solve dims={dims} block={block} block_fp16={fp16}")
+@pytest.mark.parametrize("fp16,eo", [(False, False), (True, False), (True, True)])
+def test_solve_sap(lq, dims, block, fp16, eo):
+    say(f"sap-fgcr solve dims={dims} block={block} block_fp16={fp16} block_eo={eo}")
     kappa, csw, tol = 0.135, 1.0, 1e-10
     u = fields.gauge_field(dims, "smooth", fields.SEED_GAUGE + 32)
     b = fields.gaussian_spinor(dims, fields.SEED_SOURCE + 32)
     lat = lq.Lattice(dims)
     lat.upload_gauge(u)
     x, rep = lat.solve_sap(b, kappa, csw, tol, block, ncycles=4, nmr=4, restart=16,
-                           block_fp16=fp16)
+                           block_fp16=fp16, block_eo=eo)
     wc = evenodd.WilsonClover(u, kappa, csw)
     res = dirac.norm(b - wc.M(x)) / dirac.norm(b)
     say(f"  iterations={rep.iterations} restarts={rep.reliable_updates} res={res:.2e}")
     assert res <= tol, (res, rep)
     assert abs(rep.true_residual - res) <= 0.1 * res + 1e-14
     # the oracle's FGCR with the same preconditioner takes about as many steps
-    _, info = sap.fgcr(wc.M, b, lambda v: sap.sap(wc.M, v, dims, block, 4, 4), m=16, tol=tol)
+    _, info = sap.fgcr(wc.M, b, lambda v: sap.sap(wc.M, v, dims, block, 4, 4,
+                                                  wc=wc if eo else None), m=16, tol=tol)
     assert abs(rep.iterations - info.iterations) <= max(3, info.iterations // 4), (
         rep.iterations, info.iterations)
 
@@ -105,8 +114,8 @@ def test_sap_zero_source_and_bad_blocks(lq):
         big.sap_apply(bo, bi, (32, 4, 4, 2), 1, 1)  # 1024 sites per block
 
 
-@pytest.mark.parametrize("fp16", [False, True])
-def test_full_size_sap_fgcr(lq, fp16):
+@pytest.mark.parametrize("fp16,eo", [(False, False), (True, False), (True, True)])
+def test_full_size_sap_fgcr(lq, fp16, eo):
     """The benchmark's SAP-FGCR run at its full size (32^3x64, kappa 0.135,
     csw 1, blocks 8x4x4x4, 3 cycles of 6 MR steps, restart 48; block solves
     with the FP32 operator and with the FP16 one staged in LDS): the
@@ -116,13 +125,14 @@ def test_full_size_sap_fgcr(lq, fp16):
     from tests.gpu_common import case
     from tests.test_gpu_solver import sampled_residuals
     dims, kappa, csw, tol = (32, 32, 32, 64), 0.135, 1.0, 1e-10
-    say(f"full-size SAP-FGCR 32^3x64 block_fp16={fp16}")
+    say(f"full-size SAP-FGCR 32^3x64 block_fp16={fp16} block_eo={eo}")
     u, b, _, _ = case(dims, "smooth", 2)
     lat = lq.Lattice(dims)
     lat.upload_gauge(u)
     db = lat.to_device(b, lq.FULL, lq.F64)
     dx = lat.new_field(lq.FULL, lq.F64)
-    rep = lat.solve_sap_device(dx, db, kappa, csw, tol, (8, 4, 4, 4), 3, 6, 48, block_fp16=fp16)
+    rep = lat.solve_sap_device(dx, db, kappa, csw, tol, (8, 4, 4, 4), 3, 6, 48, block_fp16=fp16,
+                               block_eo=eo)
     say(f"  {rep.iterations} steps, {rep.reliable_updates} restarts, "
         f"residual {rep.true_residual:.2e}")
     assert rep.true_residual <= tol

@@ -93,7 +93,7 @@ def test_sap_calls_reject_missing_context():
     lib.lq_sap_apply.argtypes = [vp, vp, vp, vp]
     lib.lq_solve_sap.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  vp, vp]
-    params = (ctypes.c_int * 10)(4, 4, 4, 4, 0, 0, 0, 0, 0, 0)  # lq_sap_params: block[4] + 6 ints
+    params = (ctypes.c_int * 11)(4, 4, 4, 4, 0, 0, 0, 0, 0, 0, 0)  # lq_sap_params: block[4] + 7 ints
     buf = ctypes.create_string_buffer(64)
     assert lib.lq_sap_apply(None, buf, buf, params) == -1
     assert lib.lq_solve_sap(None, buf, buf, 0.13, 1.0, 1e-10, params, None) == -1
