@@ -346,10 +346,15 @@ def sap_fgcr(lq, lat, torch, db, block, ncycles, nmr, restart, dr_m=70, dr_k=10)
                      ("fgcr_fp16_eo_blocks", {"restart": restart, "block_fp16": True,
                                               "block_eo": True}),
                      ("fgmres_dr_fp16_eo_blocks", {"restart": dr_m, "deflate": dr_k,
-                                                   "block_fp16": True, "block_eo": True})):
+                                                   "block_fp16": True, "block_eo": True}),
+                     ("fgcr_fp16_eo_blocks_4mr_restart24",
+                      {"restart": 24, "block_fp16": True, "block_eo": True, "nmr": 4})):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rep = lat.solve_sap_device(dx, db, KAPPA, CSW, TOL, block, ncycles, nmr, **kw)
+        kw_nmr = kw.pop("nmr", nmr)
+        rep = lat.solve_sap_device(dx, db, KAPPA, CSW, TOL, block, ncycles, kw_nmr, **kw)
+        if kw_nmr != nmr:
+            kw["nmr"] = kw_nmr
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
         out[name] = {**kw, "ms": round(ms, 1), "steps": rep.iterations,

@@ -8,17 +8,24 @@
 // turn (0 first), takes nmr minimal-residual steps on every block of that
 // colour with Dirichlet boundary conditions (hops that leave the block are
 // dropped) and then recomputes the residual r = eta - M psi on the whole
-// lattice.  One workgroup solves one block: the block's residual and its
-// links are copied into LDS once per launch (one site per thread); the
-// clover blocks stream from HBM.
-// All of it is FP32 on full-lattice fields (even half, then odd half).
+// lattice (except after the last colour of the last cycle, where nothing
+// reads it).  One workgroup solves one block, in one of three forms: the
+// block's residual and its FP32 links copied into LDS once per launch, the
+// clover blocks streamed from HBM at every MR step (one site per thread); or
+// the residual with the FP16 clover blocks and links all staged in LDS; or
+// that, with MR on the even-odd reduced block operator (a pair of sites per
+// thread).  Arithmetic is FP32 on full-lattice fields (even half, then odd
+// half).
 //
 // FGCR: right-preconditioned GCR, z_k = K r, w_k = M z_k orthonormalised by
-// Gram-Schmidt against the earlier w (classical, applied twice; the z
-// transformed alike),
-// x += <w_k, r> z_k; the recursion restarts every `restart` steps, where the
-// residual is recomputed in FP64 and the FP32 correction added to the FP64
-// solution (iterative refinement, as the paper describes).
+// Gram-Schmidt against the earlier w (classical, applied twice), r -= <w_k, r>
+// w_k.  The z_k are kept as K produced them: the Gram-Schmidt coefficients
+// and norms form an upper triangle H with M Z = W H, and the correction
+// Z H^-1 (<w_k, r>)_k is formed once per cycle (the same iterates as
+// transforming every z_k alike, with one pass over the z_k instead of one per
+// step).  The recursion restarts every `restart` steps, where the residual is
+// recomputed in FP64 and the FP32 correction added to the FP64 solution
+// (iterative refinement, as the paper describes).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -1025,11 +1032,15 @@ void caxpby(lq_ctx* ctx, void* y, std::complex<double> a, const void* x, std::co
 // launches and passes over memory.
 int gs_groups(const lq_ctx* ctx) { return grid_for(entries(ctx), 256 * GS_E); }
 
-void gram_schmidt(lq_ctx* ctx, int k, void* w, void* z) {
+// w -= sum_j <w_j, w> w_j over the k earlier directions, classical and
+// applied twice; h (k entries) receives the summed coefficients of both
+// passes, and z (may be null) is transformed alike.
+void gram_schmidt(lq_ctx* ctx, int k, void* w, void* z, std::complex<double>* h) {
   Sap* sp = ctx->sap;
   const int64_t n = entries(ctx);
   const int G = gs_groups(ctx);
   LQ_CHECK(k >= 1 && k <= 64, LQ_EINVAL, "Gram-Schmidt over 1..64 directions");
+  for (int j = 0; j < k; ++j) h[j] = 0.0;
   for (int pass = 0; pass < 2; ++pass) {
     hipLaunchKernelGGL(sap_mdot_kernel, dim3(G), dim3(256), 0, ctx->cur,
                        reinterpret_cast<const float2* const*>(sp->wdev), k,
@@ -1040,8 +1051,10 @@ void gram_schmidt(lq_ctx* ctx, int k, void* w, void* z) {
     LQ_HIP(hipMemcpyAsync(sp->hpart, sp->mres, sizeof(double) * 2 * k, hipMemcpyDeviceToHost,
                           ctx->cur));
     LQ_HIP(hipStreamSynchronize(ctx->cur));
-    for (int j = 0; j < k; ++j)
+    for (int j = 0; j < k; ++j) {
       sp->hcoef[j] = make_float2((float)sp->hpart[2 * j], (float)sp->hpart[2 * j + 1]);
+      h[j] += std::complex<double>(sp->hcoef[j].x, sp->hcoef[j].y);
+    }
     LQ_HIP(hipMemcpyAsync(sp->coef, sp->hcoef, sizeof(float2) * k, hipMemcpyHostToDevice,
                           ctx->cur));
     const int Gx = grid_for(n, 256 * GS_E);
@@ -1049,12 +1062,29 @@ void gram_schmidt(lq_ctx* ctx, int k, void* w, void* z) {
                        reinterpret_cast<float2*>(w),
                        reinterpret_cast<const float2* const*>(sp->wdev), sp->coef, k, n, n / 2,
                        ctx->geo.vh);
-    hipLaunchKernelGGL(sap_maxpy_kernel, dim3(Gx), dim3(256), 0, ctx->cur,
-                       reinterpret_cast<float2*>(z),
-                       reinterpret_cast<const float2* const*>(sp->zdev), sp->coef, k, n, n / 2,
-                       ctx->geo.vh);
+    if (z)
+      hipLaunchKernelGGL(sap_maxpy_kernel, dim3(Gx), dim3(256), 0, ctx->cur,
+                         reinterpret_cast<float2*>(z),
+                         reinterpret_cast<const float2* const*>(sp->zdev), sp->coef, k, n, n / 2,
+                         ctx->geo.vh);
     LQ_HIP(hipGetLastError());
   }
+}
+
+// y -= sum_j c_j V_j over the k directions of the device pointer array V
+// (coefficients staged through the pinned host buffer).
+void sap_lincomb_sub(lq_ctx* ctx, void* y, void** V, const std::complex<double>* c, int k) {
+  Sap* sp = ctx->sap;
+  const int64_t n = entries(ctx);
+  LQ_HIP(hipStreamSynchronize(ctx->cur));  // the staging buffer may still be in flight
+  for (int j = 0; j < k; ++j)
+    sp->hcoef[j] = make_float2((float)c[j].real(), (float)c[j].imag());
+  LQ_HIP(hipMemcpyAsync(sp->coef, sp->hcoef, sizeof(float2) * k, hipMemcpyHostToDevice,
+                        ctx->cur));
+  hipLaunchKernelGGL(sap_maxpy_kernel, dim3(grid_for(n, 256 * GS_E)), dim3(256), 0, ctx->cur,
+                     reinterpret_cast<float2*>(y), reinterpret_cast<const float2* const*>(V),
+                     sp->coef, k, n, n / 2, ctx->geo.vh);
+  LQ_HIP(hipGetLastError());
 }
 
 SapBlocks blocks_of(const lq_ctx* ctx, const lq_sap_params& q) {
@@ -1113,6 +1143,8 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
   const Geo& g = ctx->geo;
   for (int cy = 0; cy < ncy; ++cy)
     for (int c = 0; c < 2; ++c) {
+      // the residual after the last colour of the last cycle is never used
+      const bool last = cy == ncy - 1 && c == 1;
       if (q.block_fp16 && q.block_eo) {
         hipLaunchKernelGGL(sap_mr16eo_kernel, dim3(nblk_colour), dim3((sb.vb / 2 + 63) / 64 * 64),
                            lds16, ctx->cur, g, sb, lk, c, nmr, (float)ctx->clov.kappa,
@@ -1125,7 +1157,7 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
         ctx->bytes += ctx->V / 2.0 * (clover_site_bytes(LQ_F16) +
                                       (double)lk.nl / sb.vb * link_site_bytes(LQ_F16) +
                                       3 * spinor_site_bytes(LQ_F32));
-        full_m<P32, true>(ctx, sp->r, in, out);
+        if (!last) full_m<P32, true>(ctx, sp->r, in, out);
         continue;
       }
       if (q.block_fp16) {
@@ -1142,7 +1174,7 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
         ctx->bytes += ctx->V / 2.0 * (clover_site_bytes(LQ_F16) +
                                       (double)lk.nl / sb.vb * link_site_bytes(LQ_F16) +
                                       3 * spinor_site_bytes(LQ_F32));
-        full_m<P32, true>(ctx, sp->r, in, out);
+        if (!last) full_m<P32, true>(ctx, sp->r, in, out);
         continue;
       }
       if (cache)
@@ -1167,7 +1199,7 @@ void sap_apply_impl(lq_ctx* ctx, void* out, const void* in, const lq_sap_params&
                                            clover_site_bytes(LQ_F32)) +
                                     (cache ? 4 : 0) * link_site_bytes(LQ_F32) +
                                     3 * spinor_site_bytes(LQ_F32));
-      full_m<P32, true>(ctx, sp->r, in, out);
+      if (!last) full_m<P32, true>(ctx, sp->r, in, out);
     }
 }
 
@@ -1269,24 +1301,41 @@ bool solve_sap(lq_ctx* ctx, void* x, const void* b, double tol, const lq_sap_par
       // stops at what the FP64 residual still needs (with a margin of 2)
       const double cycle = std::max(1e-5, 0.5 * tol / res);
       const int iters0 = iters;
+      // The preconditioned directions z_k stay as K produced them: with H the
+      // upper triangle of Gram-Schmidt coefficients (H[j][k], j < k) and the
+      // norms (H[k][k]), M Z = W H, so the correction is Z H^-1 alpha, formed
+      // once at the end of the cycle instead of transforming every z_k.
+      std::vector<std::complex<double>> H((size_t)m * m, 0.0), alpha(m, 0.0), hk(m);
+      int kk = 0;
       for (int k = 0; k < m && iters < maxiter; ++k) {
         sap_apply_impl(ctx, sp->z[k], rho, q);
         full_m<P32, false>(ctx, sp->w[k], nullptr, sp->z[k]);
-        if (k > 0) gram_schmidt(ctx, k, sp->w[k], sp->z[k]);
+        if (k > 0) gram_schmidt(ctx, k, sp->w[k], nullptr, hk.data());
         dot3<float2, float2>(ctx, sp->w[k], sp->w[k], d);
         const double wn = std::sqrt(d[2]);
         if (!(wn > 0.0) || !std::isfinite(wn)) break;
+        for (int j = 0; j < k; ++j) H[(size_t)j * m + k] = hk[j];
+        H[(size_t)k * m + k] = wn;
         caxpby(ctx, sp->w[k], 1.0 / wn, sp->w[k], 0.0);
-        caxpby(ctx, sp->z[k], 1.0 / wn, sp->z[k], 0.0);
         dot3<float2, float2>(ctx, sp->w[k], rho, d);
         const std::complex<double> al(d[0], d[1]);
-        caxpby(ctx, sp->xc, al, sp->z[k], 1.0);
+        alpha[k] = al;
         caxpby(ctx, rho, -al, sp->w[k], 1.0);
         ++iters;
+        kk = k + 1;
         dot3<float2, float2>(ctx, rho, rho, d);
         if (std::sqrt(d[2]) <= cycle) break;
       }
       if (iters == iters0) break;  // breakdown at the cycle's first direction
+      // y = H^-1 alpha (back substitution), xc = Z y
+      std::vector<std::complex<double>> y(kk), neg(kk);
+      for (int i = kk - 1; i >= 0; --i) {
+        std::complex<double> t = alpha[i];
+        for (int j = i + 1; j < kk; ++j) t -= H[(size_t)i * m + j] * y[j];
+        y[i] = t / H[(size_t)i * m + i];
+        neg[i] = -y[i];  // the kernel subtracts
+      }
+      sap_lincomb_sub(ctx, sp->xc, sp->zdev, neg.data(), kk);
       hipLaunchKernelGGL(sap_add64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, ctx->cur,
                          reinterpret_cast<double2*>(x), reinterpret_cast<const float2*>(sp->xc),
                          rn, n);
