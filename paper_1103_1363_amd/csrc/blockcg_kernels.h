@@ -25,10 +25,16 @@
 
 namespace lq {
 
-constexpr int BCG_BT = 16;          // sites per tile
+#ifndef LQ_BCG_BT
+#define LQ_BCG_BT 16
+#endif
+#ifndef LQ_BCG_GRID
+#define LQ_BCG_GRID 2048
+#endif
+constexpr int BCG_BT = LQ_BCG_BT;      // sites per tile
 constexpr int BCG_ROWS = BCG_BT * 12;
 constexpr int BCG_THREADS = 256;
-constexpr int BCG_GRID = 1024;      // workgroups (persistent over tiles)
+constexpr int BCG_GRID = LQ_BCG_GRID;  // workgroups (persistent over tiles)
 
 // value of entry (s, r, c) as FP32 complex
 template <class P>
