@@ -154,6 +154,29 @@ def su3_sweep(lq, torch, n=1 << 23, prec=0, reps=20):
     return out
 
 
+def sap_sweep(lq, torch, lat, block=(8, 4, 4, 4), ncycles=3, nmr=6, reps=5):
+    """One SAP application (lq_sap_apply) on a Gaussian FP32 source with each
+    block solver: FP32 operator (links in LDS, clover from HBM), FP16
+    operator staged in LDS, and the even-odd reduced block solve on the
+    FP16 staged operator; mean time over `reps` after one warm-up."""
+    from gen import fields
+    e = lat.to_device(fields.gaussian_spinor(lat.dims, fields.SEED_SOURCE + 2), lq.FULL, lq.F32)
+    y = lat.new_field(lq.FULL, lq.F32)
+    out = {"block": list(block), "ncycles": ncycles, "nmr": nmr}
+    for name, fp16, eo in (("fp32", False, False), ("fp16_staged", True, False),
+                           ("fp16_even_odd", True, True)):
+        lat.sap_apply(y, e, block, ncycles, nmr, block_fp16=fp16, block_eo=eo)
+        a, b = _events(torch)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            lat.sap_apply(y, e, block, ncycles, nmr, block_fp16=fp16, block_eo=eo)
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = {"ms": round(a.elapsed_time(b) / reps, 3)}
+    return out
+
+
 def make_lattices(lq, dims, copies, seed=1100, u=None, tile_sites=0, mr_tile_sites=0):
     """`copies` contexts, each with its own device copy of one smooth gauge
     field (distinct buffers are what the rotation needs; the values may
@@ -177,6 +200,8 @@ def main():
     ap.add_argument("--reps", type=int, default=50)
     ap.add_argument("--copy-kernel", action="store_true")
     ap.add_argument("--su3", action="store_true", help="the SU(3) array-product sweeps")
+    ap.add_argument("--sap", action="store_true",
+                    help="one SAP application per block solver (kappa 0.135, csw 1)")
     ap.add_argument("--gauge-cache", default=None,
                     help="an .npy file holding the smooth gauge field (written if absent)")
     a = ap.parse_args()
@@ -193,7 +218,7 @@ def main():
         out["su3_f64"] = su3_sweep(lq, torch, prec=0)
         out["su3_f32"] = su3_sweep(lq, torch, prec=1)
     precs = [p for p in a.prec.split(",") if p]
-    if precs:
+    if precs or a.sap:
         print(f"sweep: one gauge field {dims} in {a.copies} contexts", file=sys.stderr, flush=True)
         u = None
         if a.gauge_cache and os.path.exists(a.gauge_cache):
@@ -208,6 +233,10 @@ def main():
         for p in precs:
             print(f"sweep: {p}", file=sys.stderr, flush=True)
             out[p] = dslash_sweep(lq, lats, torch, p, a.reps)
+        if a.sap:
+            print("sweep: SAP", file=sys.stderr, flush=True)
+            lats[0].set_clover(0.135, 1.0)
+            out["sap"] = sap_sweep(lq, torch, lats[0])
     print(json.dumps(out), flush=True)
 
 
