@@ -462,8 +462,9 @@ def cpu_baseline(u, b, dims, gpu_iters):
 def config_16(lq, torch):
     """The 16^3x32 configuration (kappa 0.135, csw 1, smooth links, Gaussian
     source): FP32 inner iteration with FP64 reliable updates against plain
-    FP64 CG.  Its fields (about 0.1 GB) stay in the 256 MB last-level cache,
-    so its rates are cache-resident, not HBM rates."""
+    FP64 CG, and BiCGStab on the Schur operator (FP32 inner and FP64).  Its
+    fields (about 0.1 GB) stay in the 256 MB last-level cache, so its rates
+    are cache-resident, not HBM rates."""
     from gen import fields
     d16 = (16, 16, 16, 32)
     u16 = fields.gauge_field(d16, "smooth", fields.SEED_GAUGE + 1)
@@ -484,6 +485,14 @@ def config_16(lq, torch):
                      "reliable_updates": r.reliable_updates, "fallback": r.fallback,
                      "true_residual": r.true_residual}
     out["speedup_f32_vs_plain_fp64"] = round(out["plain_fp64"]["ms"] / out["mixed_f32"]["ms"], 3)
+    for name, prec in (("bicgstab_f32", lq.F32), ("bicgstab_f64", lq.F64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lat.solve_device(dx, db, KAPPA, CSW, TOL, solver=lq.BICGSTAB, inner_prec=prec)[0]
+        torch.cuda.synchronize()
+        out[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), "iterations": r.iterations,
+                     "reliable_updates": r.reliable_updates, "fallback": r.fallback,
+                     "true_residual": r.true_residual}
     del lat, db, dx
     return out
 
