@@ -88,7 +88,8 @@ typedef struct {
   int inner_prec;        /* lq_prec of the inner iteration: F64 = plain solve,
                             F32/F16 = mixed precision with FP64 reliable updates */
   int maxiter;           /* total inner iterations, default 20000 */
-  double delta;          /* reliable-update trigger ||r|| < delta * max ||r||, default 0.1 */
+  double delta;          /* reliable-update trigger ||r|| < delta * max ||r||, default 0.1
+                            (0.03 for batched = 1) */
   int restart;           /* FGMRES restart length m, default 32 */
   int check_every;       /* iterations per captured graph replay, default 8 */
   int use_graph;         /* 1 (default when 0 is given: 1) replay captured iterations;
