@@ -3,6 +3,7 @@ turn two counter runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per launch.
 
 Usage: python -m paper_1103_1363_amd.prof_summary TRACE [--top N] [--match REGEX]
        python -m paper_1103_1363_amd.prof_summary --pmc FETCH_CSV WRITE_CSV [--kernel SUBSTR]
+       python -m paper_1103_1363_amd.prof_summary --counters CSV [CSV ...] [--match REGEX]
 
 For every kernel: launches, total and average duration, and the average over
 "working" launches only.  The solvers replay captured graphs of several CG
@@ -132,6 +133,21 @@ def pmc_traffic(fetch_csv, write_csv, kernel=None):
     return cf, cw, rows
 
 
+def counter_table(paths, match=None):
+    """Median per dispatch of every counter in the counter files, per kernel:
+    [(kernel, counter, dispatches, median)]."""
+    rows = []
+    for path in paths:
+        with open(path) as f:
+            counters = sorted({r["Counter_Name"] for r in csv.DictReader(f)})
+        for c in counters:
+            for name, vals in sorted(pmc_counters(path, c).items()):
+                if match and not re.search(match, name):
+                    continue
+                rows.append((name, c, len(vals), statistics.median(vals)))
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("trace", nargs="?")
@@ -139,7 +155,15 @@ def main():
     ap.add_argument("--pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--kernel")
     ap.add_argument("--match", help="regular expression on the short kernel name")
+    ap.add_argument("--counters", nargs="+", metavar="CSV",
+                    help="counter_collection.csv files: median of each counter per dispatch")
     a = ap.parse_args()
+    if a.counters:
+        print(f"# source_digest: {source_digest()}")
+        print(f"{'kernel':40s} {'counter':36s} {'dispatches':>10s} {'per_dispatch':>14s}")
+        for name, c, n, v in counter_table(a.counters, a.match):
+            print(f"{name[:40]:40s} {c:36s} {n:10d} {v:14.6g}")
+        return
     if a.pmc:
         cf, cw, rows = pmc_traffic(a.pmc[0], a.pmc[1], a.kernel)
         print(f"# counter scale (bytes per KiB counted): FETCH {cf:.3f}, WRITE {cw:.3f} "
