@@ -207,10 +207,8 @@ __device__ __forceinline__ void hop_dir16(const Geo& g, const Field<P16>& in,
       y[MU] = (y[MU] == 0) ? g.L[MU] - 1 : y[MU] - 1;
     sy = cb_index(g, y);
   }
-  const unsigned* din = reinterpret_cast<const unsigned*>(in.d);
   unsigned v[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) v[c] = din[spin_idx(sy, c)];
+  load_chunks16(in.d, sy, v);
   const float scale = in.norm[sy] * sign;
   using PJ = Proj<MU, S>;
   hf2 f0[6], f1[6];

@@ -102,13 +102,15 @@ __global__ void pack_kernel(Geo g, Field<P> f_even, Field<P> f_odd, const double
     for (int c = 0; c < 12; ++c) m = fmax(m, fmax(fabs(v[c].x), fabs(v[c].y)));
     f.norm[s] = (float)m;
     double inv = m > 0.0 ? 1.0 / m : 0.0;
+    unsigned u[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       __half2 h;
       h.x = __half((_Float16)(v[c].x * inv));
       h.y = __half((_Float16)(v[c].y * inv));
-      f.d[spin_idx(s, c)] = h;
+      __builtin_memcpy(&u[c], &h, 4);
     }
+    store_chunks16(f.d, s, u);
   } else {
 #pragma unroll
     for (int c = 0; c < 12; ++c)

@@ -38,13 +38,22 @@ struct Error : std::runtime_error {
 // ---------------------------------------------------------------- layout
 // Sites of one parity are numbered by their checkerboard index s = i / 2
 // (i the full-lattice index).  Device fields group sites into blocks of 64;
-// inside a block each complex component occupies 64 consecutive slots, so
-// the 64 lanes of a wavefront read one component of 64 consecutive sites
-// with a single coalesced load.
+// in FP64 and FP32 fields each complex component occupies 64 consecutive
+// slots inside a block, so the 64 lanes of a wavefront read one component of
+// 64 consecutive sites with a single coalesced load (FP16 fields: below).
 constexpr int SB = 64;  // sites per block
 
 __host__ __device__ inline int64_t spin_idx(int64_t s, int c) {  // c in [0, 12)
   return ((s >> 6) * 12 + c) * SB + (s & 63);
+}
+// FP16 spinor fields are chunked instead: inside a block the 12 components of
+// a site (4 bytes each) form three 16-byte chunks (components 4k .. 4k+3),
+// and chunk k of the block's 64 sites is contiguous (1 KB).  A lane reads
+// its site's spinor with three 16-byte loads, and a wavefront's load of one
+// chunk of 64 consecutive sites is one coalesced kilobyte.  Index in 16-byte
+// units, k in [0, 3).
+__host__ __device__ inline int64_t chunk16_idx(int64_t s, int k) {
+  return ((s >> 6) * 3 + k) * SB + (s & 63);
 }
 __host__ __device__ inline int64_t clov_idx(int64_t s, int c) {  // c in [0, 36)
   return ((s >> 6) * 36 + c) * SB + (s & 63);
@@ -197,6 +206,40 @@ __device__ __forceinline__ void st<P16>(__half2* p, int64_t i, C<float> v) {
   p[i] = __floats2half2_rn(v.re, v.im);
 }
 
+typedef unsigned h16x4 __attribute__((ext_vector_type(4)));  // one chunk: 4 FP16 pairs
+
+// FP16 pair (bits) <-> complex
+__device__ __forceinline__ C<float> h2_to_c(unsigned u) {
+  __half2 h;
+  __builtin_memcpy(&h, &u, 4);
+  const float2 f = __half22float2(h);
+  return {f.x, f.y};
+}
+__device__ __forceinline__ unsigned c_to_h2(float re, float im) {
+  const __half2 h = __floats2half2_rn(re, im);
+  unsigned u;
+  __builtin_memcpy(&u, &h, 4);
+  return u;
+}
+
+// The 12 FP16 pairs of site s of a chunked FP16 field (raw bits), and back.
+__device__ __forceinline__ void load_chunks16(const __half2* d, int64_t s, unsigned v[12]) {
+  const h16x4* q = reinterpret_cast<const h16x4*>(d);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const h16x4 w = q[chunk16_idx(s, k)];
+    v[4 * k] = w.x;
+    v[4 * k + 1] = w.y;
+    v[4 * k + 2] = w.z;
+    v[4 * k + 3] = w.w;
+  }
+}
+__device__ __forceinline__ void store_chunks16(__half2* d, int64_t s, const unsigned v[12]) {
+  h16x4* q = reinterpret_cast<h16x4*>(d);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) q[chunk16_idx(s, k)] = h16x4{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
+}
+
 // A device spinor field of one parity (and one right-hand side).
 template <class P>
 struct Field {
@@ -228,12 +271,15 @@ __host__ __device__ inline Field<P> field_at(void* base, int64_t nblk) {
 template <class P>
 __device__ __forceinline__ void load_spinor(const Field<P>& f, int64_t s,
                                             C<typename P::R> v[12]) {
-#pragma unroll
-  for (int c = 0; c < 12; ++c) v[c] = ld<P>(f.d, spin_idx(s, c));
   if constexpr (P::has_norm) {
-    float n = f.norm[s];
+    unsigned u[12];
+    load_chunks16(f.d, s, u);
+    const float n = f.norm[s];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) v[c] = n * v[c];
+    for (int c = 0; c < 12; ++c) v[c] = n * h2_to_c(u[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = ld<P>(f.d, spin_idx(s, c));
   }
 }
 template <class P>
@@ -245,8 +291,10 @@ __device__ __forceinline__ void store_spinor(const Field<P>& f, int64_t s,
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
     f.norm[s] = m;
     const float inv = scale_inv(m);
+    unsigned u[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) st<P>(f.d, spin_idx(s, c), inv * v[c]);
+    for (int c = 0; c < 12; ++c) u[c] = c_to_h2(inv * v[c].re, inv * v[c].im);
+    store_chunks16(f.d, s, u);
   } else {
 #pragma unroll
     for (int c = 0; c < 12; ++c) st<P>(f.d, spin_idx(s, c), v[c]);
@@ -258,12 +306,17 @@ __device__ __forceinline__ void store_spinor(const Field<P>& f, int64_t s,
 template <class P>
 __device__ __forceinline__ typename P::R load_raw(const Field<P>& f, int64_t s,
                                                    C<typename P::R> v[12]) {
+  if constexpr (P::has_norm) {
+    unsigned u[12];
+    load_chunks16(f.d, s, u);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) v[c] = ld<P>(f.d, spin_idx(s, c));
-  if constexpr (P::has_norm)
+    for (int c = 0; c < 12; ++c) v[c] = h2_to_c(u[c]);
     return f.norm[s];
-  else
+  } else {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = ld<P>(f.d, spin_idx(s, c));
     return (typename P::R)1;
+  }
 }
 
 }  // namespace lq

@@ -234,6 +234,27 @@ template <class T>
 __device__ __forceinline__ T& at32(T* base, unsigned i) {
   return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T));
 }
+// The 12 FP16 pairs of site s of an FP16 field (three 16-byte chunks of four
+// pairs, chunk k of a 64-site block contiguous), and back.
+__device__ __forceinline__ void ld_pairs16(const unsigned* d, unsigned s, unsigned v[12]) {
+  const h16x4* q = reinterpret_cast<const h16x4*>(d);
+  const unsigned b = (s >> 6) * 192u + (s & 63u);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const h16x4 w = at32(q, b + 64u * k);
+    v[4 * k] = w.x;
+    v[4 * k + 1] = w.y;
+    v[4 * k + 2] = w.z;
+    v[4 * k + 3] = w.w;
+  }
+}
+__device__ __forceinline__ void st_pairs16(unsigned* d, unsigned s, const unsigned v[12]) {
+  h16x4* q = reinterpret_cast<h16x4*>(d);
+  const unsigned b = (s >> 6) * 192u + (s & 63u);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    at32(q, b + 64u * k) = h16x4{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
+}
 
 // The 12 components of site s as FP16 pairs scaled to a largest component
 // of 1, and that scale (FP16 fields store exactly this; an FP32 field is
@@ -242,9 +263,7 @@ template <class P>
 __device__ __forceinline__ float load_h(const Field<P>& f, unsigned s, unsigned v[12]) {
   const unsigned b = spin_base(s);
   if constexpr (P::has_norm) {
-    const unsigned* d = reinterpret_cast<const unsigned*>(f.d);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) v[c] = at32(d, b + 64u * c);
+    ld_pairs16(reinterpret_cast<const unsigned*>(f.d), s, v);
     return at32(f.norm, s);
   } else {
     C<float> x[12];
@@ -274,9 +293,10 @@ __device__ __forceinline__ void store_h(const Field<P>& f, unsigned s, const C<f
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
     at32(f.norm, s) = m;
     const float inv = scale_inv(m);
-    unsigned* d = reinterpret_cast<unsigned*>(f.d);
+    unsigned u[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) at32(d, b + 64u * c) = pack_h(inv * v[c].re, inv * v[c].im);
+    for (int c = 0; c < 12; ++c) u[c] = pack_h(inv * v[c].re, inv * v[c].im);
+    st_pairs16(reinterpret_cast<unsigned*>(f.d), s, u);
   } else {
 #pragma unroll
     for (int c = 0; c < 12; ++c) at32(f.d, b + 64u * c) = make_float2(v[c].re, v[c].im);
@@ -460,10 +480,7 @@ __device__ __forceinline__ void carry_h(const Geo& g, const Field<P16>& other,
                                         const unsigned* __restrict__ gauge, int p, unsigned s,
                                         unsigned sy, unsigned w[12]) {
   unsigned v[12];
-  const unsigned b = spin_base(sy);
-  const unsigned* d = reinterpret_cast<const unsigned*>(other.d);
-#pragma unroll
-  for (int c = 0; c < 12; ++c) v[c] = at32(d, b + 64u * c);
+  ld_pairs16(reinterpret_cast<const unsigned*>(other.d), sy, v);
   const unsigned ls = BACK ? sy : s;
   const unsigned lb = (unsigned)(((BACK ? 1 - p : p) * 4 + MU) * (int)g.nblk) * 384u +
                       (ls >> 6) * 384u + (ls & 63u);
@@ -514,10 +531,7 @@ __device__ __forceinline__ void stage_term(const Geo& g, const Field<P16>& same,
                                            int slot, int lane) {
   unsigned w[12];
   if constexpr (H == 0) {
-    const unsigned b = spin_base(s);
-    const unsigned* d = reinterpret_cast<const unsigned*>(same.d);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) w[c] = at32(d, b + 64u * c);
+    ld_pairs16(reinterpret_cast<const unsigned*>(same.d), s, w);
   } else {
     carry_h<(H - 1) / 2, ((H - 1) & 1) != 0>(g, other, gauge, p, s, sy[H], w);
   }
