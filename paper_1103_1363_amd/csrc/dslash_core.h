@@ -89,8 +89,15 @@ template <class P>
 __device__ __forceinline__ void load_link(const typename P::S* __restrict__ gauge, int64_t nblk,
                                           int p, int mu, int64_t s, C<typename P::R> u[9]) {
   using R = typename P::R;
+  if constexpr (P::id == LQ_F16) {
+    unsigned w[6];
+    load_link16_raw(gauge, nblk, p, mu, s, w);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) u[c] = ldnt<P>(gauge, link_idx(nblk, p, mu, s, c));
+    for (int c = 0; c < 6; ++c) u[c] = h2_to_c(w[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) u[c] = ldnt<P>(gauge, link_idx(nblk, p, mu, s, c));
+  }
   // row2 = conj(row0 x row1)
   u[6] = conj(u[1] * u[5] - u[2] * u[4]);
   u[7] = conj(u[2] * u[3] - u[0] * u[5]);
@@ -220,11 +227,13 @@ __device__ __forceinline__ void hop_dir16(const Geo& g, const Field<P16>& in,
   // the link: rows 0 and 1 as stored, row 2 = conj(row0 x row1)
   const int lp = BACK ? 1 - p : p;
   const int64_t ls = BACK ? sy : s;
-  const unsigned* gl = reinterpret_cast<const unsigned*>(gauge);
   hf2 u[9];
+  {
+    unsigned w[6];
+    load_link16_raw(gauge, g.nblk, lp, MU, ls, w);
 #pragma unroll
-  for (int c = 0; c < 6; ++c)
-    u[c] = hf2_bits(__builtin_nontemporal_load(gl + link_idx(g.nblk, lp, MU, ls, c)));
+    for (int c = 0; c < 6; ++c) u[c] = hf2_bits(w[c]);
+  }
   {
     // conj(a b - c d): Re = dot2(a, cj(b)) - dot2(c, cj(d)), -Im = dot2(c, sw(d)) - dot2(a, sw(b))
     auto cj = [](hf2 z) { return hf2{z.x, -z.y}; };

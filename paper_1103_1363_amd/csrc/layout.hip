@@ -56,7 +56,7 @@ __global__ void compress_gauge_kernel(Geo g, const double2* __restrict__ host, d
       __half2 h;
       h.x = __half(hr);
       h.y = __half(hi);
-      g16[k] = h;
+      g16[link16_idx(g.nblk, p, mu, s, c)] = h;
     }
   }
   red[threadIdx.x] = err;

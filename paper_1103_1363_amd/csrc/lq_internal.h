@@ -63,6 +63,13 @@ __host__ __device__ inline int64_t clov_idx(int64_t s, int c) {  // c in [0, 36)
 __host__ __device__ inline int64_t link_idx(int64_t nblk, int p, int mu, int64_t s, int c) {
   return ((((int64_t)p * 4 + mu) * nblk + (s >> 6)) * 6 + c) * SB + (s & 63);
 }
+// FP16 links are chunked like FP16 spinors: per (parity, mu, block) the
+// entries 0..3 of the 64 sites as 16-byte chunks (1 KB), then entries 4, 5 as
+// 8-byte chunks (512 B); index of entry c in 4-byte pairs.
+__host__ __device__ inline int64_t link16_idx(int64_t nblk, int p, int mu, int64_t s, int c) {
+  const int64_t base = (((int64_t)p * 4 + mu) * nblk + (s >> 6)) * 384;
+  return c < 4 ? base + (s & 63) * 4 + c : base + 256 + (s & 63) * 2 + (c - 4);
+}
 
 // Reciprocal of an FP16 field's per-site (or per-site, per-RHS) scale m, the
 // largest component magnitude: 0 when m is below the smallest normal FP32
@@ -220,6 +227,24 @@ __device__ __forceinline__ unsigned c_to_h2(float re, float im) {
   unsigned u;
   __builtin_memcpy(&u, &h, 4);
   return u;
+}
+
+// The 6 stored FP16 pairs (rows 0 and 1) of a chunked FP16 link: one 16-byte
+// and one 8-byte streaming load.
+typedef unsigned h16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void load_link16_raw(const __half2* __restrict__ gauge, int64_t nblk,
+                                                int p, int mu, int64_t s, unsigned w[6]) {
+  const unsigned* g = reinterpret_cast<const unsigned*>(gauge);
+  const h16x4 a = __builtin_nontemporal_load(
+      reinterpret_cast<const h16x4*>(g + link16_idx(nblk, p, mu, s, 0)));
+  const h16x2 b = __builtin_nontemporal_load(
+      reinterpret_cast<const h16x2*>(g + link16_idx(nblk, p, mu, s, 4)));
+  w[0] = a.x;
+  w[1] = a.y;
+  w[2] = a.z;
+  w[3] = a.w;
+  w[4] = b.x;
+  w[5] = b.y;
 }
 
 // The 12 FP16 pairs of site s of a chunked FP16 field (raw bits), and back.

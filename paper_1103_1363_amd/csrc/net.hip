@@ -234,6 +234,23 @@ template <class T>
 __device__ __forceinline__ T& at32(T* base, unsigned i) {
   return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(T));
 }
+// Rows 0 and 1 of the FP16 link (parity p, direction mu, site ls) as six pairs:
+// one 16-byte and one 8-byte streaming load (chunked FP16 link layout: per
+// (parity, mu, block) entries 0..3 of the 64 sites, then entries 4, 5).
+__device__ __forceinline__ void ld_link16(const unsigned* __restrict__ gauge, unsigned nblk, int p,
+                                          int mu, unsigned ls, unsigned u[6]) {
+  const unsigned lb = ((unsigned)(p * 4 + mu) * nblk + (ls >> 6)) * 384u;
+  const h16x4 a = __builtin_nontemporal_load(&at32(reinterpret_cast<const h16x4*>(gauge + lb), ls & 63u));
+  const h16x2 b =
+      __builtin_nontemporal_load(&at32(reinterpret_cast<const h16x2*>(gauge + lb + 256u), ls & 63u));
+  u[0] = a.x;
+  u[1] = a.y;
+  u[2] = a.z;
+  u[3] = a.w;
+  u[4] = b.x;
+  u[5] = b.y;
+}
+
 // The 12 FP16 pairs of site s of an FP16 field (three 16-byte chunks of four
 // pairs, chunk k of a 64-site block contiguous), and back.
 __device__ __forceinline__ void ld_pairs16(const unsigned* d, unsigned s, unsigned v[12]) {
@@ -343,13 +360,9 @@ __device__ __forceinline__ float transport_h(const Geo& g, const Field<PI>& othe
   const unsigned sy = (unsigned)cb_index(g, y);
   unsigned v[12];
   const float scale = sign * load_h<PI>(other, sy, v);
-  // link entry c of (parity, MU, site ls): ((parity * 4 + MU) nblk + ls / 64) 384 + 64 c + ls % 64
   const unsigned ls = BACK ? sy : s;
-  const unsigned lb = (unsigned)(((BACK ? 1 - p : p) * 4 + MU) * (int)g.nblk) * 384u +
-                      (ls >> 6) * 384u + (ls & 63u);
   unsigned u[9];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) u[c] = __builtin_nontemporal_load(&at32(gauge, lb + 64u * c));
+  ld_link16(gauge, (unsigned)g.nblk, BACK ? 1 - p : p, MU, ls, u);
   {  // row 2 = conj(row 0 x row 1)
     C<float> r[6];
 #pragma unroll
@@ -482,11 +495,8 @@ __device__ __forceinline__ void carry_h(const Geo& g, const Field<P16>& other,
   unsigned v[12];
   ld_pairs16(reinterpret_cast<const unsigned*>(other.d), sy, v);
   const unsigned ls = BACK ? sy : s;
-  const unsigned lb = (unsigned)(((BACK ? 1 - p : p) * 4 + MU) * (int)g.nblk) * 384u +
-                      (ls >> 6) * 384u + (ls & 63u);
   unsigned u[9];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) u[c] = __builtin_nontemporal_load(&at32(gauge, lb + 64u * c));
+  ld_link16(gauge, (unsigned)g.nblk, BACK ? 1 - p : p, MU, ls, u);
   {
     C<float> r[6];
 #pragma unroll

@@ -475,7 +475,7 @@ __global__ __launch_bounds__(SAP_MAXV) void sap_mr16_kernel(
     for (int mu = 0; mu < 4; ++mu)
       if (fi[mu] >= 0)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) L16[c * lk.nl + fi[mu]] = gl[link_idx(g.nblk, p, mu, s, c)];
+        for (int c = 0; c < 6; ++c) L16[c * lk.nl + fi[mu]] = gl[link16_idx(g.nblk, p, mu, s, c)];
   }
   C<float> rt[12], del[12];
   if (on) load_spinor<P32>(rf, s, rt);
@@ -681,10 +681,10 @@ __global__ __launch_bounds__(SAP_MAXV / 2) void sap_mr16eo_kernel(
     for (int mu = 0; mu < 4; ++mu) {
       if (E.fi[mu] >= 0)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) L16[c * lk.nl + E.fi[mu]] = gl[link_idx(g.nblk, 0, mu, E.s, c)];
+        for (int c = 0; c < 6; ++c) L16[c * lk.nl + E.fi[mu]] = gl[link16_idx(g.nblk, 0, mu, E.s, c)];
       if (O.fi[mu] >= 0)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) L16[c * lk.nl + O.fi[mu]] = gl[link_idx(g.nblk, 1, mu, O.s, c)];
+        for (int c = 0; c < 6; ++c) L16[c * lk.nl + O.fi[mu]] = gl[link16_idx(g.nblk, 1, mu, O.s, c)];
     }
   }
   C<float> ro[12], rho[12], del[12], w[12], acc[12];
