@@ -34,16 +34,17 @@ namespace {
 using cplx = std::complex<double>;
 constexpr int KE = 4;  // entries per thread in the batched kernels
 
-// Which entries of a field belong to sites: a field is one or two halves of
-// per_half entries; in each half only the last 64-site block has padding,
-// entries below lim are all live and in the last block the sites below rem.
+// Which entries of an FP32 field belong to sites: a field is one or two
+// halves of per_half entries; in each half only the last 64-site block has
+// padding, entries below lim are all live and in the last block the sites
+// below rem (the chunked FP32 layout: site_in_block32).
 struct Live {
   int64_t per_half, lim;
   int rem;
 };
 __device__ __forceinline__ bool kr_live(int64_t i, const Live& L) {
   const int64_t k = i < L.per_half ? i : i - L.per_half;
-  return k < L.lim || (int)(k & (SB - 1)) < L.rem;
+  return k < L.lim || site_in_block32(k) < L.rem;
 }
 
 // part[(j G + b) 2 + c]: workgroup b's partial of <V_j, x>
@@ -158,11 +159,14 @@ __global__ void kr_scale_kernel(float2* __restrict__ y, float ar, float ai,
 }
 
 // out = s * in rounded to FP32 (s = 1 / |in| keeps any FP64 magnitude in range)
+// (i counts FP32 entries; the FP64 entry of the same site and component is
+// flat32_to_64(i))
 __global__ void kr_to32_kernel(float2* __restrict__ out, const double2* __restrict__ in, double s,
                                int64_t n, Live L) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !kr_live(i, L)) return;
-  out[i] = make_float2((float)(s * in[i].x), (float)(s * in[i].y));
+  const double2 v = in[flat32_to_64(i)];
+  out[i] = make_float2((float)(s * v.x), (float)(s * v.y));
 }
 
 // y += s * x (FP64 += FP32)
@@ -170,10 +174,11 @@ __global__ void kr_add64_kernel(double2* __restrict__ y, const float2* __restric
                                 int64_t n, Live L) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !kr_live(i, L)) return;
-  double2 v = y[i];
+  const int64_t i64 = flat32_to_64(i);
+  double2 v = y[i64];
   v.x += s * (double)x[i].x;
   v.y += s * (double)x[i].y;
-  y[i] = v;
+  y[i64] = v;
 }
 
 void* kalloc(size_t bytes) {

@@ -112,9 +112,10 @@ __global__ void pack_kernel(Geo g, Field<P> f_even, Field<P> f_odd, const double
     }
     store_chunks16(f.d, s, u);
   } else {
+    C<typename P::R> w[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c)
-      st<P>(f.d, spin_idx(s, c), C<typename P::R>{(typename P::R)v[c].x, (typename P::R)v[c].y});
+    for (int c = 0; c < 12; ++c) w[c] = C<typename P::R>{(typename P::R)v[c].x, (typename P::R)v[c].y};
+    store_spinor<P>(f, s, w);
   }
 }
 

@@ -38,9 +38,10 @@ struct Error : std::runtime_error {
 // ---------------------------------------------------------------- layout
 // Sites of one parity are numbered by their checkerboard index s = i / 2
 // (i the full-lattice index).  Device fields group sites into blocks of 64;
-// in FP64 and FP32 fields each complex component occupies 64 consecutive
-// slots inside a block, so the 64 lanes of a wavefront read one component of
-// 64 consecutive sites with a single coalesced load (FP16 fields: below).
+// in FP64 fields each complex component occupies 64 consecutive slots inside
+// a block, so the 64 lanes of a wavefront read one component of 64
+// consecutive sites with a single coalesced load (FP32 and FP16 fields:
+// 16-byte chunks, below).
 constexpr int SB = 64;  // sites per block
 
 __host__ __device__ inline int64_t spin_idx(int64_t s, int c) {  // c in [0, 12)
@@ -55,6 +56,22 @@ __host__ __device__ inline int64_t spin_idx(int64_t s, int c) {  // c in [0, 12)
 __host__ __device__ inline int64_t chunk16_idx(int64_t s, int k) {
   return ((s >> 6) * 3 + k) * SB + (s & 63);
 }
+// FP32 spinor fields are chunked too: 16-byte chunks of two complex
+// components (2k, 2k + 1), chunk k of the block's 64 sites contiguous.
+// Index in 16-byte units, k in [0, 6).
+__host__ __device__ inline int64_t chunk32_idx(int64_t s, int k) {
+  return ((s >> 6) * 6 + k) * SB + (s & 63);
+}
+// Entrywise kernels that pair an FP32 field with an FP64 one: the FP64
+// (component-major) entry that holds FP32 entry j (both counted in complex
+// entries; a block is 768 entries in either precision), and the site within
+// its block of an FP32 entry.
+__host__ __device__ inline int64_t flat32_to_64(int64_t j) {
+  const int64_t b = j / 768;
+  const int r = (int)(j - b * 768);
+  return b * 768 + ((r >> 7) * 2 + (r & 1)) * SB + ((r & 127) >> 1);
+}
+__host__ __device__ inline int site_in_block32(int64_t j) { return (int)((j & 127) >> 1); }
 __host__ __device__ inline int64_t clov_idx(int64_t s, int c) {  // c in [0, 36)
   return ((s >> 6) * 36 + c) * SB + (s & 63);
 }
@@ -214,6 +231,7 @@ __device__ __forceinline__ void st<P16>(__half2* p, int64_t i, C<float> v) {
 }
 
 typedef unsigned h16x4 __attribute__((ext_vector_type(4)));  // one chunk: 4 FP16 pairs
+typedef float f32x4 __attribute__((ext_vector_type(4)));     // one chunk: 2 FP32 complex
 
 // FP16 pair (bits) <-> complex
 __device__ __forceinline__ C<float> h2_to_c(unsigned u) {
@@ -265,6 +283,23 @@ __device__ __forceinline__ void store_chunks16(__half2* d, int64_t s, const unsi
   for (int k = 0; k < 3; ++k) q[chunk16_idx(s, k)] = h16x4{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
 }
 
+// The 12 components of site s of a chunked FP32 field, and back.
+__device__ __forceinline__ void load_chunks32(const float2* d, int64_t s, C<float> v[12]) {
+  const f32x4* q = reinterpret_cast<const f32x4*>(d);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const f32x4 w = q[chunk32_idx(s, k)];
+    v[2 * k] = {w.x, w.y};
+    v[2 * k + 1] = {w.z, w.w};
+  }
+}
+__device__ __forceinline__ void store_chunks32(float2* d, int64_t s, const C<float> v[12]) {
+  f32x4* q = reinterpret_cast<f32x4*>(d);
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    q[chunk32_idx(s, k)] = f32x4{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+}
+
 // A device spinor field of one parity (and one right-hand side).
 template <class P>
 struct Field {
@@ -302,6 +337,8 @@ __device__ __forceinline__ void load_spinor(const Field<P>& f, int64_t s,
     const float n = f.norm[s];
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[c] = n * h2_to_c(u[c]);
+  } else if constexpr (P::id == LQ_F32) {
+    load_chunks32(f.d, s, v);
   } else {
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[c] = ld<P>(f.d, spin_idx(s, c));
@@ -320,6 +357,8 @@ __device__ __forceinline__ void store_spinor(const Field<P>& f, int64_t s,
 #pragma unroll
     for (int c = 0; c < 12; ++c) u[c] = c_to_h2(inv * v[c].re, inv * v[c].im);
     store_chunks16(f.d, s, u);
+  } else if constexpr (P::id == LQ_F32) {
+    store_chunks32(f.d, s, v);
   } else {
 #pragma unroll
     for (int c = 0; c < 12; ++c) st<P>(f.d, spin_idx(s, c), v[c]);
@@ -337,6 +376,9 @@ __device__ __forceinline__ typename P::R load_raw(const Field<P>& f, int64_t s,
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[c] = h2_to_c(u[c]);
     return f.norm[s];
+  } else if constexpr (P::id == LQ_F32) {
+    load_chunks32(f.d, s, v);
+    return 1.f;
   } else {
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[c] = ld<P>(f.d, spin_idx(s, c));

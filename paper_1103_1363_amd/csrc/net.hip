@@ -25,6 +25,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include <cstdio>
@@ -223,7 +224,8 @@ __device__ __forceinline__ unsigned swap_h(unsigned u) { return (u >> 16) | (u <
 // Indices in the FP16 form are 32-bit: a parity of the lattices the library
 // accepts has at most 2^24 sites, so the largest element index (a link
 // entry) stays below 2^30.
-__device__ __forceinline__ unsigned spin_base(unsigned s) { return (s >> 6) * 768u + (s & 63u); }
+// chunk 0 of site s of an FP32 field in 16-byte units (chunk k at + 64 k)
+__device__ __forceinline__ unsigned spin_base(unsigned s) { return (s >> 6) * 384u + (s & 63u); }
 // element i of an array of T at base, with a 32-bit byte offset (so that the
 // load takes the base from scalar registers and only the offset per lane)
 template <class T>
@@ -284,10 +286,12 @@ __device__ __forceinline__ float load_h(const Field<P>& f, unsigned s, unsigned 
     return at32(f.norm, s);
   } else {
     C<float> x[12];
+    const f32x4* q = reinterpret_cast<const f32x4*>(f.d);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      const float2 q = at32(f.d, b + 64u * c);
-      x[c] = C<float>{q.x, q.y};
+    for (int k = 0; k < 6; ++k) {
+      const f32x4 w = at32(q, b + 64u * k);
+      x[2 * k] = C<float>{w.x, w.y};
+      x[2 * k + 1] = C<float>{w.z, w.w};
     }
     float m = 0.f;
 #pragma unroll
@@ -315,8 +319,10 @@ __device__ __forceinline__ void store_h(const Field<P>& f, unsigned s, const C<f
     for (int c = 0; c < 12; ++c) u[c] = pack_h(inv * v[c].re, inv * v[c].im);
     st_pairs16(reinterpret_cast<unsigned*>(f.d), s, u);
   } else {
+    f32x4* q = reinterpret_cast<f32x4*>(f.d);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) at32(f.d, b + 64u * c) = make_float2(v[c].re, v[c].im);
+    for (int k = 0; k < 6; ++k)
+      at32(q, b + 64u * k) = f32x4{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
   }
 }
 
@@ -811,18 +817,19 @@ void axpby_f32_impl(lq_ctx* ctx, void* out, double a, const void* x, double b, c
 }
 
 // y += c x for complex c, elementwise over the complex entries of two
-// fields of one parity (FP32 y and x, or FP64 y and FP32 x): the component
-// order is the same in every precision.
+// fields of one parity (FP32 y and x, or FP64 y and FP32 x; i counts FP32
+// entries, and an FP64 y takes the entry of the same site and component).
 template <class TY>
 __global__ void net_caxpy_kernel(TY* __restrict__ y, double cr, double ci,
                                  const float2* __restrict__ x, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int64_t iy = std::is_same<TY, double2>::value ? flat32_to_64(i) : i;
   const float2 v = x[i];
-  TY o = y[i];
+  TY o = y[iy];
   o.x += (cr * v.x - ci * v.y);
   o.y += (cr * v.y + ci * v.x);
-  y[i] = o;
+  y[iy] = o;
 }
 
 void copy_bytes(lq_ctx* ctx, void* dst, const void* src, size_t bytes) {

@@ -31,6 +31,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 #include "dslash_core.h"
@@ -790,11 +791,13 @@ __global__ void sap_a32_kernel(const double2* __restrict__ in, float2* __restric
 }
 
 // Entries of a full field that belong to sites (not the padding of the last
-// 64-site block of each parity): entry i of parity half h.
+// 64-site block of each parity): entry i of parity half h, for the
+// component-major FP64 layout (T = double2) or the chunked FP32 one.
+template <class T>
 __device__ __forceinline__ bool live_entry(int64_t i, int64_t per_half, int64_t vh) {
   const int64_t k = i % per_half;
-  const int64_t site = (k / (12 * SB)) * SB + (k % SB);
-  return site < vh;
+  const int64_t in_block = std::is_same<T, double2>::value ? (k % SB) : site_in_block32(k);
+  return (k / (12 * SB)) * SB + in_block < vh;
 }
 
 // partials of <a, b> (re, im) and |b|^2 over the live entries of two full fields
@@ -806,7 +809,7 @@ __global__ __launch_bounds__(256) void sap_dot_kernel(const TA* __restrict__ a,
   double v[3] = {0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    if (!live_entry(i, per_half, vh)) continue;
+    if (!live_entry<TA>(i, per_half, vh)) continue;
     const double ax = a[i].x, ay = a[i].y, bx = b[i].x, by = b[i].y;
     v[0] += ax * bx + ay * by;
     v[1] += ax * by - ay * bx;
@@ -831,7 +834,7 @@ __global__ __launch_bounds__(256) void sap_mdot_kernel(const float2* const* __re
 #pragma unroll
   for (int e = 0; e < GS_E; ++e) {
     idx[e] = ((int64_t)blockIdx.x * GS_E + e) * 256 + threadIdx.x;
-    live[e] = idx[e] < n && live_entry(idx[e], per_half, vh);
+    live[e] = idx[e] < n && live_entry<float2>(idx[e], per_half, vh);
     xv[e] = live[e] ? x[idx[e]] : make_float2(0.f, 0.f);
   }
   for (int j = 0; j < k; ++j) {
@@ -876,7 +879,7 @@ __global__ __launch_bounds__(256) void sap_maxpy_kernel(float2* __restrict__ y,
 #pragma unroll
   for (int e = 0; e < GS_E; ++e) {
     idx[e] = ((int64_t)blockIdx.x * GS_E + e) * 256 + threadIdx.x;
-    live[e] = idx[e] < n && live_entry(idx[e], per_half, vh);
+    live[e] = idx[e] < n && live_entry<float2>(idx[e], per_half, vh);
     yv[e] = live[e] ? y[idx[e]] : make_float2(0.f, 0.f);
   }
   for (int j = 0; j < k; ++j) {
@@ -907,20 +910,26 @@ __global__ void sap_caxpby_kernel(float2* __restrict__ y, float ar, float ai,
 
 // FP64 -> FP32 and FP64 += FP32, entrywise
 // out = s * in, rounded to FP32 (s = 1 / |in| keeps any FP64 magnitude in range)
+// (i counts FP32 entries; the FP64 entry of the same site and component is
+// flat32_to_64(i))
 __global__ void sap_to32_kernel(float2* __restrict__ out, const double2* __restrict__ in,
                                 double s, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = make_float2((float)(s * in[i].x), (float)(s * in[i].y));
+  if (i < n) {
+    const double2 v = in[flat32_to_64(i)];
+    out[i] = make_float2((float)(s * v.x), (float)(s * v.y));
+  }
 }
 // y += s * x
 __global__ void sap_add64_kernel(double2* __restrict__ y, const float2* __restrict__ x,
                                  double s, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    double2 v = y[i];
+    const int64_t i64 = flat32_to_64(i);
+    double2 v = y[i64];
     v.x += s * (double)x[i].x;
     v.y += s * (double)x[i].y;
-    y[i] = v;
+    y[i64] = v;
   }
 }
 
