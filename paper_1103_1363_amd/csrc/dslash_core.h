@@ -94,6 +94,14 @@ __device__ __forceinline__ void load_link(const typename P::S* __restrict__ gaug
     load_link16_raw(gauge, nblk, p, mu, s, w);
 #pragma unroll
     for (int c = 0; c < 6; ++c) u[c] = h2_to_c(w[c]);
+  } else if constexpr (P::id == LQ_F32) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const f32x4 w = __builtin_nontemporal_load(
+          reinterpret_cast<const f32x4*>(gauge + link32_idx(nblk, p, mu, s, 2 * k)));
+      u[2 * k] = {w.x, w.y};
+      u[2 * k + 1] = {w.z, w.w};
+    }
   } else {
 #pragma unroll
     for (int c = 0; c < 6; ++c) u[c] = ldnt<P>(gauge, link_idx(nblk, p, mu, s, c));

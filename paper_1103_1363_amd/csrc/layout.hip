@@ -51,7 +51,7 @@ __global__ void compress_gauge_kernel(Geo g, const double2* __restrict__ host, d
       C<double> v = u[c / 3][c % 3];
       int64_t k = link_idx(g.nblk, p, mu, s, c);
       g64[k] = make_double2(v.re, v.im);
-      g32[k] = make_float2((float)v.re, (float)v.im);
+      g32[link32_idx(g.nblk, p, mu, s, c)] = make_float2((float)v.re, (float)v.im);
       _Float16 hr = (_Float16)v.re, hi = (_Float16)v.im;
       __half2 h;
       h.x = __half(hr);

@@ -80,6 +80,12 @@ __host__ __device__ inline int64_t clov_idx(int64_t s, int c) {  // c in [0, 36)
 __host__ __device__ inline int64_t link_idx(int64_t nblk, int p, int mu, int64_t s, int c) {
   return ((((int64_t)p * 4 + mu) * nblk + (s >> 6)) * 6 + c) * SB + (s & 63);
 }
+// FP32 links: per (parity, mu, block) three 16-byte chunks of two entries
+// (entries 2k, 2k + 1), chunk k of the 64 sites contiguous; index of entry c
+// in complex (8-byte) units.
+__host__ __device__ inline int64_t link32_idx(int64_t nblk, int p, int mu, int64_t s, int c) {
+  return (((int64_t)p * 4 + mu) * nblk + (s >> 6)) * 384 + (c >> 1) * 128 + (s & 63) * 2 + (c & 1);
+}
 // FP16 links are chunked like FP16 spinors: per (parity, mu, block) the
 // entries 0..3 of the 64 sites as 16-byte chunks (1 KB), then entries 4, 5 as
 // 8-byte chunks (512 B); index of entry c in 4-byte pairs.

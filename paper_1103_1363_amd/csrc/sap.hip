@@ -241,7 +241,7 @@ __global__ __launch_bounds__(SAP_MAXV) void sap_mr_kernel(Geo g, SapBlocks sb, i
       if (on && l[mu] + 1 < sb.B[mu])
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-          const C<float> e = ldnt<P32>(gauge, link_idx(g.nblk, p, mu, s, c));
+          const C<float> e = ldnt<P32>(gauge, link32_idx(g.nblk, p, mu, s, c));
           links[(mu * 6 + c) * sb.vb + t] = make_float2(e.re, e.im);
         }
   }
