@@ -159,22 +159,22 @@ __device__ inline void store_block<double2>(double2* dst, int64_t s, int b, cons
 template <>
 __device__ inline void store_block<float2>(float2* dst, int64_t s, int b, const Cd m[36]) {
   for (int k = 0; k < 3; ++k)
-    dst[clov_idx(s, 18 * b + k)] = make_float2((float)m[7 * (2 * k)].re, (float)m[7 * (2 * k + 1)].re);
+    dst[clov32_idx(s, 18 * b + k)] = make_float2((float)m[7 * (2 * k)].re, (float)m[7 * (2 * k + 1)].re);
   for (int r = 0; r < 6; ++r)
     for (int c = r + 1; c < 6; ++c) {
       const Cd v = m[6 * r + c];
-      dst[clov_idx(s, 18 * b + 3 + tri_idx(r, c))] = make_float2((float)v.re, (float)v.im);
+      dst[clov32_idx(s, 18 * b + 3 + tri_idx(r, c))] = make_float2((float)v.re, (float)v.im);
     }
 }
 template <>
 __device__ inline void store_block<__half2>(__half2* dst, int64_t s, int b, const Cd m[36]) {
   for (int k = 0; k < 3; ++k)
-    dst[clov_idx(s, 18 * b + k)] =
+    dst[clov16_idx(s, 18 * b + k)] =
         __floats2half2_rn((float)m[7 * (2 * k)].re, (float)m[7 * (2 * k + 1)].re);
   for (int r = 0; r < 6; ++r)
     for (int c = r + 1; c < 6; ++c) {
       const Cd v = m[6 * r + c];
-      dst[clov_idx(s, 18 * b + 3 + tri_idx(r, c))] = __floats2half2_rn((float)v.re, (float)v.im);
+      dst[clov16_idx(s, 18 * b + 3 + tri_idx(r, c))] = __floats2half2_rn((float)v.re, (float)v.im);
     }
 }
 

@@ -365,8 +365,33 @@ __device__ __forceinline__ void clover_mul(const typename P::S* __restrict__ cl,
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     C<R> m[18];
+    if constexpr (P::id == LQ_F32) {
+      const f32x4* q = reinterpret_cast<const f32x4*>(cl);
 #pragma unroll
-    for (int k = 0; k < 18; ++k) m[k] = ldnt<P>(cl, clov_idx(s, 18 * b + k));
+      for (int j = 0; j < 9; ++j) {
+        const f32x4 w = __builtin_nontemporal_load(q + ((s >> 6) * 18 + 9 * b + j) * SB + (s & 63));
+        m[2 * j] = {w.x, w.y};
+        m[2 * j + 1] = {w.z, w.w};
+      }
+    } else if constexpr (P::id == LQ_F16) {
+      const unsigned* u = reinterpret_cast<const unsigned*>(cl);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const h16x4 w = __builtin_nontemporal_load(
+            reinterpret_cast<const h16x4*>(u + clov16_idx(s, 18 * b + 4 * j)));
+        m[4 * j] = h2_to_c(w.x);
+        m[4 * j + 1] = h2_to_c(w.y);
+        m[4 * j + 2] = h2_to_c(w.z);
+        m[4 * j + 3] = h2_to_c(w.w);
+      }
+      const h16x2 t = __builtin_nontemporal_load(
+          reinterpret_cast<const h16x2*>(u + clov16_idx(s, 18 * b + 16)));
+      m[16] = h2_to_c(t.x);
+      m[17] = h2_to_c(t.y);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 18; ++k) m[k] = ldnt<P>(cl, clov_idx(s, 18 * b + k));
+    }
     const C<R>* xb = x + 6 * b;
 #pragma unroll
     for (int r = 0; r < 6; ++r) {

@@ -75,6 +75,20 @@ __host__ __device__ inline int site_in_block32(int64_t j) { return (int)((j & 12
 __host__ __device__ inline int64_t clov_idx(int64_t s, int c) {  // c in [0, 36)
   return ((s >> 6) * 36 + c) * SB + (s & 63);
 }
+// Clover tables in FP32 and FP16 are chunked for 16-byte loads too.  FP32:
+// chunks of two entries (2j, 2j + 1), chunk j of the block's 64 sites
+// contiguous, index in complex units.  FP16: per chirality block b (entries
+// 18 b .. 18 b + 17) the entries 0..15 as four 16-byte chunks and 16, 17 as
+// one 8-byte chunk, index in 4-byte pairs.  e in [0, 36).
+__host__ __device__ inline int64_t clov32_idx(int64_t s, int e) {
+  return ((s >> 6) * 18 + (e >> 1)) * (2 * SB) + (s & 63) * 2 + (e & 1);
+}
+__host__ __device__ inline int64_t clov16_idx(int64_t s, int e) {
+  const int b = e >= 18 ? 1 : 0, k = e - 18 * b;
+  const int64_t base = (s >> 6) * (36 * SB) + b * (18 * SB);
+  return k < 16 ? base + (k >> 2) * (4 * SB) + (s & 63) * 4 + (k & 3)
+                : base + 16 * SB + (s & 63) * 2 + (k - 16);
+}
 // compressed links: parity p, direction mu, site s, complex entry c in [0, 6)
 // (row 0 then row 1)
 __host__ __device__ inline int64_t link_idx(int64_t nblk, int p, int mu, int64_t s, int c) {

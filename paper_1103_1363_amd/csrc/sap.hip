@@ -674,8 +674,8 @@ __global__ __launch_bounds__(SAP_MAXV / 2) void sap_mr16eo_kernel(
     const unsigned* ao = reinterpret_cast<const unsigned*>(aooinv16);
 #pragma unroll
     for (int k = 0; k < 36; ++k) {
-      A16[k * sb.vb + E.t] = ae[clov_idx(E.s, k)];
-      A16[k * sb.vb + O.t] = ao[clov_idx(O.s, k)];
+      A16[k * sb.vb + E.t] = ae[clov16_idx(E.s, k)];
+      A16[k * sb.vb + O.t] = ao[clov16_idx(O.s, k)];
     }
     const unsigned* gl = reinterpret_cast<const unsigned*>(gauge16);
 #pragma unroll
@@ -785,9 +785,17 @@ __global__ void sap_a16_kernel(const double2* __restrict__ in, __half2* __restri
 }
 
 // FP64 clover blocks -> FP32
+// (out in the chunked FP32 table layout: entry i of out holds site
+// (i / 2304) 64 + (i % 128) / 2, entry 2 ((i % 2304) / 128) + i % 2)
 __global__ void sap_a32_kernel(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
+  if (i < n) {
+    const int64_t blk = i / (36 * SB);
+    const int r = (int)(i - blk * (36 * SB));
+    const int e = 2 * (r >> 7) + (r & 1), site = (r & 127) >> 1;
+    const double2 v = in[(blk * 36 + e) * SB + site];
+    out[i] = make_float2((float)v.x, (float)v.y);
+  }
 }
 
 // Entries of a full field that belong to sites (not the padding of the last
