@@ -785,15 +785,11 @@ __global__ void sap_a16_kernel(const double2* __restrict__ in, __half2* __restri
 }
 
 // FP64 clover blocks -> FP32
-// (out in the chunked FP32 table layout: entry i of out holds site
-// (i / 2304) 64 + (i % 128) / 2, entry 2 ((i % 2304) / 128) + i % 2)
+// (out in the chunked FP32 table layout)
 __global__ void sap_a32_kernel(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    const int64_t blk = i / (36 * SB);
-    const int r = (int)(i - blk * (36 * SB));
-    const int e = 2 * (r >> 7) + (r & 1), site = (r & 127) >> 1;
-    const double2 v = in[(blk * 36 + e) * SB + site];
+    const double2 v = in[clov32_to_64(i)];
     out[i] = make_float2((float)v.x, (float)v.y);
   }
 }

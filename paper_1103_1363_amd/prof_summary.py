@@ -66,7 +66,7 @@ def summary(path, top=20, match=None):
 # their device code, the precision traits and loads they use, and the
 # reduction helpers; with the compile flags, they fix the kernels' code.
 KERNEL_SOURCES = ("solver_kernels.h", "dslash_core.h", "reduce.h", "lq_internal.h",
-                  "site_index.h")
+                  "site_index.h", "field_index.h")
 
 
 def source_digest():
