@@ -225,7 +225,7 @@ __device__ __forceinline__ unsigned swap_h(unsigned u) { return (u >> 16) | (u <
 // accepts has at most 2^24 sites, so the largest element index (a link
 // entry) stays below 2^30.
 // chunk 0 of site s of an FP32 field in 16-byte units (chunk k at + 64 k)
-__device__ __forceinline__ unsigned spin_base(unsigned s) { return (s >> 6) * 384u + (s & 63u); }
+__device__ __forceinline__ unsigned chunk32_base(unsigned s) { return (s >> 6) * 384u + (s & 63u); }
 // element i of an array of T at base, with a 32-bit byte offset (so that the
 // load takes the base from scalar registers and only the offset per lane)
 template <class T>
@@ -280,7 +280,7 @@ __device__ __forceinline__ void st_pairs16(unsigned* d, unsigned s, const unsign
 // rounded the same way).
 template <class P>
 __device__ __forceinline__ float load_h(const Field<P>& f, unsigned s, unsigned v[12]) {
-  const unsigned b = spin_base(s);
+  const unsigned b = chunk32_base(s);
   if constexpr (P::has_norm) {
     ld_pairs16(reinterpret_cast<const unsigned*>(f.d), s, v);
     return at32(f.norm, s);
@@ -307,7 +307,7 @@ __device__ __forceinline__ float load_h(const Field<P>& f, unsigned s, unsigned 
 // 1, with the scale), as store_spinor with 32-bit indices.
 template <class P>
 __device__ __forceinline__ void store_h(const Field<P>& f, unsigned s, const C<float> v[12]) {
-  const unsigned b = spin_base(s);
+  const unsigned b = chunk32_base(s);
   if constexpr (P::has_norm) {
     float m = 0.f;
 #pragma unroll
