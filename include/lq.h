@@ -37,8 +37,9 @@
  *
  * Device fields are opaque byte buffers of lq_field_bytes() bytes, owned
  * by the caller (any device allocation, 256-byte aligned).  Their inner
- * layout is private to the library (site-blocked, 64 sites per block,
- * component-major inside a block; FP16 fields carry one FP32 scale per site).
+ * layout is private to the library (site-blocked, 64 sites per block;
+ * FP64 component-major inside a block, FP32 and FP16 in 16-byte chunks of
+ * components; FP16 fields carry one FP32 scale per site).
  *
  * Every call returns an lq_status; no C++ exception crosses this boundary.
  * On failure a message is kept in the context (lq_last_error).  All device
